@@ -1,0 +1,419 @@
+"""Pins of the FP64 oracle against facts fixed outside it (no GPU needed).
+
+Each test names the part of the method it pins (arXiv:2304.01841, Sec. 2
+steps 1-3, Sec. 4.1 for the random numbers) and what fixes the expected value:
+a closed form, an invariant, a special case, brute force, an independent
+high-precision quadrature, or an independent generator implementation.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2304_01841_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _plane(nw=40, nt=300, **kw):
+    return W.plane(nw, nt, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10 (Sec. 4.1: random123 / Salmon et al. SC'11)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND reference")
+    exe = str(tmp_path_factory.mktemp("rr") / "rocrand_philox_ref")
+    subprocess.check_call([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1",
+                           os.path.join(HERE, "rocrand_philox_ref.cpp"), "-o", exe])
+    return exe
+
+
+def test_philox_matches_rocrand_engine(rocrand_ref):
+    """P5: the oracle's Philox4x32-10 equals rocRAND's independent engine over a
+    sweep of counters and keys (including all-zero and all-one words)."""
+    rng = np.random.default_rng(7)
+    n = 3000
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0; key[0] = 0
+    ctr[1] = 0xFFFFFFFF; key[1] = 0xFFFFFFFF
+    ctr[2] = [0, 1, 2, 3]; key[2] = [5, 6]
+    lines = "\n".join("%x %x %x %x %x %x" % (*c, *k) for c, k in zip(ctr.tolist(), key.tolist()))
+    out = subprocess.run([rocrand_ref], input=lines + "\n", capture_output=True, text=True,
+                         check=True).stdout.split()
+    ref = np.array([int(v, 16) for v in out], dtype=np.uint64).astype(np.uint32).reshape(n, 4)
+    got = O.philox4x32_10(ctr, key)
+    assert np.array_equal(got, ref)
+
+
+def test_normals_are_standard():
+    """P6: the Box-Muller deviates keyed by (event, depo, bin) are standard
+    normal: mean 0, variance 1, skew 0, kurtosis 3, KS distance small, and the
+    cosine/sine partners of one word pair are uncorrelated."""
+    from scipy import stats
+
+    zs = np.array([O.normal(I, J, 3, e, W.PHILOX_SEED, 1)
+                   for e in range(40) for I in range(-5, 20) for J in range(-8, 40)])
+    n = zs.size
+    assert abs(zs.mean()) < 4.5 / math.sqrt(n)
+    assert abs(zs.var() - 1.0) < 4.5 * math.sqrt(2.0 / n)
+    assert abs(stats.skew(zs)) < 4.5 * math.sqrt(6.0 / n)
+    assert abs(stats.kurtosis(zs)) < 4.5 * math.sqrt(24.0 / n)
+    assert stats.kstest(zs, "norm").pvalue > 1e-3
+    even = np.array([O.normal(7, 4 * k, 1, e, 11, 0) for e in range(200) for k in range(20)])
+    odd = np.array([O.normal(7, 4 * k + 1, 1, e, 11, 0) for e in range(200) for k in range(20)])
+    assert abs(np.corrcoef(even, odd)[0, 1]) < 4.5 / math.sqrt(even.size)
+
+
+def test_normal_depends_on_every_key_field():
+    base = O.normal(3, 9, 4, 5, 77, 2)
+    assert O.normal(4, 9, 4, 5, 77, 2) != base
+    assert O.normal(3, 13, 4, 5, 77, 2) != base
+    assert O.normal(3, 9, 5, 5, 77, 2) != base
+    assert O.normal(3, 9, 4, 6, 77, 2) != base
+    assert O.normal(3, 9, 4, 5, 78, 2) != base
+    assert O.normal(3, 9, 4, 5, 77, 3) != base
+    # ticks 4k..4k+3 share one Philox call but use different words / branches
+    zs = [O.normal(3, 8 + m, 4, 5, 77, 2) for m in range(4)]
+    assert len(set(zs)) == 4
+
+
+# ---------------------------------------------------------------------------
+# Drift, window and weights (Sec. 2 step 1)
+# ---------------------------------------------------------------------------
+def test_drift_widths_closed_form():
+    """Diffusion widths sqrt(2 D T) (longitudinal one over the drift speed) at
+    a drift of 2.5 ms: 2.098 mm transverse -> 4.195 pitch bins of 0.5 mm,
+    0.8839 us longitudinal -> 1.768 ticks of 0.5 us."""
+    phys = W.physics(False)
+    pl = _plane()
+    x = 1.6 * 2500.0
+    st, (mu_p, s_p, mu_t, s_t), _ = O.depo_window([x, 0.0, 100.0, -2500.0 + 50.0, 1.0], phys, pl)
+    assert st == O.STATUS_OK
+    assert s_p == pytest.approx(math.sqrt(2 * 8.8e-4 * 2500.0) / 0.5, rel=1e-14)
+    assert s_t == pytest.approx(math.sqrt(2 * 4e-4 * 2500.0) / 1.6 / 0.5, rel=1e-14)
+    assert mu_p == pytest.approx(200.0, rel=1e-15)
+    assert mu_t == pytest.approx(100.0, rel=1e-13)
+
+
+def test_window_bounds_match_exact_arithmetic():
+    """Window = floor(mu -/+ 3 s), checked against 50-digit arithmetic on random
+    depos (skipping the measure-zero cases where FP64 rounding straddles an
+    integer)."""
+    import mpmath as mp
+
+    mp.mp.dps = 50
+    phys = W.physics(False)
+    pl = _plane(nw=200, nt=6000)
+    rng = np.random.default_rng(3)
+    checked = 0
+    for _ in range(400):
+        x = rng.uniform(0, 4000.0)
+        z = rng.uniform(0, 1000.0)
+        t = rng.uniform(-2500.0, 500.0)
+        st, (mu_p, s_p, mu_t, s_t), (lo_p, lo_t, n_p, n_t) = O.depo_window(
+            [x, 0.0, z, t, 10.0], phys, pl)
+        if st != O.STATUS_OK:
+            continue
+        T = mp.mpf(x) / mp.mpf(1.6)
+        mp_mu_p = mp.mpf(z) / mp.mpf(0.5)
+        mp_s_p = mp.sqrt(2 * mp.mpf(8.8e-4) * T) / mp.mpf(0.5)
+        mp_mu_t = (mp.mpf(t) + T) / mp.mpf(0.5)
+        mp_s_t = mp.sqrt(2 * mp.mpf(4e-4) * T) / mp.mpf(1.6) / mp.mpf(0.5)
+        for lo, n, mu, s in ((lo_p, n_p, mp_mu_p, mp_s_p), (lo_t, n_t, mp_mu_t, mp_s_t)):
+            a, b = mu - 3 * s, mu + 3 * s
+            if min(abs(a - mp.nint(a)), abs(b - mp.nint(b))) < 1e-9:
+                continue
+            assert lo == int(mp.floor(a))
+            assert lo + n - 1 == int(mp.floor(b))
+            checked += 1
+    assert checked > 300
+
+
+@pytest.mark.parametrize("mu,s", [(10.3, 1.0), (50.77, 2.5), (20.0, 4.195), (33.5, 1.768),
+                                  (7.9, 0.3)])
+def test_weights_equal_quadrature(mu, s):
+    """P3: each weight is the Gaussian pdf integrated over its bin by numerical
+    quadrature, normalised over the window (agreement <= 1e-13)."""
+    import mpmath as mp
+
+    mp.mp.dps = 30
+    lo = math.floor(mu - 3 * s)
+    n = math.floor(mu + 3 * s) - lo + 1
+    Wo = O.axis_weights(lo, n, mu, s)
+    pdf = lambda u: mp.exp(-(u - mu) ** 2 / (2 * s * s)) / (s * mp.sqrt(2 * mp.pi))
+    ref = np.array([float(mp.quad(pdf, [lo + i, lo + i + 1])) for i in range(n)])
+    ref /= ref.sum()
+    assert np.max(np.abs(Wo - ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("s", [1.0, 1.7, 2.5, 4.2])
+def test_weight_moments_sheppard(s):
+    """P2: with a +-10 sigma window, the binned Gaussian has mean mu and
+    variance s^2 + 1/12 (Sheppard's correction); the residual is of order
+    exp(-2 pi^2 s^2) < 3e-9 for s >= 1."""
+    for mu in (10.0, 10.37, 25.5, 99.91):
+        lo = math.floor(mu - 10 * s)
+        n = math.floor(mu + 10 * s) - lo + 1
+        Wo = O.axis_weights(lo, n, mu, s)
+        c = lo + np.arange(n) + 0.5
+        mean = float(np.sum(Wo * c))
+        var = float(np.sum(Wo * (c - mean) ** 2))
+        bound = 10 * s * math.exp(-2 * math.pi ** 2 * s * s) + 1e-12
+        assert abs(mean - mu) < bound
+        assert abs(var - (s * s + 1.0 / 12.0)) < 10 * bound
+
+
+def test_zero_drift_is_single_bin():
+    """P4: a depo on the response plane (no drift) has zero width: a 1 x 1
+    patch holding all its charge in the bin that contains it."""
+    phys = W.physics(False)
+    pl = _plane()
+    dep = np.array([[0.0, 0.0, 12.3, 7.6, 1234.5]])
+    meta, vals, st = O.rasterize(dep, phys, pl)
+    assert st[0] == 0
+    assert meta[0, 2] == 1 and meta[0, 3] == 1
+    assert meta[0, 0] == math.floor(12.3 / 0.5) and meta[0, 1] == math.floor(7.6 / 0.5)
+    assert vals[0] == 1234.5
+    # with fluctuation on, a single bin has p = 1: no variance, charge kept
+    meta, vals, st = O.rasterize(dep, W.physics(True), pl)
+    assert vals[0] == 1234.5
+
+
+def test_invalid_and_empty_depos():
+    phys = W.physics(False)
+    pl = _plane(nw=10, nt=100)
+    dep = np.array([[-1.0, 0, 10, 0, 5.0],          # behind the plane
+                    [10.0, 0, 10, 0, -5.0],         # negative charge
+                    [np.nan, 0, 10, 0, 5.0],        # not finite
+                    [10.0, 0, 1e6, 0, 5.0],         # window misses the grid
+                    [10.0, 0, 10, 0, 5.0]])         # fine
+    meta, vals, st = O.rasterize(dep, phys, pl)
+    assert st.tolist() == [1, 1, 1, 2, 0]
+    assert (meta[:4, 2] == 0).all() and meta[4, 2] > 0
+
+
+# ---------------------------------------------------------------------------
+# Patches and Scatter-Add (Sec. 2 steps 1-2)
+# ---------------------------------------------------------------------------
+def test_charge_conserved_without_fluctuation():
+    """P1: every patch integrates to its depo's charge, so the grid total equals
+    the total charge when all windows lie inside the grid (~1e-12 relative)."""
+    rng = np.random.default_rng(11)
+    pl = _plane(nw=60, nt=2000)
+    dep = W.uniform_depos(rng, 2000, (20.0, 280.0), (30.0, 900.0))
+    meta, vals, st = O.rasterize(dep, W.physics(False), pl)
+    assert (st == 0).all()
+    Np, Nt = O.grid_shape(pl)
+    assert meta[:, 0].min() >= 0 and (meta[:, 0] + meta[:, 2]).max() <= Np
+    assert meta[:, 1].min() >= 0 and (meta[:, 1] + meta[:, 3]).max() <= Nt
+    for d in range(0, 2000, 97):
+        o, n = meta[d, 4], meta[d, 2] * meta[d, 3]
+        assert vals[o:o + n].sum() == pytest.approx(dep[d, 4], rel=1e-13)
+    G = O.scatter(meta, vals, pl)
+    assert G.sum() == pytest.approx(dep[:, 4].sum(), rel=1e-12)
+
+
+def test_patch_is_outer_product_without_fluctuation():
+    rng = np.random.default_rng(12)
+    pl = _plane()
+    dep = W.uniform_depos(rng, 20, (20.0, 180.0), (20.0, 120.0))
+    meta, vals, st = O.rasterize(dep, W.physics(False), pl)
+    for d in range(20):
+        lo_p, lo_t, n_p, n_t, off = meta[d]
+        P = vals[off:off + n_p * n_t].reshape(n_p, n_t)
+        # rank one: every 2x2 minor vanishes
+        assert np.linalg.matrix_rank(P, tol=1e-9 * P.max()) == 1
+        # row / column sums give the axis weight profiles times q
+        st, (mu_p, s_p, mu_t, s_t), _ = O.depo_window(dep[d], W.physics(False), pl)
+        assert np.allclose(P.sum(1) / dep[d, 4], O.axis_weights(lo_p, n_p, mu_p, s_p), rtol=1e-12)
+        assert np.allclose(P.sum(0) / dep[d, 4], O.axis_weights(lo_t, n_t, mu_t, s_t), rtol=1e-12)
+
+
+def test_fluctuation_statistics():
+    """P6: with fluctuation, each patch still sums exactly to q; across many
+    events a bin's mean tends to q p and its variance to about q p (1 - p)
+    (the renormalisation to q only slightly anticorrelates the bins)."""
+    phys = W.physics(True)
+    pl = _plane()
+    dep = np.array([[1.6 * 1500.0, 0.0, 100.1, -1500.0 + 60.2, 2000.0]])
+    vals_e = []
+    for e in range(3000):
+        meta, vals, st = O.rasterize(dep, phys, pl, event_id=e)
+        assert vals.sum() == pytest.approx(2000.0, rel=1e-12)
+        assert (vals >= 0).all()
+        vals_e.append(vals)
+    V = np.array(vals_e)
+    meta, mean_vals, _ = O.rasterize(dep, W.physics(False), pl)
+    p = mean_vals / 2000.0
+    big = p > 0.02
+    n = V.shape[0]
+    m = V.mean(0)
+    sd = np.sqrt(2000.0 * p * (1 - p))
+    assert np.all(np.abs(m[big] - mean_vals[big]) < 4.5 * sd[big] / math.sqrt(n) + 0.05 * sd[big])
+    ratio = V.var(0)[big] / (2000.0 * p[big] * (1 - p[big]))
+    assert np.all((ratio > 0.8) & (ratio < 1.1))
+
+
+def test_scatter_drops_out_of_grid_bins():
+    """Charge of bins outside the grid is lost (not renormalised)."""
+    phys = W.physics(False)
+    pl = _plane(nw=10, nt=100)  # 100 pitch bins
+    dep = np.array([[1.6 * 2000.0, 0.0, 0.2, -2000.0 + 20.0, 1000.0]])  # straddles pitch 0
+    meta, vals, st = O.rasterize(dep, phys, pl)
+    assert meta[0, 0] < 0
+    G = O.scatter(meta, vals, pl)
+    lo_p, lo_t, n_p, n_t, off = meta[0]
+    P = vals.reshape(n_p, n_t)
+    inside = P[-lo_p:, :].sum()
+    assert G.sum() == pytest.approx(inside, rel=1e-13)
+    assert G.sum() < 1000.0
+
+
+def test_linearity_and_integer_shift():
+    """P10: without fluctuation the grid is linear in the depo set, and shifting
+    every depo by whole bins (exactly representable) shifts the grid."""
+    rng = np.random.default_rng(13)
+    pl = _plane(nw=30, nt=600)
+    phys = W.physics(False)
+    A = W.uniform_depos(rng, 50, (30.0, 100.0), (30.0, 150.0))
+    B = W.uniform_depos(rng, 50, (30.0, 100.0), (30.0, 150.0))
+    A[:, 2] = np.round(A[:, 2] * 1024) / 1024
+    A[:, 3] = np.round(A[:, 3] * 1024) / 1024
+    A[:, 0] = np.round(A[:, 0] / 1.6) * 1.6   # whole-us drift
+    GA = O.grid(A, phys, pl)
+    GB = O.grid(B, phys, pl)
+    GAB = O.grid(np.concatenate([A, B]), phys, pl)
+    assert np.allclose(GAB, GA + GB, rtol=0, atol=1e-12 * GAB.max())
+    S = A.copy()
+    S[:, 2] += 7 * 0.5      # 7 pitch bins
+    S[:, 3] += 11 * 0.5     # 11 ticks
+    GS = O.grid(S, phys, pl)
+    assert np.array_equal(GS[7:, 11:], GA[:-7, :-11])
+
+
+def test_problem_scale_matches_paper():
+    """The synthetic collection workload has the problem scale the paper states
+    (golden fixture: patch O(20x20), grid O(10^4 x 10^4), response O(100x100))."""
+    fx = {}
+    with open(os.path.join(HERE, "golden", "paper_problem_scale.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                fx[k] = float(v)
+    rng = np.random.default_rng(5)
+    dep = W.track_depos(rng, 4, 500)
+    pl = W.plane(960, 6000)
+    meta, _, _ = O.rasterize(dep, W.physics(False), pl)
+    order = lambda v, ref: 0.1 * ref <= v <= 10 * ref
+    assert order(meta[:, 2].mean() * meta[:, 3].mean(), fx["patch_extent_order"] ** 2)
+    assert order(O.grid_shape(pl)[0] * O.grid_shape(pl)[1], fx["grid_extent_order"] ** 2)
+    R = W.response("unipolar")
+    assert order(R.size, fx["response_extent_order"] ** 2)
+
+
+# ---------------------------------------------------------------------------
+# Convolution (Sec. 2 step 3)
+# ---------------------------------------------------------------------------
+def _brute_conv(G, R, r0):
+    """Independent brute force: shift-and-add of every response tap."""
+    Np, Nt = G.shape
+    Rp, Rt = R.shape
+    O_ = np.zeros_like(G)
+    for r in range(Rp):
+        for s in range(Rt):
+            # O[p][t] += R[r][s] G[p + r0 - r][t - s]
+            dp = r0 - r
+            p_lo, p_hi = max(0, -dp), min(Np, Np - dp)
+            if p_lo >= p_hi or s >= Nt:
+                continue
+            O_[p_lo:p_hi, s:] += R[r, s] * G[p_lo + dp:p_hi + dp, :Nt - s]
+    return O_
+
+
+@pytest.mark.parametrize("Np,Nt,Rp,Rt,r0", [(7, 9, 3, 4, 1), (16, 16, 5, 5, 2), (13, 20, 6, 7, 0),
+                                            (10, 11, 4, 3, 3), (24, 31, 9, 8, 4)])
+def test_convolution_fft_equals_direct_and_brute(Np, Nt, Rp, Rt, r0):
+    """P7: the FFT convolution equals the defining double sum and an
+    independent brute-force shift-and-add, for non-separable non-symmetric
+    responses and several origins (FP64, <= 1e-12)."""
+    rng = np.random.default_rng(Np * 100 + Nt)
+    G = rng.standard_normal((Np, Nt))
+    R = rng.standard_normal((Rp, Rt))
+    ref = _brute_conv(G, R, r0)
+    direct = O.convolve_direct(G, R, r0)
+    fft = O.convolve(G, R, r0)
+    scale = np.abs(ref).max()
+    assert np.abs(direct - ref).max() <= 1e-12 * scale
+    assert np.abs(fft - ref).max() <= 1e-12 * scale
+    # and against scipy's spatial-domain convolution, cropped
+    from scipy.signal import convolve2d
+    full = convolve2d(G, R, mode="full")
+    assert np.abs(full[r0:r0 + Np, :Nt] - ref).max() <= 1e-12 * scale
+
+
+def test_convolution_delta_response_is_identity():
+    """P8: a unit response at (r0, 0) returns the grid unchanged."""
+    rng = np.random.default_rng(21)
+    G = rng.standard_normal((30, 40))
+    R = np.zeros((9, 7))
+    R[4, 0] = 1.0
+    assert np.array_equal(O.convolve_direct(G, R, 4), G)
+    assert np.abs(O.convolve(G, R, 4) - G).max() <= 1e-13
+
+
+def test_convolution_sum_invariant():
+    """P9: for a grid whose charge sits away from the edges, the cropped output
+    holds the whole linear convolution, so its sum is sum(G) sum(R)."""
+    rng = np.random.default_rng(22)
+    Np, Nt, Rp, Rt, r0 = 60, 80, 9, 11, 4
+    G = np.zeros((Np, Nt))
+    G[10:50, 0:60] = rng.uniform(0, 1, (40, 60))
+    R = rng.standard_normal((Rp, Rt))
+    out = O.convolve(G, R, r0)
+    assert out.sum() == pytest.approx(G.sum() * R.sum(), rel=1e-12)
+
+
+def test_convolution_points_match_full():
+    rng = np.random.default_rng(23)
+    G = rng.standard_normal((50, 70))
+    R = rng.standard_normal((11, 13))
+    full = O.convolve(G, R, 5)
+    pts = np.array([[0, 0], [49, 69], [25, 3], [3, 60], [47, 12]])
+    assert np.allclose(O.convolve_points(G, R, 5, pts), full[pts[:, 0], pts[:, 1]], rtol=0,
+                       atol=1e-12 * np.abs(full).max())
+
+
+def test_wire_rows_pick_cell_centres():
+    O_ = np.arange(30 * 4).reshape(30, 4).astype(float)
+    Wv = O.wire_rows(O_, 10)
+    assert Wv.shape == (3, 4)
+    assert np.array_equal(Wv[:, 0], O_[[5, 15, 25], 0])
+
+
+def test_fluctuation_variance_short_drift():
+    """P6 at large bin probabilities: a short drift gives p up to ~0.3, where
+    the binomial variance q p (1 - p) differs clearly from the Poisson q p.
+    After rescaling the patch to q, the delta method gives
+    var_i = q p_i (1 - p_i)(1 - 2 p_i) + p_i^2 sum_j q p_j (1 - p_j)."""
+    phys = W.physics(True)
+    pl = _plane()
+    q = 20000.0
+    dep = np.array([[1.6 * 100.0, 0.0, 100.2, -100.0 + 60.3, q]])
+    meta, mean_vals, _ = O.rasterize(dep, W.physics(False), pl)
+    p = mean_vals / q
+    V = np.array([O.rasterize(dep, phys, pl, event_id=e)[1] for e in range(4000)])
+    expect = q * p * (1 - p) * (1 - 2 * p) + p ** 2 * np.sum(q * p * (1 - p))
+    big = p > 0.05
+    assert big.sum() >= 3 and p.max() > 0.2
+    ratio = V.var(0)[big] / expect[big]
+    assert np.all(np.abs(ratio - 1.0) < 0.12)
