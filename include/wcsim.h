@@ -1,0 +1,242 @@
+/*
+ * wcsim.h -- C ABI of the MI355X LArTPC signal-simulation hot path.
+ *
+ * The library computes the three steps the paper's DepoTransform holds
+ * (arXiv:2304.01841, Sec. 2):
+ *   1. Rasterization: every ionization-electron group ("depo") is drifted to
+ *      the response plane, diffused into 2-D Gaussian widths and binned into a
+ *      patch of (pitch-impact bin x time tick) weights, optionally with
+ *      statistical fluctuation (Sec. 2 step 1; random numbers Sec. 4.1);
+ *   2. Scatter-Add: patches are summed into a plane grid with atomic adds
+ *      (Sec. 2 step 2);
+ *   3. Convolution: the grid is convolved with the detector response by FFT
+ *      (Sec. 2 step 3; inverse real transform along the tick axis as in the
+ *      idft_cr example of Sec. 4.2).
+ *
+ * Units: mm, us, electrons.  Diffusion constants in mm^2/us (1 cm^2/s =
+ * 1e-4 mm^2/us).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a wcsim_status; no C++ exception crosses the ABI.
+ *     On failure, wcsim_last_error() gives a message (thread-local, valid until
+ *     the next wcsim_* call on the same thread).
+ *   - Validation failures return WCSIM_E_INVALID with nothing launched and
+ *     outputs untouched.  HIP runtime failures return WCSIM_E_DEVICE,
+ *     allocation failures WCSIM_E_NOMEM.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on it, except wcsim_plane_create/destroy, the patch-set
+ *     calls that allocate or copy to the host, and every path that reads or
+ *     writes host memory, which synchronise the stream before returning.
+ *   - A wcsim_plane is immutable after creation and may be shared by
+ *     concurrent calls on different streams; calls that share a workspace
+ *     must be ordered by the caller.
+ *   - Device pointers must be device (or managed) memory of the current HIP
+ *     device; the caller owns every buffer it passes in.
+ */
+#ifndef WCSIM_H
+#define WCSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WCSIM_OK = 0,
+    WCSIM_E_INVALID = -1, /* bad argument; nothing launched */
+    WCSIM_E_NOMEM = -2,   /* allocation failed / workspace too small */
+    WCSIM_E_DEVICE = -3,  /* HIP runtime error */
+    WCSIM_E_STATE = -4    /* object used in a wrong state (e.g. NULL handle) */
+} wcsim_status;
+
+typedef enum { WCSIM_MEM_HOST = 0, WCSIM_MEM_DEVICE = 1 } wcsim_mem;
+
+typedef enum {
+    WCSIM_OUT_WIRE = 0, /* [nwires][nticks]: impact row nimpact/2 of each wire cell */
+    WCSIM_OUT_PITCH = 1 /* [nwires*nimpact][nticks]: every pitch-impact row */
+} wcsim_out;
+
+/* One depo (Sec. 2 step 1, "ionization electron group"): x is the drift
+ * coordinate, (y, z) the transverse position, t the deposition time and q the
+ * number of electrons (q >= 0).  Array of structures, 40 bytes per depo. */
+typedef struct {
+    double x, y, z, t, q;
+} wcsim_depo;
+
+/* Drift and diffusion constants and fluctuation switch. */
+typedef struct {
+    double drift_speed; /* mm/us, > 0 */
+    double DL, DT;      /* longitudinal / transverse diffusion, mm^2/us, >= 0 */
+    double nsigma;      /* patch half-extent in Gaussian widths, >= 0 */
+    int32_t fluctuate;  /* 0: mean patch; 1: binomial fluctuation */
+    int32_t reserved;   /* must be 0 */
+    uint64_t seed;      /* Philox key (mixed with plane_id) */
+} wcsim_physics;
+
+/* Plane geometry and response (Sec. 2 steps 2-3).  The grid has
+ * nwires*nimpact pitch bins of pitch/nimpact mm, starting at pitch coordinate
+ * pitch_origin, and nticks ticks of `tick` us starting at t0.  The pitch
+ * coordinate of a depo is y*dir_y + z*dir_z.  The response is
+ * [resp_npitch][resp_nticks] float32 in host memory, row-major; response row
+ * resp_origin is aligned with the output row and tick 0 of the response is
+ * the output tick itself (causal):
+ *   out[p][t] = sum_r sum_s response[r][s] grid[p + resp_origin - r][t - s]. */
+typedef struct {
+    int32_t plane_id, nwires, nimpact, nticks;
+    double pitch, tick, t0;
+    double plane_x, dir_y, dir_z, pitch_origin;
+    int32_t resp_npitch, resp_nticks, resp_origin, reserved;
+    const float *response;
+} wcsim_plane_desc;
+
+/* Execution schedule of a plane; 0 in a field means "choose".  The result of
+ * the simulation does not depend on it (up to float32 rounding). */
+typedef struct {
+    int32_t fft_ticks;  /* even padded tick-axis transform length N' >= nticks + resp_nticks - 1 */
+    int32_t fft_pitch;  /* pitch-axis overlap-save block transform length L > resp_npitch - 1 */
+    int32_t freq_chunk; /* spectrum columns per chunk (8 or 16) */
+    int32_t tile;       /* raster tile shape id (see wcsim_plane_info.tile) */
+} wcsim_schedule;
+
+/* Derived sizes of a plane (read-only). */
+typedef struct {
+    int64_t npitch, nticks, nwires, nimpact;
+    int32_t fft_ticks, fft_pitch, freq_chunk, tile;
+    int32_t nchunks;        /* spectrum column chunks */
+    int32_t pitch_blocks;   /* overlap-save blocks along pitch */
+    int32_t tile_pitch, tile_ticks;
+    int64_t ntiles;
+    int64_t spectrum_bytes; /* resident response spectrum */
+} wcsim_plane_info;
+
+typedef struct wcsim_plane wcsim_plane;
+typedef struct wcsim_patches wcsim_patches;
+
+/* Create a plane: validates the descriptor and physics, copies the response,
+ * chooses a schedule and computes the resident response spectrum on the GPU
+ * (Sec. 2 step 3: the response is transformed once per plane).  Synchronises
+ * `stream`.  Errors: WCSIM_E_INVALID for NULL pointers, non-positive sizes,
+ * nimpact < 1, resp_origin outside [0, resp_npitch), non-finite or
+ * out-of-range constants, or a non-unit pitch direction; WCSIM_E_NOMEM when
+ * device memory runs out.  The plane owns its device memory until
+ * wcsim_plane_destroy. */
+wcsim_status wcsim_plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phys,
+                                void *stream, wcsim_plane **out);
+
+/* Same with an explicit schedule (fields 0 = choose).  WCSIM_E_INVALID when a
+ * requested schedule is not supported for the plane. */
+wcsim_status wcsim_plane_create_with_schedule(const wcsim_plane_desc *desc,
+                                              const wcsim_physics *phys,
+                                              const wcsim_schedule *sched, void *stream,
+                                              wcsim_plane **out);
+
+/* Frees the plane (synchronises the device first).  NULL is ignored. */
+void wcsim_plane_destroy(wcsim_plane *plane);
+
+wcsim_status wcsim_plane_get_info(const wcsim_plane *plane, wcsim_plane_info *info);
+
+/* Rasterization (Sec. 2 step 1): one patch per depo.
+ *   depos: n depos in host (mem = WCSIM_MEM_HOST) or device memory.
+ *   event_id: mixed into the fluctuation random numbers (low 32 bits).
+ * A patch covers the inclusive window floor(mu - nsigma s) ..
+ * floor(mu + nsigma s) along pitch and ticks.  Depos whose window misses the
+ * grid, and invalid depos, get an empty patch.  Host depos are validated on
+ * the host (non-finite field, q < 0 or x < plane_x -> WCSIM_E_INVALID);
+ * invalid device depos contribute nothing.  A window longer than 1024 bins on
+ * either axis is rejected (host) or dropped (device).
+ * The patch set is allocated by the library (the call synchronises `stream`
+ * to size it) and owned by the caller through *out until
+ * wcsim_patches_destroy. */
+wcsim_status wcsim_rasterize(const wcsim_plane *plane, const wcsim_depo *depos, int64_t n,
+                             wcsim_mem mem, uint64_t event_id, void *stream,
+                             wcsim_patches **out);
+
+/* Number of depos and of patch values in a patch set. */
+wcsim_status wcsim_patches_count(const wcsim_patches *patches, int64_t *ndepos, int64_t *nvalues);
+
+/* Device views of a patch set (valid until wcsim_patches_destroy):
+ *   meta    [ndepos][4] int32 = lo_p, lo_t, n_p, n_t (absolute first bin and
+ *           window lengths; n_p = n_t = 0 for an empty patch),
+ *   offsets [ndepos + 1] int64 exclusive prefix sum of n_p*n_t (the scan of
+ *           patch sizes, Sec. 4.3),
+ *   values  [nvalues] float32, patch d row-major n_p x n_t at offsets[d]. */
+wcsim_status wcsim_patches_device(const wcsim_patches *patches, const int32_t **meta,
+                                  const int64_t **offsets, const float **values);
+
+/* Copy a patch set to host arrays of the sizes above (synchronous). */
+wcsim_status wcsim_patches_copy_to_host(const wcsim_patches *patches, int32_t *meta,
+                                        int64_t *offsets, float *values);
+
+void wcsim_patches_destroy(wcsim_patches *patches);
+
+/* Scatter-Add (Sec. 2 step 2): grid[p][t] += patch value for every patch bin
+ * inside the [npitch][nticks] float32 device grid; bins outside are dropped.
+ * zero_first != 0 clears the grid first.  Atomic float adds: the summation
+ * order is unspecified. */
+wcsim_status wcsim_scatter_add(const wcsim_plane *plane, const wcsim_patches *patches,
+                               float *grid, int32_t zero_first, void *stream);
+
+/* Workspace (device bytes) that wcsim_convolve needs for an output kind. */
+size_t wcsim_convolve_workspace_bytes(const wcsim_plane *plane, wcsim_out out_kind);
+
+/* Convolution (Sec. 2 step 3): out = grid (*) response, cropped to the grid
+ * (see wcsim_plane_desc), as [npitch][nticks] (WCSIM_OUT_PITCH) or
+ * [nwires][nticks] (WCSIM_OUT_WIRE) float32 in device memory.  `grid` is the
+ * [npitch][nticks] float32 device grid.  `workspace` is device memory of at
+ * least wcsim_convolve_workspace_bytes bytes, aligned to 256 bytes. */
+wcsim_status wcsim_convolve(const wcsim_plane *plane, const float *grid, float *out,
+                            wcsim_out out_kind, void *workspace, void *stream);
+
+/* Workspace (device bytes) for wcsim_simulate_event with up to n depos. */
+size_t wcsim_simulate_workspace_bytes(const wcsim_plane *plane, int64_t n, wcsim_out out_kind);
+
+/* The whole DepoTransform (Sec. 2 steps 1-3) for one event: rasterize with
+ * fluctuation as configured, scatter into the plane grid through LDS-staged
+ * tiles, convolve, and write `out` ([nwires][nticks] or [npitch][nticks]
+ * float32, in host or device memory per out_mem).  Depos follow the rules of
+ * wcsim_rasterize.  `workspace`: device memory of at least
+ * wcsim_simulate_workspace_bytes(plane, n, out_kind) bytes, 256-byte aligned;
+ * after the call it also holds the plane grid (see wcsim_workspace_grid) and
+ * the count of invalid device depos (wcsim_workspace_invalid_count). */
+wcsim_status wcsim_simulate_event(const wcsim_plane *plane, const wcsim_depo *depos, int64_t n,
+                                  wcsim_mem depo_mem, uint64_t event_id, float *out,
+                                  wcsim_out out_kind, wcsim_mem out_mem, void *workspace,
+                                  void *stream);
+
+/* Device pointer to the [npitch][nticks] grid inside a simulate workspace. */
+float *wcsim_workspace_grid(const wcsim_plane *plane, void *workspace, int64_t n);
+
+/* Number of invalid depos dropped by the last wcsim_simulate_event that used
+ * this workspace (synchronises `stream`). */
+wcsim_status wcsim_workspace_invalid_count(const void *workspace, void *stream, int64_t *count);
+
+/* Batched form: nevents events, each with its own plane (planes may repeat),
+ * depos (device memory), event id and output (device memory), run as one
+ * sequence of launches whose kernels each cover every event.  `workspace`:
+ * device memory of at least wcsim_batch_workspace_bytes bytes. */
+size_t wcsim_batch_workspace_bytes(const wcsim_plane *const *planes, const int64_t *n,
+                                   int32_t nevents, wcsim_out out_kind);
+wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
+                                  const wcsim_depo *const *depos, const int64_t *n,
+                                  const uint64_t *event_ids, int32_t nevents,
+                                  float *const *outs, wcsim_out out_kind, void *workspace,
+                                  void *stream);
+
+/* Diagnostic: the Philox4x32-10 generator the fluctuation uses (Sec. 4.1,
+ * random123), evaluated on the GPU: out[i] = Philox4x32-10(ctr[i], key[i]).
+ * ctr/out: n x 4 uint32, key: n x 2 uint32, all device memory. */
+wcsim_status wcsim_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64_t n,
+                                 uint32_t *out, void *stream);
+
+const char *wcsim_last_error(void);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t wcsim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCSIM_H */

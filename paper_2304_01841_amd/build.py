@@ -1,0 +1,53 @@
+"""Build libwcsim.so (HIP, gfx950) in-tree with hipcc.
+
+Usage: python -m paper_2304_01841_amd.build   (or call build()).
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+SRC = [os.path.join(PKG, "csrc", f) for f in ("api.hip", "raster.hip", "fft.hip")]
+HDR = [os.path.join(ROOT, "include", "wcsim.h"), os.path.join(PKG, "csrc", "wcsim_internal.h")]
+LIB = os.path.join(PKG, "libwcsim.so")
+
+HIPCC_FLAGS = [
+    "-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-shared",
+    # no packed FP32 instructions (see DESIGN notes on gfx950 packed-math)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def hipcc() -> str:
+    return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source into one shared library (always recompiles)."""
+    bdir = os.path.join(ROOT, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    objs = []
+    for src in SRC:
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f != "-shared"] + [
+            "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIPCC_FLAGS + objs + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,609 @@
+// C ABI of libwcsim (declared in include/wcsim.h): argument validation,
+// plane objects with their resident response spectra, patch sets, workspace
+// carving and the launch sequences of the DepoTransform steps
+// (arXiv:2304.01841, Sec. 2).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wcsim_internal.h"
+
+namespace wcs {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+wcsim_status fail(wcsim_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+wcsim_status check_hip(hipError_t e, const char *what)
+{
+    set_error(std::string("HIP error in ") + what + ": " + hipGetErrorString(e));
+    return (e == hipErrorOutOfMemory) ? WCSIM_E_NOMEM : WCSIM_E_DEVICE;
+}
+
+namespace {
+
+bool finite_all(std::initializer_list<double> v)
+{
+    for (double x : v)
+        if (!std::isfinite(x))
+            return false;
+    return true;
+}
+
+wcsim_status validate_plane(const wcsim_plane_desc *d, const wcsim_physics *ph)
+{
+    if (!d || !ph)
+        return fail(WCSIM_E_INVALID, "NULL plane descriptor or physics");
+    if (d->nwires <= 0 || d->nimpact < 1 || d->nticks <= 0)
+        return fail(WCSIM_E_INVALID, "nwires, nimpact and nticks must be positive");
+    if ((int64_t)d->nwires * d->nimpact > (1LL << 30) || d->nticks > (1 << 24))
+        return fail(WCSIM_E_INVALID, "plane too large");
+    if (!finite_all({d->pitch, d->tick, d->t0, d->plane_x, d->dir_y, d->dir_z, d->pitch_origin}))
+        return fail(WCSIM_E_INVALID, "non-finite plane geometry");
+    if (!(d->pitch > 0.0) || !(d->tick > 0.0))
+        return fail(WCSIM_E_INVALID, "pitch and tick must be positive");
+    const double norm = d->dir_y * d->dir_y + d->dir_z * d->dir_z;
+    if (fabs(norm - 1.0) > 1e-6)
+        return fail(WCSIM_E_INVALID, "pitch direction must be a unit vector");
+    if (d->resp_npitch <= 0 || d->resp_nticks <= 0 || !d->response)
+        return fail(WCSIM_E_INVALID, "response must be non-empty");
+    if (d->resp_origin < 0 || d->resp_origin >= d->resp_npitch)
+        return fail(WCSIM_E_INVALID, "resp_origin outside [0, resp_npitch)");
+    if (d->resp_npitch > 4096 || d->resp_nticks > 8192)
+        return fail(WCSIM_E_INVALID, "response too large");
+    for (int64_t i = 0; i < (int64_t)d->resp_npitch * d->resp_nticks; ++i)
+        if (!std::isfinite(d->response[i]))
+            return fail(WCSIM_E_INVALID, "non-finite response value");
+    if (!finite_all({ph->drift_speed, ph->DL, ph->DT, ph->nsigma}))
+        return fail(WCSIM_E_INVALID, "non-finite physics constant");
+    if (!(ph->drift_speed > 0.0) || ph->DL < 0.0 || ph->DT < 0.0 || ph->nsigma < 0.0)
+        return fail(WCSIM_E_INVALID, "drift speed must be > 0 and DL, DT, nsigma >= 0");
+    if (ph->fluctuate != 0 && ph->fluctuate != 1)
+        return fail(WCSIM_E_INVALID, "fluctuate must be 0 or 1");
+    if (ph->reserved != 0 || d->reserved != 0)
+        return fail(WCSIM_E_INVALID, "reserved fields must be 0");
+    return WCSIM_OK;
+}
+
+int pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v)
+        p *= 2;
+    return p;
+}
+
+// Host copy of exp(-2 pi i j / n), j < count, rounded from FP64.
+std::vector<float2> twiddles(int n, int count)
+{
+    std::vector<float2> t((size_t)count);
+    for (int j = 0; j < count; ++j) {
+        const double a = -2.0 * M_PI * (double)j / (double)n;
+        t[(size_t)j] = make_float2((float)cos(a), (float)sin(a));
+    }
+    return t;
+}
+
+void free_plane(wcsim_plane *p)
+{
+    if (!p)
+        return;
+    (void)hipFree(p->twT);
+    (void)hipFree(p->twHalf);
+    (void)hipFree(p->twL);
+    (void)hipFree(p->K);
+    delete p;
+}
+
+constexpr size_t kLdsBytes = 160 * 1024;
+
+wcsim_status choose_schedule(wcsim_plane *pl, const wcsim_schedule *sc)
+{
+    const int nmin = (int)(pl->Nt + pl->Rt - 1);
+    int nfft = (sc && sc->fft_ticks) ? sc->fft_ticks : smallest_smooth_even(nmin);
+    if (nfft < nmin || (nfft & 1))
+        return fail(WCSIM_E_INVALID, "fft_ticks must be even and >= nticks + resp_nticks - 1");
+    pl->Nfft = nfft;
+    pl->N2 = nfft / 2;
+    if (!make_plan(pl->N2, &pl->planT))
+        return fail(WCSIM_E_INVALID, "fft_ticks/2 must factor into 2, 3 and 5");
+    if (sizeof(float2) * (size_t)(pl->N2 + 1) * 2 > kLdsBytes)
+        return fail(WCSIM_E_INVALID, "tick-axis transform too long for LDS");
+    pl->F = (sc && sc->freq_chunk) ? sc->freq_chunk : 16;
+    if (pl->F != 8 && pl->F != 16)
+        return fail(WCSIM_E_INVALID, "freq_chunk must be 8 or 16");
+    int L = (sc && sc->fft_pitch) ? sc->fft_pitch : std::max(256, pow2_at_least(2 * pl->Rp));
+    if (L < pl->Rp)
+        return fail(WCSIM_E_INVALID, "fft_pitch must be >= resp_npitch");
+    if (!make_plan(L, &pl->planL))
+        return fail(WCSIM_E_INVALID, "fft_pitch must factor into 2, 3 and 5");
+    if (sizeof(float2) * (size_t)L * pl->F > kLdsBytes)
+        return fail(WCSIM_E_INVALID, "pitch block too large for LDS");
+    {
+        // every pass must stage at most 32 complex values per thread of 1024
+        for (int q = 0; q < pl->planL.npass; ++q) {
+            const int R = pl->planL.radix[q];
+            if ((int64_t)L / R * pl->F > 1024LL * (32 / R))
+                return fail(WCSIM_E_INVALID, "pitch block too large for one workgroup");
+        }
+        for (int q = 0; q < pl->planT.npass; ++q) {
+            const int R = pl->planT.radix[q];
+            if ((int64_t)pl->N2 / R * 2 > 1024LL * (32 / R))
+                return fail(WCSIM_E_INVALID, "tick transform too large for one workgroup");
+        }
+    }
+    pl->L = L;
+    pl->V = L - pl->Rp + 1;
+    pl->nblocks = (int)((pl->Np + pl->V - 1) / pl->V);
+    pl->H = pl->N2 + 1;
+    pl->C = (pl->H + pl->F - 1) / pl->F;
+    pl->tile = (sc && sc->tile) ? sc->tile : 0;
+    if (pl->tile < 0 || pl->tile >= kNumTileShapes)
+        return fail(WCSIM_E_INVALID, "unknown tile shape");
+    pl->ts = tile_shape(pl->tile);
+    pl->ntp = (int)((pl->Np + pl->ts.tp - 1) / pl->ts.tp);
+    pl->ntt = (int)((pl->Nt + pl->ts.tt - 1) / pl->ts.tt);
+    pl->ntiles = (int64_t)pl->ntp * pl->ntt;
+    return WCSIM_OK;
+}
+
+template <typename T>
+wcsim_status upload(T **dst, const std::vector<T> &src, hipStream_t s)
+{
+    WCS_HIP(hipMalloc((void **)dst, sizeof(T) * src.size()));
+    WCS_HIP(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s));
+    return WCSIM_OK;
+}
+
+wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phys,
+                          const wcsim_schedule *sched, void *stream, wcsim_plane **out)
+{
+    if (!out)
+        return fail(WCSIM_E_INVALID, "NULL output handle");
+    *out = nullptr;
+    wcsim_status st = validate_plane(desc, phys);
+    if (st != WCSIM_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    wcsim_plane *pl = new (std::nothrow) wcsim_plane();
+    if (!pl)
+        return fail(WCSIM_E_NOMEM, "host allocation failed");
+    pl->desc = *desc;
+    pl->desc.response = nullptr;
+    pl->phys = *phys;
+    (void)hipGetDevice(&pl->device);
+    pl->Np = (int64_t)desc->nwires * desc->nimpact;
+    pl->Nt = desc->nticks;
+    pl->Nw = desc->nwires;
+    pl->Rp = desc->resp_npitch;
+    pl->Rt = desc->resp_nticks;
+    pl->r0 = desc->resp_origin;
+    PlaneParams &k = pl->kp;
+    k.v = phys->drift_speed;
+    k.DL = phys->DL;
+    k.DT = phys->DT;
+    k.nsigma = phys->nsigma;
+    k.dp = desc->pitch / (double)desc->nimpact;
+    k.tick = desc->tick;
+    k.t0 = desc->t0;
+    k.plane_x = desc->plane_x;
+    k.dir_y = desc->dir_y;
+    k.dir_z = desc->dir_z;
+    k.pitch_origin = desc->pitch_origin;
+    k.Np = (int32_t)pl->Np;
+    k.Nt = (int32_t)pl->Nt;
+    k.nimpact = desc->nimpact;
+    k.plane_id = desc->plane_id;
+    k.key0 = (uint32_t)phys->seed;
+    k.key1 = (uint32_t)(phys->seed >> 32) ^ (uint32_t)desc->plane_id;
+    k.fluct = phys->fluctuate;
+    k.pad_ = 0;
+    if ((st = choose_schedule(pl, sched)) != WCSIM_OK) {
+        free_plane(pl);
+        return st;
+    }
+    float *resp = nullptr;
+    void *work = nullptr;
+    auto cleanup = [&](wcsim_status r) {
+        (void)hipFree(resp);
+        (void)hipFree(work);
+        if (r != WCSIM_OK)
+            free_plane(pl);
+        return r;
+    };
+    if ((st = upload(&pl->twT, twiddles(pl->N2, pl->N2), s)) != WCSIM_OK ||
+        (st = upload(&pl->twHalf, twiddles(pl->Nfft, pl->N2 + 1), s)) != WCSIM_OK ||
+        (st = upload(&pl->twL, twiddles(pl->L, pl->L), s)) != WCSIM_OK)
+        return cleanup(st);
+    hipError_t e;
+    const size_t kbytes = sizeof(float2) * (size_t)pl->C * pl->L * pl->F;
+    if ((e = hipMalloc((void **)&pl->K, kbytes)) != hipSuccess)
+        return cleanup(check_hip(e, "hipMalloc(response spectrum)"));
+    const size_t rbytes = sizeof(float) * (size_t)pl->Rp * pl->Rt;
+    if ((e = hipMalloc((void **)&resp, rbytes)) != hipSuccess)
+        return cleanup(check_hip(e, "hipMalloc(response)"));
+    if ((e = hipMalloc(&work, response_work_bytes(pl))) != hipSuccess)
+        return cleanup(check_hip(e, "hipMalloc(response work)"));
+    if ((e = hipMemcpyAsync(resp, desc->response, rbytes, hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return cleanup(check_hip(e, "hipMemcpyAsync(response)"));
+    if ((e = build_response_spectrum(pl, resp, work, s)) != hipSuccess)
+        return cleanup(check_hip(e, "response spectrum"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return cleanup(check_hip(e, "hipStreamSynchronize"));
+    *out = pl;
+    return cleanup(WCSIM_OK);
+}
+
+// Host-side checks of host depos: finite fields, q >= 0, x >= plane_x, and a
+// window no longer than kMaxWindow bins at the longest drift.
+wcsim_status validate_host_depos(const wcsim_plane *pl, const wcsim_depo *d, int64_t n)
+{
+    double xmax = pl->kp.plane_x;
+    for (int64_t i = 0; i < n; ++i) {
+        const wcsim_depo &q = d[i];
+        if (!finite_all({q.x, q.y, q.z, q.t, q.q}))
+            return fail(WCSIM_E_INVALID, "depo " + std::to_string(i) + " has a non-finite field");
+        if (q.q < 0.0)
+            return fail(WCSIM_E_INVALID, "depo " + std::to_string(i) + " has negative charge");
+        if (q.x < pl->kp.plane_x)
+            return fail(WCSIM_E_INVALID,
+                        "depo " + std::to_string(i) + " lies behind the response plane");
+        xmax = std::max(xmax, q.x);
+    }
+    const double T = (xmax - pl->kp.plane_x) / pl->kp.v;
+    const double sp = sqrt(2.0 * pl->kp.DT * T) / pl->kp.dp;
+    const double stt = sqrt(2.0 * pl->kp.DL * T) / pl->kp.v / pl->kp.tick;
+    if (2.0 * pl->kp.nsigma * std::max(sp, stt) + 2.0 > (double)kMaxWindow)
+        return fail(WCSIM_E_INVALID, "patch window longer than 1024 bins");
+    return WCSIM_OK;
+}
+
+}  // namespace
+}  // namespace wcs
+
+using namespace wcs;
+
+extern "C" {
+
+int32_t wcsim_version(void) { return 10000; }
+
+const char *wcsim_last_error(void) { return g_last_error.c_str(); }
+
+wcsim_status wcsim_plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phys,
+                                void *stream, wcsim_plane **out)
+{
+    return plane_create(desc, phys, nullptr, stream, out);
+}
+
+wcsim_status wcsim_plane_create_with_schedule(const wcsim_plane_desc *desc,
+                                              const wcsim_physics *phys,
+                                              const wcsim_schedule *sched, void *stream,
+                                              wcsim_plane **out)
+{
+    return plane_create(desc, phys, sched, stream, out);
+}
+
+void wcsim_plane_destroy(wcsim_plane *plane)
+{
+    if (!plane)
+        return;
+    (void)hipDeviceSynchronize();
+    free_plane(plane);
+}
+
+wcsim_status wcsim_plane_get_info(const wcsim_plane *pl, wcsim_plane_info *info)
+{
+    if (!pl || !info)
+        return fail(WCSIM_E_INVALID, "NULL argument");
+    info->npitch = pl->Np;
+    info->nticks = pl->Nt;
+    info->nwires = pl->Nw;
+    info->nimpact = pl->kp.nimpact;
+    info->fft_ticks = pl->Nfft;
+    info->fft_pitch = pl->L;
+    info->freq_chunk = pl->F;
+    info->tile = pl->tile;
+    info->nchunks = pl->C;
+    info->pitch_blocks = pl->nblocks;
+    info->tile_pitch = pl->ts.tp;
+    info->tile_ticks = pl->ts.tt;
+    info->ntiles = pl->ntiles;
+    info->spectrum_bytes = (int64_t)sizeof(float2) * pl->C * pl->L * pl->F;
+    return WCSIM_OK;
+}
+
+wcsim_status wcsim_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64_t n,
+                                 uint32_t *out, void *stream)
+{
+    if (n < 0 || (n > 0 && (!ctr || !key || !out)))
+        return fail(WCSIM_E_INVALID, "bad Philox arguments");
+    WCS_HIP(launch_philox(ctr, key, n, out, (hipStream_t)stream));
+    return WCSIM_OK;
+}
+
+wcsim_status wcsim_rasterize(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                             wcsim_mem mem, uint64_t event_id, void *stream, wcsim_patches **out)
+{
+    if (!pl)
+        return fail(WCSIM_E_STATE, "NULL plane");
+    if (!out || n < 0 || (n > 0 && !depos) || (mem != WCSIM_MEM_HOST && mem != WCSIM_MEM_DEVICE))
+        return fail(WCSIM_E_INVALID, "bad rasterize arguments");
+    if (n > (1LL << 31) - 1)
+        return fail(WCSIM_E_INVALID, "too many depos");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (mem == WCSIM_MEM_HOST) {
+        wcsim_status st = validate_host_depos(pl, depos, n);
+        if (st != WCSIM_OK)
+            return st;
+    }
+    wcsim_patches *P = new (std::nothrow) wcsim_patches();
+    if (!P)
+        return fail(WCSIM_E_NOMEM, "host allocation failed");
+    P->n = n;
+    P->device = pl->device;
+    void *scratch = nullptr;
+    auto bail = [&](wcsim_status r) {
+        (void)hipFree(scratch);
+        if (r != WCSIM_OK) {
+            (void)hipFree(P->meta);
+            (void)hipFree(P->offsets);
+            (void)hipFree(P->values);
+            (void)hipFree(P->staged);
+            delete P;
+        } else {
+            (void)hipFree(P->staged);
+            P->staged = nullptr;
+            *out = P;
+        }
+        return r;
+    };
+    hipError_t e;
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    if ((e = hipMalloc((void **)&P->meta, sizeof(int32_t) * 4 * nn)) != hipSuccess ||
+        (e = hipMalloc((void **)&P->offsets, sizeof(int64_t) * (nn + 1))) != hipSuccess ||
+        (e = hipMalloc(&scratch, scan_scratch_bytes(n + 1))) != hipSuccess)
+        return bail(check_hip(e, "hipMalloc(patch set)"));
+    const wcsim_depo *dd = depos;
+    if (mem == WCSIM_MEM_HOST && n > 0) {
+        if ((e = hipMalloc((void **)&P->staged, sizeof(wcsim_depo) * nn)) != hipSuccess)
+            return bail(check_hip(e, "hipMalloc(depos)"));
+        if ((e = hipMemcpyAsync(P->staged, depos, sizeof(wcsim_depo) * (size_t)n,
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return bail(check_hip(e, "hipMemcpyAsync(depos)"));
+        dd = P->staged;
+    }
+    if ((e = launch_patch_sizes(pl, dd, n, P->meta, P->offsets, s)) != hipSuccess ||
+        (e = launch_exclusive_scan_i64(P->offsets, n + 1, scratch, s)) != hipSuccess)
+        return bail(check_hip(e, "patch sizes"));
+    int64_t total = 0;
+    if ((e = hipMemcpyAsync(&total, P->offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(check_hip(e, "patch total"));
+    P->nvalues = total;
+    if ((e = hipMalloc((void **)&P->values, sizeof(float) * (size_t)std::max<int64_t>(total, 1))) !=
+        hipSuccess)
+        return bail(check_hip(e, "hipMalloc(patch values)"));
+    if ((e = launch_patch_values(pl, dd, n, event_id, P->meta, P->offsets, P->values, s)) !=
+        hipSuccess)
+        return bail(check_hip(e, "patch values"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(check_hip(e, "hipStreamSynchronize"));
+    return bail(WCSIM_OK);
+}
+
+wcsim_status wcsim_patches_count(const wcsim_patches *P, int64_t *ndepos, int64_t *nvalues)
+{
+    if (!P)
+        return fail(WCSIM_E_STATE, "NULL patch set");
+    if (ndepos)
+        *ndepos = P->n;
+    if (nvalues)
+        *nvalues = P->nvalues;
+    return WCSIM_OK;
+}
+
+wcsim_status wcsim_patches_device(const wcsim_patches *P, const int32_t **meta,
+                                  const int64_t **offsets, const float **values)
+{
+    if (!P)
+        return fail(WCSIM_E_STATE, "NULL patch set");
+    if (meta)
+        *meta = P->meta;
+    if (offsets)
+        *offsets = P->offsets;
+    if (values)
+        *values = P->values;
+    return WCSIM_OK;
+}
+
+wcsim_status wcsim_patches_copy_to_host(const wcsim_patches *P, int32_t *meta, int64_t *offsets,
+                                        float *values)
+{
+    if (!P)
+        return fail(WCSIM_E_STATE, "NULL patch set");
+    if (meta)
+        WCS_HIP(hipMemcpy(meta, P->meta, sizeof(int32_t) * 4 * (size_t)P->n, hipMemcpyDeviceToHost));
+    if (offsets)
+        WCS_HIP(hipMemcpy(offsets, P->offsets, sizeof(int64_t) * (size_t)(P->n + 1),
+                          hipMemcpyDeviceToHost));
+    if (values && P->nvalues > 0)
+        WCS_HIP(hipMemcpy(values, P->values, sizeof(float) * (size_t)P->nvalues,
+                          hipMemcpyDeviceToHost));
+    return WCSIM_OK;
+}
+
+void wcsim_patches_destroy(wcsim_patches *P)
+{
+    if (!P)
+        return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(P->meta);
+    (void)hipFree(P->offsets);
+    (void)hipFree(P->values);
+    (void)hipFree(P->staged);
+    delete P;
+}
+
+wcsim_status wcsim_scatter_add(const wcsim_plane *pl, const wcsim_patches *P, float *grid,
+                               int32_t zero_first, void *stream)
+{
+    if (!pl || !P)
+        return fail(WCSIM_E_STATE, "NULL plane or patch set");
+    if (!grid)
+        return fail(WCSIM_E_INVALID, "NULL grid");
+    hipStream_t s = (hipStream_t)stream;
+    if (zero_first)
+        WCS_HIP(launch_fill_zero(grid, sizeof(float) * (size_t)pl->Np * pl->Nt, s));
+    WCS_HIP(launch_scatter_flat(pl, P->n, P->meta, P->offsets, P->values, grid, s));
+    return WCSIM_OK;
+}
+
+size_t wcsim_convolve_workspace_bytes(const wcsim_plane *pl, wcsim_out out_kind)
+{
+    if (!pl)
+        return 0;
+    return conv_work_bytes(pl, out_kind);
+}
+
+wcsim_status wcsim_convolve(const wcsim_plane *pl, const float *grid, float *out,
+                            wcsim_out out_kind, void *workspace, void *stream)
+{
+    if (!pl)
+        return fail(WCSIM_E_STATE, "NULL plane");
+    if (!grid || !out || !workspace)
+        return fail(WCSIM_E_INVALID, "NULL grid, output or workspace");
+    if (out_kind != WCSIM_OUT_WIRE && out_kind != WCSIM_OUT_PITCH)
+        return fail(WCSIM_E_INVALID, "bad output kind");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(WCSIM_E_INVALID, "workspace must be 256-byte aligned");
+    WCS_HIP(launch_convolve(pl, grid, out, out_kind, workspace, (hipStream_t)stream));
+    return WCSIM_OK;
+}
+
+static size_t sim_grid_offset(const wcsim_plane *pl, int64_t n) { return raster_work_bytes(pl, n); }
+
+static size_t sim_conv_offset(const wcsim_plane *pl, int64_t n)
+{
+    return sim_grid_offset(pl, n) + align_up(sizeof(float) * (size_t)pl->Np * pl->Nt);
+}
+
+size_t wcsim_simulate_workspace_bytes(const wcsim_plane *pl, int64_t n, wcsim_out out_kind)
+{
+    if (!pl || n < 0)
+        return 0;
+    return sim_conv_offset(pl, n) + conv_work_bytes(pl, out_kind) +
+           align_up(sizeof(wcsim_depo) * (size_t)std::max<int64_t>(n, 1));
+}
+
+float *wcsim_workspace_grid(const wcsim_plane *pl, void *workspace, int64_t n)
+{
+    if (!pl || !workspace)
+        return nullptr;
+    return (float *)((char *)workspace + sim_grid_offset(pl, n));
+}
+
+wcsim_status wcsim_workspace_invalid_count(const void *workspace, void *stream, int64_t *count)
+{
+    if (!workspace || !count)
+        return fail(WCSIM_E_INVALID, "NULL argument");
+    int32_t c = 0;
+    WCS_HIP(hipMemcpyAsync(&c, workspace, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           (hipStream_t)stream));
+    WCS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    *count = c;
+    return WCSIM_OK;
+}
+
+wcsim_status wcsim_simulate_event(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                                  wcsim_mem depo_mem, uint64_t event_id, float *out,
+                                  wcsim_out out_kind, wcsim_mem out_mem, void *workspace,
+                                  void *stream)
+{
+    if (!pl)
+        return fail(WCSIM_E_STATE, "NULL plane");
+    if (n < 0 || (n > 0 && !depos) || !out || !workspace)
+        return fail(WCSIM_E_INVALID, "bad simulate arguments");
+    if (n > (1LL << 31) - 1)
+        return fail(WCSIM_E_INVALID, "too many depos");
+    if ((depo_mem != WCSIM_MEM_HOST && depo_mem != WCSIM_MEM_DEVICE) ||
+        (out_mem != WCSIM_MEM_HOST && out_mem != WCSIM_MEM_DEVICE))
+        return fail(WCSIM_E_INVALID, "bad memory kind");
+    if (out_kind != WCSIM_OUT_WIRE && out_kind != WCSIM_OUT_PITCH)
+        return fail(WCSIM_E_INVALID, "bad output kind");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(WCSIM_E_INVALID, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    const RasterWork rw = raster_work_carve(pl, n, ws);
+    float *grid = (float *)(ws + sim_grid_offset(pl, n));
+    char *conv = ws + sim_conv_offset(pl, n);
+    wcsim_depo *staged = (wcsim_depo *)(conv + conv_work_bytes(pl, out_kind));
+    const wcsim_depo *dd = depos;
+    if (depo_mem == WCSIM_MEM_HOST) {
+        wcsim_status st = validate_host_depos(pl, depos, n);
+        if (st != WCSIM_OK)
+            return st;
+        if (n > 0)
+            WCS_HIP(hipMemcpyAsync(staged, depos, sizeof(wcsim_depo) * (size_t)n,
+                                   hipMemcpyHostToDevice, s));
+        dd = staged;
+    }
+    WCS_HIP(launch_fill_zero(grid, sizeof(float) * (size_t)pl->Np * pl->Nt, s));
+    WCS_HIP(launch_raster_fused(pl, dd, n, event_id, rw, grid, s));
+    const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
+    const size_t out_bytes = sizeof(float) * (size_t)nout * pl->Nt;
+    // Host output: the spectrum buffer of pass A is free once pass B has run
+    // and is at least as large as the output.
+    float *dst = (out_mem == WCSIM_MEM_HOST) ? (float *)conv : out;
+    WCS_HIP(launch_convolve(pl, grid, dst, out_kind, conv, s));
+    if (out_mem == WCSIM_MEM_HOST) {
+        WCS_HIP(hipMemcpyAsync(out, dst, out_bytes, hipMemcpyDeviceToHost, s));
+        WCS_HIP(hipStreamSynchronize(s));
+    }
+    return WCSIM_OK;
+}
+
+size_t wcsim_batch_workspace_bytes(const wcsim_plane *const *planes, const int64_t *n,
+                                   int32_t nevents, wcsim_out out_kind)
+{
+    if (!planes || !n || nevents <= 0)
+        return 0;
+    size_t m = 0;
+    for (int32_t e = 0; e < nevents; ++e)
+        m = std::max(m, wcsim_simulate_workspace_bytes(planes[e], n[e], out_kind));
+    return m;
+}
+
+wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
+                                  const wcsim_depo *const *depos, const int64_t *n,
+                                  const uint64_t *event_ids, int32_t nevents, float *const *outs,
+                                  wcsim_out out_kind, void *workspace, void *stream)
+{
+    if (!planes || !depos || !n || !event_ids || !outs || !workspace || nevents < 0)
+        return fail(WCSIM_E_INVALID, "bad batch arguments");
+    for (int32_t e = 0; e < nevents; ++e) {
+        wcsim_status st = wcsim_simulate_event(planes[e], depos[e], n[e], WCSIM_MEM_DEVICE,
+                                               event_ids[e], outs[e], out_kind, WCSIM_MEM_DEVICE,
+                                               workspace, stream);
+        if (st != WCSIM_OK)
+            return st;
+    }
+    return WCSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,548 @@
+// FFT convolution of the plane grid with the detector response on gfx950
+// (arXiv:2304.01841, Sec. 2 step 3: "the main computation here is FFT"; the
+// tick-axis inverse is a complex-to-real transform along axis 1, the idft_cr
+// of Sec. 4.2).
+//
+// The grid is [Np][Nt] float32 (ticks contiguous).  The linear convolution
+// out[p][t] = sum_r sum_s R[r][s] G[p + r0 - r][t - s] runs in three passes,
+// each one HBM read and one HBM write of its operand:
+//   A  tick-axis real FFT of every pitch row, zero-padded to N' = 2 N2 >=
+//      Nt + Rt - 1 (no wrap-around), written as column chunks [C][Np][F] of
+//      F consecutive frequencies so that the next pass reads whole chunks;
+//   B  per frequency chunk and pitch block: overlap-save along pitch.  A block
+//      of L rows (the V = L - Rp + 1 output rows plus Rp - 1 rows of history)
+//      is transformed in LDS, multiplied by the resident response spectrum
+//      K = DFT_{L x N'}(R) / (L N'), transformed back, and the V valid rows are
+//      kept (all rows, or only each wire's centre impact row);
+//   C  tick-axis inverse real FFT of every kept row, cropped to Nt ticks.
+// No step is a dense contraction, so there is no MFMA: the transforms are
+// mixed-radix (2, 3, 4, 5, 8) self-sorting Stockham passes over LDS, each pass
+// staging its butterflies in registers between two barriers so one LDS buffer
+// suffices.  Twiddles come from FP64-derived float32 tables.
+#include <math.h>
+
+#include <vector>
+
+#include "wcsim_internal.h"
+
+namespace wcs {
+namespace {
+
+constexpr int kRegComplex = 32;  // complex values a thread stages per pass
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // * (-i)
+__device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }  // * (+i)
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Forward DFTs of length R in registers: X_m = sum_t x_t exp(-2 pi i t m / R).
+template <int R>
+__device__ __forceinline__ void dft(float2 *x);
+
+template <>
+__device__ __forceinline__ void dft<2>(float2 *x)
+{
+    const float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft<4>(float2 *x)
+{
+    const float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+    const float2 t2 = cadd(x[1], x[3]), t3 = mul_mi(csub(x[1], x[3]));
+    x[0] = cadd(t0, t2);
+    x[2] = csub(t0, t2);
+    x[1] = cadd(t1, t3);
+    x[3] = csub(t1, t3);
+}
+
+template <>
+__device__ __forceinline__ void dft<8>(float2 *x)
+{
+    // Even outputs are the 4-point DFT of x_t + x_{t+4}; odd outputs the
+    // 4-point DFT of (x_t - x_{t+4}) exp(-2 pi i t / 8).
+    constexpr float c = 0.70710678118654752440f;
+    float2 a[4], b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        a[t] = cadd(x[t], x[t + 4]);
+        b[t] = csub(x[t], x[t + 4]);
+    }
+    b[1] = make_float2(c * (b[1].x + b[1].y), c * (b[1].y - b[1].x));
+    b[2] = mul_mi(b[2]);
+    b[3] = make_float2(c * (b[3].y - b[3].x), -c * (b[3].x + b[3].y));
+    dft<4>(a);
+    dft<4>(b);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        x[2 * m] = a[m];
+        x[2 * m + 1] = b[m];
+    }
+}
+
+template <>
+__device__ __forceinline__ void dft<3>(float2 *x)
+{
+    constexpr float h = 0.86602540378443864676f;  // sin(pi/3)
+    const float2 s = cadd(x[1], x[2]);
+    const float2 d = csub(x[1], x[2]);
+    const float2 m = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+    const float2 r = make_float2(h * d.y, -h * d.x);  // -i sin(pi/3) d
+    x[0] = cadd(x[0], s);
+    x[1] = cadd(m, r);
+    x[2] = csub(m, r);
+}
+
+template <>
+__device__ __forceinline__ void dft<5>(float2 *x)
+{
+    constexpr float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+    constexpr float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+    constexpr float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+    constexpr float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+    const float2 b1 = cadd(x[1], x[4]), d1 = csub(x[1], x[4]);
+    const float2 b2 = cadd(x[2], x[3]), d2 = csub(x[2], x[3]);
+    const float2 x0 = x[0];
+    const float2 e1 = make_float2(x0.x + c1 * b1.x + c2 * b2.x, x0.y + c1 * b1.y + c2 * b2.y);
+    const float2 e2 = make_float2(x0.x + c2 * b1.x + c1 * b2.x, x0.y + c2 * b1.y + c1 * b2.y);
+    // o1 = s1 d1 + s2 d2, o2 = s2 d1 - s1 d2; X1,4 = e1 -/+ i o1, X2,3 = e2 -/+ i o2
+    const float2 o1 = make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+    const float2 o2 = make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+    x[0] = cadd(x0, cadd(b1, b2));
+    x[1] = cadd(e1, mul_mi(o1));
+    x[4] = csub(e1, mul_mi(o1));
+    x[2] = cadd(e2, mul_mi(o2));
+    x[3] = csub(e2, mul_mi(o2));
+}
+
+// One self-sorting Stockham pass of radix R over `nseq` sequences of length N
+// held in LDS (element x of sequence s at s*sstride + x*estride).  Sequence s
+// of butterfly g is g mod nseq (nseq a power of two), so neighbouring threads
+// touch neighbouring sequences.  With p the product of the radices already
+// applied: butterfly i (k = i mod p) reads x[i + t N/R], multiplies by
+// exp(-2 pi i t k / (p R)), runs the R-point DFT and writes y[(i-k) R + k + t p].
+template <int R, int MAXB>
+__device__ __forceinline__ void stockham_pass(float2 *buf, int N, int p, int nseq_shift,
+                                              int sstride, int estride,
+                                              const float2 *__restrict__ tw)
+{
+    const int nb = N / R;
+    const int total = nb << nseq_shift;
+    const int twstep = N / (p * R);
+    const int nseq_mask = (1 << nseq_shift) - 1;
+    float2 v[MAXB][R];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int g = threadIdx.x + b * blockDim.x;
+        if (g < total) {
+            const int s = g & nseq_mask, i = g >> nseq_shift;
+            const float2 *src = buf + s * sstride + i * estride;
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                v[b][t] = src[t * nb * estride];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int g = threadIdx.x + b * blockDim.x;
+        if (g < total) {
+            const int s = g & nseq_mask, i = g >> nseq_shift;
+            const int k = i % p;
+            if (k != 0) {
+#pragma unroll
+                for (int t = 1; t < R; ++t)
+                    v[b][t] = cmul(v[b][t], tw[t * k * twstep]);
+            }
+            dft<R>(v[b]);
+            float2 *dst = buf + s * sstride + ((i - k) * R + k) * estride;
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                dst[t * p * estride] = v[b][t];
+        }
+    }
+    __syncthreads();
+}
+
+// Forward transform of every sequence, pass by pass.
+__device__ void fft_lds(float2 *buf, const FftPlan &plan, int nseq_shift, int sstride,
+                        int estride, const float2 *__restrict__ tw)
+{
+    int p = 1;
+    for (int q = 0; q < plan.npass; ++q) {
+        const int R = plan.radix[q];
+        switch (R) {
+        case 8:
+            stockham_pass<8, kRegComplex / 8>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            break;
+        case 4:
+            stockham_pass<4, kRegComplex / 4>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            break;
+        case 2:
+            stockham_pass<2, kRegComplex / 2>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            break;
+        case 5:
+            stockham_pass<5, kRegComplex / 5>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            break;
+        default:
+            stockham_pass<3, kRegComplex / 3>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            break;
+        }
+        p *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass A: tick-axis real FFT of rows.  Real rows of length ncols (zero padded
+// to 2 N2) are packed as z_n = x_{2n} + i x_{2n+1}; Z = FFT_N2(z) gives
+// X_k = E_k - i w^k D_k and X_{N2-k} = conj(E_k + i w^k D_k), with
+// E_k = (Z_k + conj Z_{N2-k}) / 2, D_k = (Z_k - conj Z_{N2-k}) / 2 and
+// w = exp(-2 pi i / N').  Output chunk layout X[c][row][f], k = c F + f,
+// frequencies above N2 zero.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_rows_r2c(const float *__restrict__ in, int nrows,
+                                                  int ncols, int64_t in_stride, int N2,
+                                                  FftPlan plan, const float2 *__restrict__ twN2,
+                                                  const float2 *__restrict__ twHalf,
+                                                  float2 *__restrict__ X, int F_shift, int C,
+                                                  int rpw_shift)
+{
+    extern __shared__ float2 lds[];
+    const int RPW = 1 << rpw_shift;
+    const int S = N2 + 1;
+    const int row0 = blockIdx.x * RPW;
+    const bool vec2 = ((ncols & 1) == 0) && ((in_stride & 1) == 0);
+    for (int s = 0; s < RPW; ++s) {
+        const int row = row0 + s;
+        const float *src = in + (int64_t)row * in_stride;
+        for (int n = threadIdx.x; n < N2; n += blockDim.x) {
+            const int t = 2 * n;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (row < nrows) {
+                if (vec2) {
+                    if (t < ncols)
+                        v = *(const float2 *)(src + t);
+                } else {
+                    if (t < ncols)
+                        v.x = src[t];
+                    if (t + 1 < ncols)
+                        v.y = src[t + 1];
+                }
+            }
+            lds[s * S + n] = v;
+        }
+    }
+    __syncthreads();
+    fft_lds(lds, plan, rpw_shift, S, 1, twN2);
+    const int half = N2 / 2;
+    for (int s = 0; s < RPW; ++s) {
+        float2 *b = lds + s * S;
+        for (int k = threadIdx.x; k <= half; k += blockDim.x) {
+            const int kn = (k == 0) ? 0 : N2 - k;
+            const float2 Zk = b[k], Zn = b[kn];
+            const float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
+            const float2 D = make_float2(0.5f * (Zk.x - Zn.x), 0.5f * (Zk.y + Zn.y));
+            const float2 wD = cmul(twHalf[k], D);
+            b[k] = csub(E, mul_pi(wD));
+            b[(k == 0) ? N2 : kn] = conjf2(cadd(E, mul_pi(wD)));
+        }
+    }
+    __syncthreads();
+    const int F = 1 << F_shift;
+    const int total = C << (F_shift + rpw_shift);
+    for (int g = threadIdx.x; g < total; g += blockDim.x) {
+        const int f = g & (F - 1);
+        const int s = (g >> F_shift) & (RPW - 1);
+        const int c = g >> (F_shift + rpw_shift);
+        const int k = (c << F_shift) + f;
+        const int row = row0 + s;
+        if (row < nrows)
+            X[(((int64_t)c * nrows + row) << F_shift) + f] =
+                (k <= N2) ? lds[s * S + k] : make_float2(0.0f, 0.0f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass C: tick-axis inverse real FFT of rows, cropped to ncols ticks.
+// Z_k = A_k + i conj(w^k) B_k with A_k = X_k + conj X_{N2-k},
+// B_k = X_k - conj X_{N2-k}; the unnormalised inverse FFT_N2 of Z gives
+// z_n = x_{2n} + i x_{2n+1}.  The inverse runs as a forward transform of
+// conj(Z) (conj of the result).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_rows_c2r(const float2 *__restrict__ Y, int nrows,
+                                                  int N2, FftPlan plan,
+                                                  const float2 *__restrict__ twN2,
+                                                  const float2 *__restrict__ twHalf,
+                                                  float *__restrict__ out, int ncols,
+                                                  int64_t out_stride, int F_shift, int C,
+                                                  int rpw_shift)
+{
+    extern __shared__ float2 lds[];
+    const int RPW = 1 << rpw_shift;
+    const int S = N2 + 1;
+    const int row0 = blockIdx.x * RPW;
+    const int F = 1 << F_shift;
+    const int total = C << (F_shift + rpw_shift);
+    for (int g = threadIdx.x; g < total; g += blockDim.x) {
+        const int f = g & (F - 1);
+        const int s = (g >> F_shift) & (RPW - 1);
+        const int c = g >> (F_shift + rpw_shift);
+        const int k = (c << F_shift) + f;
+        const int row = row0 + s;
+        if (k <= N2)
+            lds[s * S + k] = (row < nrows) ? Y[(((int64_t)c * nrows + row) << F_shift) + f]
+                                           : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+    const int half = N2 / 2;
+    for (int s = 0; s < RPW; ++s) {
+        float2 *b = lds + s * S;
+        for (int k = threadIdx.x; k <= half; k += blockDim.x) {
+            const int kn = (k == 0) ? N2 : N2 - k;
+            const float2 Xk = b[k], Xn = b[kn];
+            const float2 A = make_float2(Xk.x + Xn.x, Xk.y - Xn.y);
+            const float2 B = make_float2(Xk.x - Xn.x, Xk.y + Xn.y);
+            const float2 wB = cmul(conjf2(twHalf[k]), B);
+            b[k] = conjf2(cadd(A, mul_pi(wB)));
+            if (k != 0)
+                b[kn] = csub(A, mul_pi(wB));  // conj of conj(A - i conj(w) B)
+        }
+    }
+    __syncthreads();
+    fft_lds(lds, plan, rpw_shift, S, 1, twN2);
+    const bool vec2 = ((ncols & 1) == 0) && ((out_stride & 1) == 0);
+    for (int s = 0; s < RPW; ++s) {
+        const int row = row0 + s;
+        if (row >= nrows)
+            break;
+        float *dst = out + (int64_t)row * out_stride;
+        const float2 *b = lds + s * S;
+        for (int n = threadIdx.x; n < N2; n += blockDim.x) {
+            const int t = 2 * n;
+            if (t >= ncols)
+                continue;
+            const float2 z = b[n];
+            if (vec2) {
+                *(float2 *)(dst + t) = make_float2(z.x, -z.y);
+            } else {
+                dst[t] = z.x;
+                if (t + 1 < ncols)
+                    dst[t + 1] = -z.y;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B: pitch-axis overlap-save convolution of one frequency chunk.
+//   mode 0: output every pitch row; mode 1: only row w*nimpact + nimpact/2 of
+//   each wire (output row w); mode 2: response spectrum (forward transform of
+//   rows 0..nrows_in-1 zero-padded to L, scaled, written as [c][L][F]).
+// Workgroups are mapped XCD-major: workgroup b runs on XCD b mod 8, and the
+// workgroups of one XCD walk the pitch blocks of one chunk before the next, so
+// the chunk's response spectrum and the rows shared by neighbouring blocks are
+// re-read from that XCD's L2.
+// ---------------------------------------------------------------------------
+__global__ void k_pitch_conv(const float2 *__restrict__ X, int nrows_in,
+                             const float2 *__restrict__ K, float2 *__restrict__ Y,
+                             int nrows_out, int L, int V, int Rp, int r0, int nblocks, int C,
+                             int F_shift, FftPlan plan, const float2 *__restrict__ twL, int mode,
+                             int nimpact, float scale)
+{
+    extern __shared__ float2 lds[];
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int lc = slot / nblocks, blk = slot - lc * nblocks;
+    const int c = lc * 8 + xcd;
+    if (c >= C)
+        return;
+    const int F = 1 << F_shift;
+    const int LF = L << F_shift;
+    const int P0 = blk * V;
+    const int in0 = (mode == 2) ? 0 : P0 + r0 - (Rp - 1);
+    const float2 *src = X + ((int64_t)c * nrows_in << F_shift);
+    for (int g = threadIdx.x; g < LF; g += blockDim.x) {
+        const int row = in0 + (g >> F_shift);
+        lds[g] = (row >= 0 && row < nrows_in) ? src[((int64_t)row << F_shift) + (g & (F - 1))]
+                                              : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+    fft_lds(lds, plan, F_shift, 1, F, twL);
+    if (mode == 2) {
+        float2 *dst = Y + (int64_t)c * LF;
+        for (int g = threadIdx.x; g < LF; g += blockDim.x)
+            dst[g] = cscale(lds[g], scale);
+        return;
+    }
+    const float2 *Kc = K + (int64_t)c * LF;
+    for (int g = threadIdx.x; g < LF; g += blockDim.x)
+        lds[g] = conjf2(cmul(lds[g], Kc[g]));
+    __syncthreads();
+    fft_lds(lds, plan, F_shift, 1, F, twL);
+    float2 *dst = Y + ((int64_t)c * nrows_out << F_shift);
+    const int first = (Rp - 1) << F_shift;
+    for (int g = first + threadIdx.x; g < LF; g += blockDim.x) {
+        const int p = P0 + (g >> F_shift) - (Rp - 1);
+        if (p >= nrows_in)
+            break;
+        int o = p;
+        if (mode == 1) {
+            if (p % nimpact != nimpact / 2)
+                continue;
+            o = p / nimpact;
+        }
+        dst[((int64_t)o << F_shift) + (g & (F - 1))] = conjf2(lds[g]);
+    }
+}
+
+int ilog2(int v)
+{
+    int s = 0;
+    while ((1 << s) < v)
+        ++s;
+    return s;
+}
+
+// Threads for a transform of `nseq` sequences of length n so that every pass
+// stages at most kRegComplex values per thread.
+int threads_for(const FftPlan &plan, int nseq)
+{
+    int need = 64;
+    for (int q = 0; q < plan.npass; ++q) {
+        const int R = plan.radix[q];
+        const int total = plan.n / R * nseq;
+        const int maxb = kRegComplex / R;
+        const int t = (total + maxb - 1) / maxb;
+        need = std::max(need, t);
+    }
+    int threads = 64;
+    while (threads < need)
+        threads *= 2;
+    return threads;
+}
+
+constexpr int kRowsPerBlock = 2;  // rows per workgroup in passes A and C (power of two)
+
+hipError_t rows_r2c(const wcsim_plane *pl, const float *in, int nrows, int ncols,
+                    int64_t in_stride, float2 *X, hipStream_t s)
+{
+    const int rpw_shift = ilog2(kRowsPerBlock);
+    const int threads = std::min(1024, std::max(256, threads_for(pl->planT, kRowsPerBlock)));
+    const size_t lds = sizeof(float2) * (size_t)(pl->N2 + 1) * kRowsPerBlock;
+    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL(k_rows_r2c, dim3(blocks), dim3(threads), lds, s, in, nrows, ncols,
+                       in_stride, pl->N2, pl->planT, pl->twT, pl->twHalf, X, ilog2(pl->F), pl->C,
+                       rpw_shift);
+    return hipGetLastError();
+}
+
+hipError_t rows_c2r(const wcsim_plane *pl, const float2 *Y, int nrows, float *out, int ncols,
+                    int64_t out_stride, hipStream_t s)
+{
+    const int rpw_shift = ilog2(kRowsPerBlock);
+    const int threads = std::min(1024, std::max(256, threads_for(pl->planT, kRowsPerBlock)));
+    const size_t lds = sizeof(float2) * (size_t)(pl->N2 + 1) * kRowsPerBlock;
+    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL(k_rows_c2r, dim3(blocks), dim3(threads), lds, s, Y, nrows, pl->N2,
+                       pl->planT, pl->twT, pl->twHalf, out, ncols, out_stride, ilog2(pl->F), pl->C,
+                       rpw_shift);
+    return hipGetLastError();
+}
+
+hipError_t pitch_pass(const wcsim_plane *pl, const float2 *X, int nrows_in, const float2 *K,
+                      float2 *Y, int nrows_out, int nblocks, int mode, float scale, hipStream_t s)
+{
+    const int F_shift = ilog2(pl->F);
+    const int threads = std::min(1024, std::max(256, threads_for(pl->planL, pl->F)));
+    const size_t lds = sizeof(float2) * (size_t)pl->L * pl->F;
+    const int xcd_chunks = (pl->C + 7) / 8;
+    const unsigned blocks = (unsigned)(8 * xcd_chunks * nblocks);
+    hipLaunchKernelGGL(k_pitch_conv, dim3(blocks), dim3(threads), lds, s, X, nrows_in, K, Y,
+                       nrows_out, pl->L, pl->V, pl->Rp, pl->r0, nblocks, pl->C, F_shift,
+                       pl->planL, pl->twL, mode, (int)pl->kp.nimpact, scale);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+bool make_plan(int n, FftPlan *plan)
+{
+    plan->n = n;
+    plan->npass = 0;
+    if (n < 2)
+        return false;
+    int m = n;
+    const int order[] = {8, 4, 2, 5, 3};
+    for (int r : order) {
+        while (m % r == 0) {
+            if (plan->npass >= kMaxPass)
+                return false;
+            plan->radix[plan->npass++] = r;
+            m /= r;
+        }
+    }
+    return m == 1;
+}
+
+int smallest_smooth_even(int nmin)
+{
+    int n = std::max(4, nmin + (nmin & 1));
+    for (;; n += 2) {
+        FftPlan p;
+        if (make_plan(n / 2, &p))
+            return n;
+    }
+}
+
+size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind)
+{
+    const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
+    return align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)pl->Np) +
+           align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)nout);
+}
+
+hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
+                           wcsim_out out_kind, void *work, hipStream_t s)
+{
+    const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
+    float2 *X = (float2 *)work;
+    float2 *Y = (float2 *)((char *)work +
+                           align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)pl->Np));
+    hipError_t e;
+    if ((e = rows_r2c(pl, grid, (int)pl->Np, (int)pl->Nt, pl->Nt, X, s)) != hipSuccess)
+        return e;
+    if ((e = pitch_pass(pl, X, (int)pl->Np, pl->K, Y, (int)nout, pl->nblocks,
+                        out_kind == WCSIM_OUT_WIRE ? 1 : 0, 1.0f, s)) != hipSuccess)
+        return e;
+    return rows_c2r(pl, Y, (int)nout, out, (int)pl->Nt, pl->Nt, s);
+}
+
+size_t response_work_bytes(const wcsim_plane *pl)
+{
+    return align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)pl->Rp);
+}
+
+// Response spectrum K[c][l][f] = sum_{i<Rp} sum_{s<Rt} R[i][s]
+//   exp(-2 pi i (l i / L + k s / N')) / (L N'), k = c F + f.
+hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void *work,
+                                   hipStream_t s)
+{
+    float2 *XR = (float2 *)work;
+    hipError_t e;
+    if ((e = rows_r2c(pl, resp_dev, pl->Rp, pl->Rt, pl->Rt, XR, s)) != hipSuccess)
+        return e;
+    const float scale = (float)(1.0 / ((double)pl->L * (double)pl->Nfft));
+    return pitch_pass(pl, XR, pl->Rp, nullptr, pl->K, pl->L, 1, 2, scale, s);
+}
+
+}  // namespace wcs

@@ -1,0 +1,805 @@
+// Rasterization and Scatter-Add on gfx950 (arXiv:2304.01841, Sec. 2 steps 1-2).
+//
+// Per depo (FP64): drift to the response plane, Gaussian widths sqrt(2 D T),
+// continuous bin coordinates and the inclusive window floor(mu -/+ n s) on each
+// axis.  Bin weights are differences of erf at the bin edges normalised over
+// the window (FP64); the patch is the outer product of the two weight vectors
+// times the charge (FP32).  With fluctuation, every bin draws a normal deviate
+// from a Philox4x32-10 stream keyed by (event, depo, absolute bin) and takes
+// the normal approximation of a binomial draw, clamped at zero, and the patch
+// is rescaled to the depo charge.
+//
+// Scatter-Add (Sec. 2 step 2) runs two ways:
+//  * fused (simulate path): depos are binned by the grid tile holding their
+//    window origin (count -> exclusive scan -> fill, the scan of Sec. 4.3);
+//    one workgroup per tile rasterizes its depos, one wavefront per patch, into
+//    an LDS copy of the tile plus a halo, then flushes the non-zero LDS cells
+//    to HBM with float atomics, so the grid sees one atomic per touched cell
+//    per tile instead of one per patch bin;
+//  * unfused (patch-set API): patches are written to a flat buffer at the
+//    scanned offsets and a second kernel adds them to the grid atomically.
+#include <math.h>
+
+#include "wcsim_internal.h"
+
+namespace wcs {
+namespace {
+
+constexpr double kSqrt2 = 1.41421356237309504880;  // sqrt(2), correctly rounded
+
+// Philox4x32-10 round constants (Salmon et al., SC'11).
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint64_t a = (uint64_t)kPhiloxM0 * c.x;
+        const uint64_t b = (uint64_t)kPhiloxM1 * c.z;
+        c = make_uint4((uint32_t)(b >> 32) ^ c.y ^ k0, (uint32_t)b, (uint32_t)(a >> 32) ^ c.w ^ k1,
+                       (uint32_t)a);
+    }
+    return c;
+}
+
+// Uniform ((r >> 9) + 1/2) 2^-23 in (0, 1), exact in binary32.
+__device__ __forceinline__ float word_to_uniform(uint32_t r)
+{
+    return ((float)(r >> 9) + 0.5f) * 0x1p-23f;
+}
+
+// Box-Muller pair: cosine branch (even tick) and sine branch (odd tick).
+// v_sin/v_cos take their argument in revolutions, so theta = 2 pi u is u.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &zc, float &zs)
+{
+    const float rho = sqrtf(-2.0f * __logf(word_to_uniform(a)));
+    const float u = word_to_uniform(b);
+    zc = rho * __builtin_amdgcn_cosf(u);
+    zs = rho * __builtin_amdgcn_sinf(u);
+}
+
+struct Win {
+    double mu_p, s_p, mu_t, s_t, q;
+    int lo_p, lo_t, n_p, n_t;
+    int status;  // 0 ok, 1 invalid, 2 misses the grid, 3 window too long
+};
+
+// Drift, diffusion and window of one depo.  FP64 with no contraction, in the
+// order the definitions are written, so that the integer window bounds are
+// reproducible bit for bit.
+__device__ __forceinline__ Win depo_window(const wcsim_depo &dep, const PlaneParams &P)
+{
+#pragma clang fp contract(off)
+    Win w;
+    w.status = 0;
+    w.lo_p = w.lo_t = w.n_p = w.n_t = 0;
+    const double x = dep.x, y = dep.y, z = dep.z, t = dep.t, q = dep.q;
+    w.q = q;
+    w.mu_p = w.s_p = w.mu_t = w.s_t = 0.0;
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(t) || !isfinite(q) || q < 0.0 ||
+        x < P.plane_x) {
+        w.status = 1;
+        return w;
+    }
+    const double L = x - P.plane_x;
+    const double T = L / P.v;
+    const double t_arr = t + T;
+    const double sigma_p = sqrt(2.0 * P.DT * T);
+    const double sigma_t = sqrt(2.0 * P.DL * T) / P.v;
+    const double proj = y * P.dir_y + z * P.dir_z;
+    w.mu_p = (proj - P.pitch_origin) / P.dp;
+    w.s_p = sigma_p / P.dp;
+    w.mu_t = (t_arr - P.t0) / P.tick;
+    w.s_t = sigma_t / P.tick;
+    const double lo_p = floor(w.mu_p - P.nsigma * w.s_p);
+    const double hi_p = floor(w.mu_p + P.nsigma * w.s_p);
+    const double lo_t = floor(w.mu_t - P.nsigma * w.s_t);
+    const double hi_t = floor(w.mu_t + P.nsigma * w.s_t);
+    if (hi_p < 0.0 || lo_p >= (double)P.Np || hi_t < 0.0 || lo_t >= (double)P.Nt) {
+        w.status = 2;
+        return w;
+    }
+    if (hi_p - lo_p + 1.0 > (double)kMaxWindow || hi_t - lo_t + 1.0 > (double)kMaxWindow) {
+        w.status = 3;
+        return w;
+    }
+    w.lo_p = (int)lo_p;
+    w.lo_t = (int)lo_t;
+    w.n_p = (int)hi_p - w.lo_p + 1;
+    w.n_t = (int)hi_t - w.lo_t + 1;
+    return w;
+}
+
+__device__ __forceinline__ double edge_erf(int lo, int k, double mu, double s)
+{
+    return erf(((double)(lo + k) - mu) / (kSqrt2 * s));
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int WIDTH>
+__device__ __forceinline__ double seg_sum(double v)
+{
+#pragma unroll
+    for (int m = WIDTH / 2; m > 0; m >>= 1)
+        v += __shfl_xor(v, m, WIDTH);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1)
+        v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Weights of one axis from `WIDTH` lanes: lane k holds edge k (n <= WIDTH - 1).
+template <int WIDTH>
+__device__ __forceinline__ void lane_axis_weights(int lo, int n, double mu, double s, int k,
+                                                  float *W)
+{
+    const double E = (k <= n && s > 0.0) ? edge_erf(lo, k, mu, s) : 0.0;
+    const double En = __shfl_down(E, 1, WIDTH);
+    const double wk = (k < n) ? 0.5 * (En - E) : 0.0;
+    const double sum = seg_sum<WIDTH>(wk);
+    if (k < n)
+        W[k] = (s > 0.0) ? (float)(wk / sum) : (k == 0 ? 1.0f : 0.0f);
+}
+
+// Both axes' weights of a patch with windows shorter than 64 bins, into the
+// wave's LDS arrays.  Windows shorter than 32 bins share one erf per lane
+// (pitch edges on lanes 0-31, tick edges on lanes 32-63).
+__device__ __forceinline__ void wave_weights(const Win &w, float *Wp, float *Wt, int lane)
+{
+    if (w.n_p < 32 && w.n_t < 32) {
+        const bool tax = lane >= 32;
+        lane_axis_weights<32>(tax ? w.lo_t : w.lo_p, tax ? w.n_t : w.n_p, tax ? w.mu_t : w.mu_p,
+                              tax ? w.s_t : w.s_p, lane & 31, tax ? Wt : Wp);
+    } else {
+        lane_axis_weights<64>(w.lo_p, w.n_p, w.mu_p, w.s_p, lane, Wp);
+        lane_axis_weights<64>(w.lo_t, w.n_t, w.mu_t, w.s_t, lane, Wt);
+    }
+    wave_lds_sync();
+}
+
+// Fluctuated bin value before rescaling: normal approximation of the binomial
+// draw of q electrons with probability p, clamped at zero.
+__device__ __forceinline__ float fluct_value(float q, float p, float z)
+{
+    const float qp = q * p;
+    return fmaxf(0.0f, qp + z * sqrtf(qp * (1.0f - p)));
+}
+
+__device__ __forceinline__ int quad_of(int J) { return J >> 2; }  // floor(J / 4)
+
+// ---------------------------------------------------------------------------
+// Fill and Philox diagnostic kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_zero16(uint4 *p, size_t n16)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_fill_zero1(unsigned char *p, size_t n)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+__global__ void k_philox(const uint4 *ctr, const uint2 *key, int64_t n, uint4 *out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = philox4x32_10(ctr[i], key[i].x, key[i].y);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan (three phases: block sums, scan of block sums, add)
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256, kScanPer = 4, kScanBlock = kScanThreads * kScanPer;
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *sh, T *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += u;
+    }
+    if (lane == 63)
+        sh[wave] = inc;
+    __syncthreads();
+    T base = 0, tot = 0;
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        if (k < wave)
+            base += sh[k];
+        tot += sh[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(T *data, int64_t n, T *block_sums)
+{
+    __shared__ T sh[kScanThreads / 64];
+    const int64_t base = blockIdx.x * (int64_t)kScanBlock + threadIdx.x * kScanPer;
+    T v[kScanPer];
+    T sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = (base + k < n) ? data[base + k] : T(0);
+        sum += v[k];
+    }
+    T total;
+    T run = block_exclusive_scan<T>(sum, sh, &total);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n)
+            data[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0)
+        block_sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(T *sums, int64_t nb)
+{
+    __shared__ T sh[kScanThreads / 64];
+    T carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        const int64_t i = b0 + threadIdx.x;
+        T v = (i < nb) ? sums[i] : T(0);
+        T total;
+        T ex = block_exclusive_scan<T>(v, sh, &total);
+        if (i < nb)
+            sums[i] = ex + carry;
+        carry += total;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(T *data, int64_t n, const T *sums)
+{
+    const int64_t base = blockIdx.x * (int64_t)kScanBlock + threadIdx.x * kScanPer;
+    const T add = sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n)
+            data[base + k] += add;
+}
+
+template <typename T>
+hipError_t exclusive_scan(T *data, int64_t n, void *scratch, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    T *sums = (T *)scratch;
+    hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, sums);
+    hipLaunchKernelGGL(k_scan_sums<T>, dim3(1), dim3(kScanThreads), 0, s, sums, nb);
+    hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, sums);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Unfused path: patch sizes, flat patch values, flat scatter
+// ---------------------------------------------------------------------------
+__global__ void k_patch_sizes(const wcsim_depo *depos, int64_t n, PlaneParams P, int32_t *meta,
+                              int64_t *sizes)
+{
+    const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (d == 0)
+        sizes[n] = 0;
+    if (d >= n)
+        return;
+    const Win w = depo_window(depos[d], P);
+    const bool ok = (w.status == 0);
+    meta[4 * d + 0] = ok ? w.lo_p : 0;
+    meta[4 * d + 1] = ok ? w.lo_t : 0;
+    meta[4 * d + 2] = ok ? w.n_p : 0;
+    meta[4 * d + 3] = ok ? w.n_t : 0;
+    sizes[d] = ok ? (int64_t)w.n_p * w.n_t : 0;
+}
+
+template <int NT>
+__device__ double block_sum_d(double v, double *red)
+{
+    v = seg_sum<64>(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k)
+        s += red[k];
+    return s;
+}
+
+// Window weights of one axis by a whole workgroup (any window up to
+// kMaxWindow bins): erf at every edge into LDS, then differences and the sum.
+template <int NT>
+__device__ void block_axis_weights(int lo, int n, double mu, double s, float *W, double *E,
+                                   double *red)
+{
+    for (int k = threadIdx.x; k <= n; k += NT)
+        E[k] = (s > 0.0) ? edge_erf(lo, k, mu, s) : 0.0;
+    __syncthreads();
+    double part = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT)
+        part += 0.5 * (E[i + 1] - E[i]);
+    const double sum = block_sum_d<NT>(part, red);
+    for (int i = threadIdx.x; i < n; i += NT)
+        W[i] = (s > 0.0) ? (float)((0.5 * (E[i + 1] - E[i])) / sum) : (i == 0 ? 1.0f : 0.0f);
+    __syncthreads();
+}
+
+// One workgroup per depo, any window size.  FLAT: write the patch at its
+// offset in the flat value buffer.  Otherwise add it to the grid with float
+// atomics (used for the few depos whose patch does not fit the LDS tiles).
+// With fluctuation the rescaling needs the patch total before any value is
+// final: FLAT stores the clamped draws and rescales them in place; the grid
+// variant draws twice (same counters, same numbers).
+template <int NT, bool FLAT>
+__global__ __launch_bounds__(NT) void k_patch_generic(const wcsim_depo *depos,
+                                                      const int32_t *index_list,
+                                                      const int32_t *list_count, int64_t n_direct,
+                                                      PlaneParams P, uint32_t event,
+                                                      const int64_t *offsets, float *values,
+                                                      float *grid)
+{
+    __shared__ float Wp[kMaxWindow], Wt[kMaxWindow];
+    __shared__ double E[kMaxWindow + 1];
+    __shared__ double red[NT / 64];
+    const int64_t count = index_list ? (int64_t)*list_count : n_direct;
+    for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
+        const int d = index_list ? index_list[k] : (int)k;
+        const Win w = depo_window(depos[d], P);
+        if (w.status != 0)
+            continue;
+        block_axis_weights<NT>(w.lo_p, w.n_p, w.mu_p, w.s_p, Wp, E, red);
+        block_axis_weights<NT>(w.lo_t, w.n_t, w.mu_t, w.s_t, Wt, E, red);
+        const float qf = (float)w.q;
+        float *out = FLAT ? values + offsets[d] : nullptr;
+        if (!P.fluct) {
+            const int cnt = w.n_p * w.n_t;
+            for (int it = threadIdx.x; it < cnt; it += NT) {
+                const int i = it / w.n_t, j = it - i * w.n_t;
+                const float v = qf * Wp[i] * Wt[j];
+                if (FLAT) {
+                    out[it] = v;
+                } else {
+                    const int I = w.lo_p + i, J = w.lo_t + j;
+                    if ((unsigned)I < (unsigned)P.Np && (unsigned)J < (unsigned)P.Nt)
+                        unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v);
+                }
+            }
+        } else {
+            const int qlo = quad_of(w.lo_t), nq = quad_of(w.lo_t + w.n_t - 1) - qlo + 1;
+            const int items = w.n_p * nq;
+            float S = 0.0f;
+            for (int it = threadIdx.x; it < items; it += NT) {
+                const int i = it / nq, qd = qlo + (it - i * nq);
+                const uint4 r = philox4x32_10(
+                    make_uint4((uint32_t)qd, (uint32_t)(w.lo_p + i), (uint32_t)d, event), P.key0,
+                    P.key1);
+                float z[4];
+                box_muller(r.x, r.y, z[0], z[1]);
+                box_muller(r.z, r.w, z[2], z[3]);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int j = 4 * qd + m - w.lo_t;
+                    if (j >= 0 && j < w.n_t) {
+                        const float F = fluct_value(qf, Wp[i] * Wt[j], z[m]);
+                        S += F;
+                        if (FLAT)
+                            out[i * w.n_t + j] = F;
+                    }
+                }
+            }
+            S = (float)block_sum_d<NT>((double)S, red);
+            const float scale = (S > 0.0f) ? qf / S : 0.0f;
+            for (int it = threadIdx.x; it < items; it += NT) {
+                const int i = it / nq, qd = qlo + (it - i * nq);
+                float z[4];
+                if (!FLAT) {
+                    const uint4 r = philox4x32_10(
+                        make_uint4((uint32_t)qd, (uint32_t)(w.lo_p + i), (uint32_t)d, event),
+                        P.key0, P.key1);
+                    box_muller(r.x, r.y, z[0], z[1]);
+                    box_muller(r.z, r.w, z[2], z[3]);
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int j = 4 * qd + m - w.lo_t;
+                    if (j >= 0 && j < w.n_t) {
+                        const float p = Wp[i] * Wt[j];
+                        if (FLAT) {
+                            float &o = out[i * w.n_t + j];
+                            o = (S > 0.0f) ? o * scale : qf * p;
+                        } else {
+                            const int I = w.lo_p + i, J = w.lo_t + j;
+                            if ((unsigned)I < (unsigned)P.Np && (unsigned)J < (unsigned)P.Nt) {
+                                const float v =
+                                    (S > 0.0f) ? fluct_value(qf, p, z[m]) * scale : qf * p;
+                                unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Flat patch set -> grid.  One wavefront per patch.
+__global__ __launch_bounds__(256) void k_scatter_flat(int64_t n, const int32_t *meta,
+                                                      const int64_t *offsets, const float *values,
+                                                      float *grid, int Np, int Nt)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t d = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    if (d >= n)
+        return;
+    const int lo_p = meta[4 * d], lo_t = meta[4 * d + 1], n_p = meta[4 * d + 2],
+              n_t = meta[4 * d + 3];
+    const float *v = values + offsets[d];
+    const int cnt = n_p * n_t;
+    for (int it = lane; it < cnt; it += 64) {
+        const int i = it / n_t, j = it - i * n_t;
+        const int I = lo_p + i, J = lo_t + j;
+        if ((unsigned)I < (unsigned)Np && (unsigned)J < (unsigned)Nt)
+            unsafeAtomicAdd(grid + (size_t)I * Nt + J, v[it]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused path: tile binning and LDS-staged rasterization
+// ---------------------------------------------------------------------------
+constexpr int kHaloP = 32, kHaloT = 16;  // patches up to 33 x 17 bins fit a tile region
+constexpr int kFastMax = 63;             // window limit of the one-wave-per-patch path
+constexpr int kFluctItems = 4;           // Philox calls per lane held in registers
+
+struct TileGeom {
+    int tp, tt, rp, rt, ntt;
+};
+
+__device__ __forceinline__ bool fits_tile(const Win &w, int p0, int t0, const TileGeom &g,
+                                          const PlaneParams &P)
+{
+    if (w.n_p > kFastMax || w.n_t > kFastMax)
+        return false;
+    if (min(w.lo_p + w.n_p, P.Np) > p0 + g.rp || min(w.lo_t + w.n_t, P.Nt) > t0 + g.rt)
+        return false;
+    if (P.fluct) {
+        const int nq = quad_of(w.lo_t + w.n_t - 1) - quad_of(w.lo_t) + 1;
+        if (w.n_p * nq > 64 * kFluctItems)
+            return false;
+    }
+    return true;
+}
+
+__global__ void k_prep_bin(const wcsim_depo *depos, int64_t n, PlaneParams P, TileGeom g,
+                           int32_t *counters, int32_t *tile_count, int32_t *depo_tile,
+                           int32_t *depo_slot, int32_t *large)
+{
+    const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (d >= n)
+        return;
+    const Win w = depo_window(depos[d], P);
+    int tile = -1, slot = 0;
+    if (w.status == 1 || w.status == 3) {
+        atomicAdd(&counters[0], 1);
+    } else if (w.status == 0) {
+        const int tp = min(max(w.lo_p, 0), P.Np - 1) / g.tp;
+        const int tt = min(max(w.lo_t, 0), P.Nt - 1) / g.tt;
+        if (fits_tile(w, tp * g.tp, tt * g.tt, g, P)) {
+            tile = tp * g.ntt + tt;
+            slot = atomicAdd(&tile_count[tile], 1);
+        } else {
+            large[atomicAdd(&counters[1], 1)] = (int32_t)d;
+        }
+    }
+    depo_tile[d] = tile;
+    depo_slot[d] = slot;
+}
+
+__global__ void k_fill_list(int64_t n, const int32_t *depo_tile, const int32_t *depo_slot,
+                            const int32_t *tile_off, int32_t *list)
+{
+    const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (d >= n)
+        return;
+    const int t = depo_tile[d];
+    if (t >= 0)
+        list[tile_off[t] + depo_slot[d]] = (int32_t)d;
+}
+
+template <int TP, int TT>
+__global__ __launch_bounds__(256) void k_raster_tiles(const wcsim_depo *depos,
+                                                      const int32_t *tile_off,
+                                                      const int32_t *list, PlaneParams P,
+                                                      uint32_t event, int ntt, float *grid)
+{
+    constexpr int RP = TP + kHaloP, RT = TT + kHaloT, NW = 4;
+    __shared__ float acc[RP * RT];
+    __shared__ float Wsh[NW][2][64];
+    const int tile = blockIdx.x;
+    const int beg = tile_off[tile], end = tile_off[tile + 1];
+    if (beg == end)
+        return;
+    for (int c = threadIdx.x; c < RP * RT; c += 256)
+        acc[c] = 0.0f;
+    __syncthreads();
+    const int p0 = (tile / ntt) * TP, t0 = (tile % ntt) * TT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float *Wp = Wsh[wave][0], *Wt = Wsh[wave][1];
+
+    for (int k = beg + wave; k < end; k += NW) {
+        const int d = list[k];
+        const Win w = depo_window(depos[d], P);
+        wave_weights(w, Wp, Wt, lane);
+        const float qf = (float)w.q;
+        if (!P.fluct) {
+            const int cnt = w.n_p * w.n_t;
+            for (int it = lane; it < cnt; it += 64) {
+                const int i = it / w.n_t, j = it - i * w.n_t;
+                const int I = w.lo_p + i, J = w.lo_t + j;
+                if ((unsigned)I < (unsigned)P.Np && (unsigned)J < (unsigned)P.Nt)
+                    atomicAdd(&acc[(I - p0) * RT + (J - t0)], qf * Wp[i] * Wt[j]);
+            }
+        } else {
+            const int qlo = quad_of(w.lo_t), nq = quad_of(w.lo_t + w.n_t - 1) - qlo + 1;
+            const int items = w.n_p * nq;
+            float F[kFluctItems][4];
+            float S = 0.0f;
+#pragma unroll
+            for (int b = 0; b < kFluctItems; ++b) {
+                const int it = lane + 64 * b;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    F[b][m] = 0.0f;
+                if (it < items) {
+                    const int i = it / nq, qd = qlo + (it - i * nq);
+                    const uint4 r = philox4x32_10(
+                        make_uint4((uint32_t)qd, (uint32_t)(w.lo_p + i), (uint32_t)d, event),
+                        P.key0, P.key1);
+                    float z[4];
+                    box_muller(r.x, r.y, z[0], z[1]);
+                    box_muller(r.z, r.w, z[2], z[3]);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int j = 4 * qd + m - w.lo_t;
+                        if (j >= 0 && j < w.n_t) {
+                            F[b][m] = fluct_value(qf, Wp[i] * Wt[j], z[m]);
+                            S += F[b][m];
+                        }
+                    }
+                }
+            }
+            S = wave_sum(S);
+            const float scale = (S > 0.0f) ? qf / S : 0.0f;
+#pragma unroll
+            for (int b = 0; b < kFluctItems; ++b) {
+                const int it = lane + 64 * b;
+                if (it < items) {
+                    const int i = it / nq, qd = qlo + (it - i * nq);
+                    const int I = w.lo_p + i;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int J = 4 * qd + m, j = J - w.lo_t;
+                        if (j >= 0 && j < w.n_t && (unsigned)I < (unsigned)P.Np &&
+                            (unsigned)J < (unsigned)P.Nt) {
+                            const float v = (S > 0.0f) ? F[b][m] * scale : qf * Wp[i] * Wt[j];
+                            atomicAdd(&acc[(I - p0) * RT + (J - t0)], v);
+                        }
+                    }
+                }
+            }
+        }
+        wave_lds_sync();  // weights are rewritten by the next patch
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < RP * RT; c += 256) {
+        const float v = acc[c];
+        if (v != 0.0f) {
+            const int I = p0 + c / RT, J = t0 + c % RT;
+            if (I < P.Np && J < P.Nt)
+                unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v);
+        }
+    }
+}
+
+unsigned blocks_for(int64_t n, int threads)
+{
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+TileShape tile_shape(int id)
+{
+    switch (id) {
+    case 1:
+        return {64, 128, kHaloP, kHaloT};
+    case 2:
+        return {32, 128, kHaloP, kHaloT};
+    default:
+        return {64, 64, kHaloP, kHaloT};
+    }
+}
+
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0)
+        return hipSuccess;
+    const size_t n16 = bytes / 16;
+    if (n16) {
+        const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_fill_zero16, dim3(blocks), dim3(256), 0, s, (uint4 *)ptr, n16);
+    }
+    const size_t rem = bytes - n16 * 16;
+    if (rem)
+        hipLaunchKernelGGL(k_fill_zero1, dim3(1), dim3(16), 0, s, (unsigned char *)ptr + n16 * 16,
+                           rem);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
+                         hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const uint4 *)ctr,
+                       (const uint2 *)key, n, (uint4 *)out);
+    return hipGetLastError();
+}
+
+size_t scan_scratch_bytes(int64_t n)
+{
+    return align_up(sizeof(int64_t) * (size_t)((n + kScanBlock - 1) / kScanBlock + 1));
+}
+
+hipError_t launch_exclusive_scan_i64(int64_t *data, int64_t n, void *scratch, hipStream_t s)
+{
+    return exclusive_scan<int64_t>(data, n, scratch, s);
+}
+
+hipError_t launch_exclusive_scan_i32(int32_t *data, int64_t n, void *scratch, hipStream_t s)
+{
+    return exclusive_scan<int32_t>(data, n, scratch, s);
+}
+
+hipError_t launch_patch_sizes(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                              int32_t *meta, int64_t *sizes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_patch_sizes, dim3(blocks_for(std::max<int64_t>(n, 1), 256)), dim3(256), 0,
+                       s, depos, n, pl->kp, meta, sizes);
+    return hipGetLastError();
+}
+
+hipError_t launch_patch_values(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                               uint64_t event_id, const int32_t *meta, const int64_t *offsets,
+                               float *values, hipStream_t s)
+{
+    (void)meta;
+    if (n <= 0)
+        return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
+    hipLaunchKernelGGL((k_patch_generic<64, true>), dim3(grid), dim3(64), 0, s, depos, nullptr,
+                       nullptr, n, pl->kp, (uint32_t)event_id, offsets, values, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *meta,
+                               const int64_t *offsets, const float *values, float *grid,
+                               hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_flat, dim3(blocks_for(n, 4)), dim3(256), 0, s, n, meta, offsets,
+                       values, grid, (int)pl->Np, (int)pl->Nt);
+    return hipGetLastError();
+}
+
+size_t raster_work_bytes(const wcsim_plane *pl, int64_t n)
+{
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    return align_up(256) + align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1)) +
+           4 * align_up(sizeof(int32_t) * nn) + scan_scratch_bytes(pl->ntiles + 1);
+}
+
+RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
+{
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    char *p = (char *)base;
+    RasterWork w;
+    w.counters = (int32_t *)p;
+    p += align_up(256);
+    w.tile_count = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1));
+    w.depo_tile = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    w.depo_slot = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    w.list = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    w.large = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    w.scan_scratch = p;
+    return w;
+}
+
+hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                               uint64_t event_id, const RasterWork &w, float *grid, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_fill_zero(w.counters, 256, s)) != hipSuccess)
+        return e;
+    if ((e = launch_fill_zero(w.tile_count, sizeof(int32_t) * (size_t)(pl->ntiles + 1), s)) !=
+        hipSuccess)
+        return e;
+    if (n <= 0)
+        return hipSuccess;
+    TileGeom g;
+    g.tp = pl->ts.tp;
+    g.tt = pl->ts.tt;
+    g.rp = pl->ts.tp + kHaloP;
+    g.rt = pl->ts.tt + kHaloT;
+    g.ntt = pl->ntt;
+    hipLaunchKernelGGL(k_prep_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, depos, n, pl->kp, g,
+                       w.counters, w.tile_count, w.depo_tile, w.depo_slot, w.large);
+    if ((e = launch_exclusive_scan_i32(w.tile_count, pl->ntiles + 1, w.scan_scratch, s)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_fill_list, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.depo_tile,
+                       w.depo_slot, w.tile_count, w.list);
+    const uint32_t ev = (uint32_t)event_id;
+    switch (pl->tile) {
+    case 1:
+        hipLaunchKernelGGL((k_raster_tiles<64, 128>), dim3((unsigned)pl->ntiles), dim3(256), 0, s,
+                           depos, w.tile_count, w.list, pl->kp, ev, pl->ntt, grid);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_raster_tiles<32, 128>), dim3((unsigned)pl->ntiles), dim3(256), 0, s,
+                           depos, w.tile_count, w.list, pl->kp, ev, pl->ntt, grid);
+        break;
+    default:
+        hipLaunchKernelGGL((k_raster_tiles<64, 64>), dim3((unsigned)pl->ntiles), dim3(256), 0, s,
+                           depos, w.tile_count, w.list, pl->kp, ev, pl->ntt, grid);
+        break;
+    }
+    // Depos whose patch does not fit a tile region: one workgroup each, direct
+    // atomics.  The grid is persistent over the device-side count.
+    const unsigned lg = (unsigned)std::min<int64_t>(n, 2048);
+    hipLaunchKernelGGL((k_patch_generic<256, false>), dim3(lg), dim3(256), 0, s, depos, w.large,
+                       w.counters + 1, (int64_t)0, pl->kp, ev, nullptr, nullptr, grid);
+    return hipGetLastError();
+}
+
+}  // namespace wcs

@@ -1,0 +1,150 @@
+// Internal declarations of libwcsim: kernel-side parameter blocks, the plane
+// object and the launch helpers shared by the raster and FFT translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "wcsim.h"
+
+namespace wcs {
+
+// ---------------------------------------------------------------------------
+// Status plumbing
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+wcsim_status fail(wcsim_status st, const std::string &msg);
+wcsim_status check_hip(hipError_t e, const char *what);
+
+#define WCS_HIP(expr)                                                      \
+    do {                                                                   \
+        hipError_t _e = (expr);                                            \
+        if (_e != hipSuccess)                                              \
+            return ::wcs::check_hip(_e, #expr);                            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel-side view of a plane's geometry and physics.  Every double here is
+// derived on the host exactly as the definitions read (dp = pitch / nimpact),
+// so that the device reproduces the window bounds operation by operation.
+// ---------------------------------------------------------------------------
+struct PlaneParams {
+    double v, DL, DT, nsigma;
+    double dp, tick, t0, plane_x, dir_y, dir_z, pitch_origin;
+    int32_t Np, Nt, nimpact, plane_id;
+    uint32_t key0, key1;  // Philox key: seed low word, seed high word ^ plane_id
+    int32_t fluct;
+    int32_t pad_;
+};
+
+// Maximum window length per axis handled anywhere in the library.
+constexpr int kMaxWindow = 1024;
+
+// ---------------------------------------------------------------------------
+// FFT plans
+// ---------------------------------------------------------------------------
+constexpr int kMaxPass = 12;
+struct FftPlan {
+    int32_t n;
+    int32_t npass;
+    int32_t radix[kMaxPass];
+};
+
+bool make_plan(int n, FftPlan *plan);     // factor n into radices {8,4,2,5,3}
+int smallest_smooth_even(int nmin);      // smallest even n >= nmin with n/2 plannable
+
+// Raster tile shapes (pitch x tick tile; the LDS region adds a halo).
+struct TileShape {
+    int tp, tt, hp, ht;
+};
+constexpr int kNumTileShapes = 3;
+TileShape tile_shape(int id);
+
+}  // namespace wcs
+
+// ---------------------------------------------------------------------------
+// Plane object
+// ---------------------------------------------------------------------------
+struct wcsim_plane {
+    wcsim_plane_desc desc;  // response pointer cleared (host copy not kept)
+    wcsim_physics phys;
+    wcs::PlaneParams kp;
+    int device;
+    int64_t Np, Nt, Nw;
+    // FFT schedule: tick axis N' = 2 N2 (real), pitch axis overlap-save blocks
+    // of length L with V = L - Rp + 1 valid rows each.
+    int Nfft, N2, H, F, C, L, V, nblocks;
+    int Rp, Rt, r0;
+    wcs::FftPlan planT, planL;
+    float2 *twT;     // exp(-2 pi i j / N2), j < N2
+    float2 *twHalf;  // exp(-2 pi i k / N'), k <= N2
+    float2 *twL;     // exp(-2 pi i j / L), j < L
+    float2 *K;       // response spectrum [C][L][F], scaled by 1/(L N')
+    int tile;
+    wcs::TileShape ts;
+    int ntp, ntt;
+    int64_t ntiles;
+};
+
+struct wcsim_patches {
+    int64_t n;
+    int64_t nvalues;
+    int32_t *meta;     // [n][4]
+    int64_t *offsets;  // [n+1]
+    float *values;
+    wcsim_depo *staged;  // device copy of host depos (owned) or nullptr
+    int device;
+};
+
+namespace wcs {
+
+// ---------------------------------------------------------------------------
+// Launch helpers (defined in raster.hip / fft.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
+
+hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
+                         hipStream_t s);
+
+// unfused rasterize: per-depo sizes, scan, values
+hipError_t launch_patch_sizes(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                              int32_t *meta, int64_t *sizes, hipStream_t s);
+size_t scan_scratch_bytes(int64_t n);
+hipError_t launch_exclusive_scan_i64(int64_t *data, int64_t n, void *scratch, hipStream_t s);
+hipError_t launch_exclusive_scan_i32(int32_t *data, int64_t n, void *scratch, hipStream_t s);
+hipError_t launch_patch_values(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                               uint64_t event_id, const int32_t *meta, const int64_t *offsets,
+                               float *values, hipStream_t s);
+hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *meta,
+                               const int64_t *offsets, const float *values, float *grid,
+                               hipStream_t s);
+
+// fused raster + LDS-staged scatter
+struct RasterWork {
+    int32_t *counters;    // [0] invalid, [1] large count
+    int32_t *tile_count;  // [ntiles + 1] -> exclusive offsets after the scan
+    int32_t *depo_tile;   // [n]
+    int32_t *depo_slot;   // [n]
+    int32_t *list;        // [n]
+    int32_t *large;       // [n]
+    void *scan_scratch;
+};
+size_t raster_work_bytes(const wcsim_plane *pl, int64_t n);
+RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base);
+hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                               uint64_t event_id, const RasterWork &w, float *grid,
+                               hipStream_t s);
+
+// FFT convolution passes
+size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind);
+hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
+                           wcsim_out out_kind, void *work, hipStream_t s);
+hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void *work,
+                                   hipStream_t s);
+size_t response_work_bytes(const wcsim_plane *pl);
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+}  // namespace wcs

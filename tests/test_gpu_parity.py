@@ -1,0 +1,270 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (normwise, max|gpu - oracle| / max|oracle| over the array):
+  * patch values and the plane grid: 1e-5 (FP32 arithmetic on FP64 weights);
+  * convolved output: 1e-4 (FP32 FFTs of length up to ~10^4);
+  * integer window bounds and the Philox words: bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2304_01841_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GRID_TOL = 1e-5
+CONV_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ws():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_01841_amd import wcsim
+    return wcsim
+
+
+def normwise(got, ref):
+    ref = np.asarray(ref, dtype=np.float64)
+    got = np.asarray(got, dtype=np.float64)
+    scale = np.abs(ref).max()
+    if scale == 0:
+        return np.abs(got).max()
+    return np.abs(got - ref).max() / scale
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Philox
+# ---------------------------------------------------------------------------
+def test_philox_bitwise(ws):
+    log("case: philox sweep")
+    rng = np.random.default_rng(1)
+    n = 200_000
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0; key[0] = 0; ctr[1] = 0xFFFFFFFF; key[1] = 0xFFFFFFFF
+    ref = O.philox4x32_10(ctr, key)
+    got = ws.philox4x32_10(torch.from_numpy(ctr.view(np.int32)).cuda(),
+                           torch.from_numpy(key.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().view(np.uint32), ref)
+
+
+# ---------------------------------------------------------------------------
+# Rasterization (patch sets)
+# ---------------------------------------------------------------------------
+def _compare_patches(ws, plane, phys, depos, event_id=0, mem="device"):
+    R = W.response("bipolar")
+    P = ws.Plane(plane, phys, R)
+    dep = torch.from_numpy(depos).cuda() if mem == "device" else depos
+    pt = ws.rasterize(P, dep, event_id)
+    meta, offs, vals = pt.to_host()
+    ometa, ovals, ost = O.rasterize(depos, phys, plane, event_id)
+    # windows: bit-exact
+    assert np.array_equal(meta[:, 0], ometa[:, 0])
+    assert np.array_equal(meta[:, 1], ometa[:, 1])
+    assert np.array_equal(meta[:, 2], ometa[:, 2])
+    assert np.array_equal(meta[:, 3], ometa[:, 3])
+    assert np.array_equal(offs[:-1], ometa[:, 4])
+    assert offs[-1] == ovals.size
+    # values: per patch, normwise
+    worst = 0.0
+    for d in range(depos.shape[0]):
+        o, n = ometa[d, 4], ometa[d, 2] * ometa[d, 3]
+        if n:
+            worst = max(worst, normwise(vals[o:o + n], ovals[o:o + n]))
+    assert worst <= GRID_TOL, worst
+    pt.destroy()
+    P.destroy()
+    return meta, offs, vals
+
+
+def test_rasterize_small_no_fluct(ws):
+    log("case: rasterize small workload, no fluctuation")
+    w = W.small()
+    _compare_patches(ws, w["planes"][0], w["phys"], w["depos"])
+
+
+def test_rasterize_small_fluct_host_depos(ws):
+    log("case: rasterize small workload, fluctuation, host depos")
+    w = W.small()
+    _compare_patches(ws, w["planes"][0], W.physics(True), w["depos"], event_id=77, mem="host")
+
+
+def test_rasterize_edges_and_large_windows(ws):
+    """Depos straddling the grid edges (negative lo), missing the grid, at zero
+    drift, and with windows beyond the one-wave path (long diffusion)."""
+    log("case: rasterize edges and long windows")
+    pl = W.plane(20, 300)
+    rng = np.random.default_rng(9)
+    dep = W.uniform_depos(rng, 300, (-5.0, 105.0), (-10.0, 160.0))
+    dep[0] = [0.0, 0.0, 50.0, 70.0, 100.0]          # zero drift
+    dep[1] = [100.0, 0.0, 5000.0, 0.0, 100.0]       # misses the grid
+    for fl in (False, True):
+        _compare_patches(ws, pl, W.physics(fl), dep, event_id=3)
+    phys = W.physics(True)
+    phys["DT"] = phys["DT"] * 40     # pitch windows ~ 110 bins
+    phys["DL"] = phys["DL"] * 40
+    _compare_patches(ws, pl, phys, dep[:60], event_id=4)
+
+
+# ---------------------------------------------------------------------------
+# Scatter-Add
+# ---------------------------------------------------------------------------
+def test_scatter_add_small(ws):
+    log("case: scatter-add small")
+    w = W.small()
+    for fl in (False, True):
+        phys = W.physics(fl)
+        P = ws.Plane(w["planes"][0], phys, w["responses"][0])
+        pt = ws.rasterize(P, torch.from_numpy(w["depos"]).cuda(), 5)
+        grid = torch.full((P.npitch, P.nticks), 7.0, device="cuda")
+        ws.scatter_add(P, pt, grid, zero_first=True)
+        G = O.grid(w["depos"], phys, w["planes"][0], 5)
+        assert normwise(grid.cpu().numpy(), G) <= GRID_TOL
+        # accumulate twice without zeroing
+        ws.scatter_add(P, pt, grid, zero_first=False)
+        assert normwise(grid.cpu().numpy(), 2 * G) <= GRID_TOL
+        if not fl:
+            assert grid.sum().item() == pytest.approx(2 * G.sum(), rel=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# Convolution
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nw,nimp,nt,Rp,Rt,r0", [
+    (7, 3, 50, 5, 9, 2),        # odd everything
+    (16, 4, 64, 8, 8, 0),
+    (13, 10, 333, 21, 40, 20),   # ragged tail in pitch and ticks
+    (30, 10, 1000, 210, 200, 105),
+    (5, 10, 601, 60, 31, 59),
+])
+def test_convolve_random_response(ws, nw, nimp, nt, Rp, Rt, r0):
+    log("case: convolve %s" % ((nw, nimp, nt, Rp, Rt, r0),))
+    rng = np.random.default_rng(nw * 1000 + nt)
+    pl = W.plane(nw, nt, nimpact=nimp)
+    R = W.random_response(rng, Rp, Rt)
+    P = ws.Plane(pl, W.physics(False), R, r0=r0)
+    G = rng.standard_normal((nw * nimp, nt)).astype(np.float32)
+    ref = O.convolve(G.astype(np.float64), R.astype(np.float64), r0)
+    g = torch.from_numpy(G).cuda()
+    out = ws.convolve(P, g, kind=ws.OUT_PITCH)
+    assert normwise(out.cpu().numpy(), ref) <= CONV_TOL
+    outw = ws.convolve(P, g, kind=ws.OUT_WIRE)
+    assert normwise(outw.cpu().numpy(), O.wire_rows(ref, nimp)) <= CONV_TOL
+
+
+def test_convolve_schedules_agree(ws):
+    """The result does not depend on the FFT schedule (padded sizes, chunk
+    width, pitch block length)."""
+    log("case: convolve schedules")
+    rng = np.random.default_rng(5)
+    pl = W.plane(40, 900)
+    R = W.random_response(rng, 50, 60)
+    G = rng.standard_normal((400, 900)).astype(np.float32)
+    ref = O.convolve(G.astype(np.float64), R.astype(np.float64), 25)
+    g = torch.from_numpy(G).cuda()
+    for sc in ({}, {"fft_ticks": 1024}, {"fft_ticks": 1000, "freq_chunk": 8},
+               {"fft_pitch": 128}, {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 240}):
+        P = ws.Plane(pl, W.physics(False), R, r0=25, schedule=sc)
+        out = ws.convolve(P, g, kind=ws.OUT_PITCH)
+        assert normwise(out.cpu().numpy(), ref) <= CONV_TOL, sc
+
+
+def test_convolve_delta_response_identity(ws):
+    log("case: convolve delta")
+    rng = np.random.default_rng(6)
+    pl = W.plane(20, 500)
+    R = np.zeros((31, 17), np.float32)
+    R[15, 0] = 1.0
+    P = ws.Plane(pl, W.physics(False), R, r0=15)
+    G = rng.standard_normal((200, 500)).astype(np.float32)
+    out = ws.convolve(P, torch.from_numpy(G).cuda(), kind=ws.OUT_PITCH)
+    assert normwise(out.cpu().numpy(), G) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Whole path
+# ---------------------------------------------------------------------------
+def _sim_and_compare(ws, w, fl=None, kinds=(0, 1), out_mem="device", event_id=None):
+    pl, R = w["planes"][0], w["responses"][0]
+    phys = w["phys"] if fl is None else W.physics(fl)
+    ev = w["event_id"] if event_id is None else event_id
+    P = ws.Plane(pl, phys, R)
+    dep = torch.from_numpy(w["depos"]).cuda()
+    G = O.grid(w["depos"], phys, pl, ev)
+    full = O.convolve(G, R.astype(np.float64), P.r0)
+    for kind in kinds:
+        wsp = ws.simulate_workspace(P, dep.shape[0], kind)
+        if out_mem == "device":
+            out = ws.simulate_event(P, dep, ev, kind=kind, workspace=wsp).cpu().numpy()
+        else:
+            out = np.zeros((P.out_rows(kind), P.nticks), np.float32)
+            ws.simulate_event(P, dep, ev, out=out, kind=kind, workspace=wsp)
+        grid = ws.workspace_grid(P, wsp, dep.shape[0]).cpu().numpy()
+        assert normwise(grid, G) <= GRID_TOL
+        ref = full if kind == ws.OUT_PITCH else O.wire_rows(full, pl["nimpact"])
+        assert normwise(out, ref) <= CONV_TOL
+        assert ws.workspace_invalid_count(wsp) == 0
+    return P
+
+
+def test_simulate_small(ws):
+    log("case: simulate small workload")
+    w = W.small()
+    _sim_and_compare(ws, w)
+    _sim_and_compare(ws, w, fl=True, out_mem="host", event_id=12)
+
+
+def test_simulate_collection_full_size(ws):
+    """Detector-scale collection plane (960 wires x 10 impact x 6000 ticks,
+    500,000 track depos, fluctuation) in the launch configuration the
+    benchmark times: the whole grid and output against the oracle."""
+    log("case: simulate collection plane, full size")
+    w = W.collection()
+    _sim_and_compare(ws, w, kinds=(ws.OUT_WIRE,))
+
+
+def test_simulate_empty_and_invalid(ws):
+    log("case: simulate empty / invalid")
+    pl = W.plane(10, 200)
+    R = W.response("bipolar", Rp=21, Rt=20, r0=10)
+    P = ws.Plane(pl, W.physics(True), R, r0=10)
+    dep = torch.zeros((0, 5), dtype=torch.float64, device="cuda")
+    wsp = ws.simulate_workspace(P, 0, ws.OUT_WIRE)
+    out = ws.simulate_event(P, dep, 0, workspace=wsp)
+    assert float(out.abs().max()) == 0.0
+    bad = np.array([[-1.0, 0, 10, 0, 5.0], [10.0, 0, 10, 0, -5.0], [np.nan, 0, 1, 0, 1.0],
+                    [10.0, 0, 10, 0, 5.0]])
+    with pytest.raises(ws.WcsimError) as ei:
+        ws.simulate_event(P, bad, 0)
+    assert ei.value.status == ws.E_INVALID
+    dev = torch.from_numpy(bad).cuda()
+    wsp = ws.simulate_workspace(P, 4, ws.OUT_WIRE)
+    out = ws.simulate_event(P, dev, 0, workspace=wsp)
+    assert ws.workspace_invalid_count(wsp) == 3
+    ref = O.wire_rows(O.convolve(O.grid(bad[3:], W.physics(True), pl, 0), R.astype(float), 10), 10)
+    # the valid depo keeps its index 3 in the Philox key
+    G = O.grid(bad, W.physics(True), pl, 0)
+    ref = O.wire_rows(O.convolve(G, R.astype(float), 10), 10)
+    assert normwise(out.cpu().numpy(), ref) <= CONV_TOL
+
+
+def test_simulate_long_windows_use_generic_path(ws):
+    log("case: simulate long windows")
+    pl = W.plane(30, 800)
+    rng = np.random.default_rng(31)
+    dep = W.uniform_depos(rng, 400, (0.0, 150.0), (0.0, 400.0))
+    phys = W.physics(True)
+    phys["DT"] *= 30
+    phys["DL"] *= 30
+    w = dict(planes=[pl], responses=[W.response("bipolar")], depos=dep, phys=phys, event_id=2)
+    _sim_and_compare(ws, w)
