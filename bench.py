@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the LArTPC signal-simulation hot path on one MI355X.
+
+A step is one whole DepoTransform (arXiv:2304.01841, Sec. 2: rasterize with
+fluctuation, scatter-add into the plane grid, FFT convolution with the
+response) of one event whose depos are already resident in HBM.  The workload
+is the detector-scale collection plane: 960 wires x 10 impact bins x 6,000
+ticks, 500,000 depos on 200 straight tracks, Philox fluctuation, a 210 x 200
+response, wire-resolution output.
+
+Prints one JSON line: depos/s (the headline), planes/s and the p50/p99 event
+latency, the per-stage times (the paper's per-kernel timers, Sec. 5.2), the
+roofline of the dominant kernel measured live with HIP events on the stream
+the library launches on, and the FP64 oracle timed on the host as a CPU
+baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # non-packed 32-bit lane ops/s (T)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kind", choices=["wire", "pitch"], default="wire")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (a plain copy kernel "
+                         "whose HBM counters scale the kernels' FETCH_SIZE / WRITE_SIZE)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(P, nout: int, n_depos: int) -> dict:
+    """Minimum HBM bytes of each stage at the minimum transform sizes:
+    H = floor((Nt + Rt - 1) / 2) + 1 frequencies per row; the grid written
+    once; the spectrum written by the tick pass and read by the pitch pass;
+    the kept rows written by the pitch pass and read by the inverse pass."""
+    Np, Nt = P.npitch, P.nticks
+    Rt = P._resp.shape[1]
+    H = (Nt + Rt - 1) // 2 + 1
+    L = P.info["fft_pitch"]
+    return {
+        "clear_grid": 4 * Np * Nt,
+        "raster_tiles": 40 * n_depos + 4 * Np * Nt,
+        "fft_ticks": 4 * Np * Nt + 8 * Np * H,
+        "conv_pitch": 8 * Np * H + 8 * L * H + 8 * nout * H,
+        "ifft_ticks": 8 * nout * H + 4 * nout * Nt,
+    }
+
+
+def cpu_baseline(w, kind_wire: bool) -> dict:
+    """The FP64 oracle on one whole event, single-threaded."""
+    from oracle import oracle as O
+
+    pl, R, phys, dep = w["planes"][0], w["responses"][0], w["phys"], w["depos"]
+    O.build()
+    t0 = time.perf_counter()
+    out = O.simulate_event(dep, phys, pl, R.astype(np.float64), R.shape[0] // 2, w["event_id"],
+                           wire_output=kind_wire, workers=1)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(out).all()
+    return {"value": dep.shape[0] / dt, "unit": "depos/s", "cores": 1, "kind": "oracle",
+            "sample": "one whole event (%d depos, %d x %d grid) in %.2f s, 1 thread"
+                      % (dep.shape[0], pl["nwires"] * pl["nimpact"], pl["nticks"], dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (events and "
+              "planes would shard with no communication); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2304_01841_amd import wcsim
+    from paper_2304_01841_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.collection()
+    pl, R = w["planes"][0], w["responses"][0]
+    kind = wcsim.OUT_WIRE if args.kind == "wire" else wcsim.OUT_PITCH
+    P = wcsim.Plane(pl, w["phys"], R)
+    dep = torch.from_numpy(w["depos"]).to(dev)
+    n = dep.shape[0]
+    nout = P.out_rows(kind)
+    out = torch.empty((nout, P.nticks), dtype=torch.float32, device=dev)
+    wsp = wcsim.simulate_workspace(P, n, kind, dev)
+    stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for i in range(args.warmup):
+        wcsim.simulate_event(P, dep, w["event_id"], out=out, kind=kind, workspace=wsp)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = wcsim.HipEvents(K * wcsim.NUM_STAGE_EVENTS)
+    NE = wcsim.NUM_STAGE_EVENTS
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        wcsim.simulate_event_profiled(P, dep, w["event_id"], out, kind, wsp,
+                                      ev.handles[i * NE:(i + 1) * NE], stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    lat = np.array([ev.elapsed_ms(i * NE, i * NE + NE - 1) for i in range(K)])
+    stages = {}
+    for j, name in enumerate(wcsim.STAGE_NAMES):
+        stages[name] = float(np.mean([ev.elapsed_ms(i * NE + j, i * NE + j + 1) for i in range(K)]))
+    ev.destroy()
+
+    ms_per_step = wall * 1e3 / K
+    depos_per_s = n * K / wall
+    planes_per_s = K / wall
+
+    # Dominant stage: longest average; roofline against HBM for the memory
+    # passes, against the VALU lane-op rate for the fluctuating raster kernel.
+    alg = algorithmic_bytes(P, nout, n)
+    dom = max(("raster_tiles", "fft_ticks", "conv_pitch", "ifft_ticks"), key=lambda s: stages[s])
+    achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes": alg[dom], "avg_ms": stages[dom]}
+    per_stage_hbm = {s: alg[s] / (stages[s] * 1e-3) / 1e9 for s in alg if stages.get(s, 0) > 0}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, kind == wcsim.OUT_WIRE)
+
+    line = {
+        "metric": "depos/sec and planes/sec on 1 GPU (batched vs plain); p50/p99 event latency",
+        "value": depos_per_s,
+        "unit": "depos/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 windows/weights)",
+        "data": "synthetic",
+        "config": {"workload": "collection plane 960 wires x 10 impact x 6000 ticks, 500000 "
+                               "track depos, Philox fluctuation, 210x200 response, plain "
+                               "per-event launch, %s output" % args.kind,
+                   "global_batch": 1, "depos_per_event": n,
+                   "fft_ticks": P.info["fft_ticks"], "fft_pitch": P.info["fft_pitch"],
+                   "freq_chunk": P.info["freq_chunk"], "tile": P.info["tile"]},
+        "planes_per_s": planes_per_s,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean())},
+        "stage_ms": stages,
+        "stage_hbm_gbs": per_stage_hbm,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    P.destroy()
+
+
+if __name__ == "__main__":
+    main()

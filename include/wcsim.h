@@ -205,6 +205,22 @@ wcsim_status wcsim_simulate_event(const wcsim_plane *plane, const wcsim_depo *de
                                   wcsim_out out_kind, wcsim_mem out_mem, void *workspace,
                                   void *stream);
 
+/* wcsim_simulate_event with stage timing, for measuring each kernel on the
+ * stream it runs on (the paper times Rasterization, Scatter-Add and FFT
+ * separately, Sec. 5.2).  `events` holds WCSIM_NUM_STAGE_EVENTS hipEvent_t
+ * handles created by the caller; they are recorded on `stream` at:
+ *   [0] start, [1] grid cleared, [2] depos binned to tiles,
+ *   [3] LDS-tiled raster + scatter done, [4] large-patch raster done,
+ *   [5] tick-axis FFT done, [6] pitch-axis convolution done,
+ *   [7] inverse tick-axis FFT done (end).
+ * Same results and errors as wcsim_simulate_event; WCSIM_E_INVALID if
+ * `events` or one of its entries is NULL. */
+#define WCSIM_NUM_STAGE_EVENTS 8
+wcsim_status wcsim_simulate_event_profiled(const wcsim_plane *plane, const wcsim_depo *depos,
+                                           int64_t n, wcsim_mem depo_mem, uint64_t event_id,
+                                           float *out, wcsim_out out_kind, wcsim_mem out_mem,
+                                           void *workspace, void *stream, void *const *events);
+
 /* Device pointer to the [npitch][nticks] grid inside a simulate workspace. */
 float *wcsim_workspace_grid(const wcsim_plane *plane, void *workspace, int64_t n);
 

@@ -85,14 +85,20 @@ int pow2_at_least(int v)
     return p;
 }
 
-// Host copy of exp(-2 pi i j / n), j < count, rounded from FP64.
+// Two-level table of W = exp(-2 pi i / n) for exponents j < count, rounded
+// from FP64: entries 0..63 hold W^l, entry 64 + h holds W^(64 h), so that
+// W^j = T[64 + j / 64] T[j mod 64].
 std::vector<float2> twiddles(int n, int count)
 {
-    std::vector<float2> t((size_t)count);
-    for (int j = 0; j < count; ++j) {
-        const double a = -2.0 * M_PI * (double)j / (double)n;
-        t[(size_t)j] = make_float2((float)cos(a), (float)sin(a));
-    }
+    std::vector<float2> t((size_t)twiddle_table_len(count));
+    auto w = [n](int64_t j) {
+        const double a = -2.0 * M_PI * (double)(j % n) / (double)n;
+        return make_float2((float)cos(a), (float)sin(a));
+    };
+    for (int l = 0; l < 64; ++l)
+        t[(size_t)l] = w(l);
+    for (size_t h = 64; h < t.size(); ++h)
+        t[h] = w(64 * (int64_t)(h - 64));
     return t;
 }
 
@@ -119,17 +125,24 @@ wcsim_status choose_schedule(wcsim_plane *pl, const wcsim_schedule *sc)
     pl->N2 = nfft / 2;
     if (!make_plan(pl->N2, &pl->planT))
         return fail(WCSIM_E_INVALID, "fft_ticks/2 must factor into 2, 3 and 5");
-    if (sizeof(float2) * (size_t)(pl->N2 + 1) * 2 > kLdsBytes)
+    if (sizeof(float2) * ((size_t)(pl->N2 + 1) * 2 + twiddle_table_len(pl->N2) +
+                          twiddle_table_len(pl->N2 + 1)) > kLdsBytes ||
+        twiddle_table_len(pl->N2 + 1) > 256)
         return fail(WCSIM_E_INVALID, "tick-axis transform too long for LDS");
-    pl->F = (sc && sc->freq_chunk) ? sc->freq_chunk : 16;
+    // Default pitch block: about four response lengths (the overlap-save
+    // history is Rp - 1 of the L rows), in 8-column chunks from L = 1024 on so
+    // that a block fits 64 KB of LDS.
+    int L = (sc && sc->fft_pitch) ? sc->fft_pitch
+                                  : std::min(2048, std::max(256, pow2_at_least(4 * pl->Rp)));
+    pl->F = (sc && sc->freq_chunk) ? sc->freq_chunk : (L >= 1024 ? 8 : 16);
     if (pl->F != 8 && pl->F != 16)
         return fail(WCSIM_E_INVALID, "freq_chunk must be 8 or 16");
-    int L = (sc && sc->fft_pitch) ? sc->fft_pitch : std::max(256, pow2_at_least(2 * pl->Rp));
     if (L < pl->Rp)
         return fail(WCSIM_E_INVALID, "fft_pitch must be >= resp_npitch");
     if (!make_plan(L, &pl->planL))
         return fail(WCSIM_E_INVALID, "fft_pitch must factor into 2, 3 and 5");
-    if (sizeof(float2) * (size_t)L * pl->F > kLdsBytes)
+    if (sizeof(float2) * ((size_t)L * pl->F + twiddle_table_len(L)) > kLdsBytes ||
+        twiddle_table_len(L) > 256)
         return fail(WCSIM_E_INVALID, "pitch block too large for LDS");
     {
         // every pass must stage at most 32 complex values per thread of 1024
@@ -529,10 +542,10 @@ wcsim_status wcsim_workspace_invalid_count(const void *workspace, void *stream, 
     return WCSIM_OK;
 }
 
-wcsim_status wcsim_simulate_event(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
-                                  wcsim_mem depo_mem, uint64_t event_id, float *out,
-                                  wcsim_out out_kind, wcsim_mem out_mem, void *workspace,
-                                  void *stream)
+static wcsim_status simulate_event(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                                   wcsim_mem depo_mem, uint64_t event_id, float *out,
+                                   wcsim_out out_kind, wcsim_mem out_mem, void *workspace,
+                                   void *stream, const hipEvent_t *ev)
 {
     if (!pl)
         return fail(WCSIM_E_STATE, "NULL plane");
@@ -563,19 +576,46 @@ wcsim_status wcsim_simulate_event(const wcsim_plane *pl, const wcsim_depo *depos
                                    hipMemcpyHostToDevice, s));
         dd = staged;
     }
+    if (ev)
+        WCS_HIP(hipEventRecord(ev[0], s));
     WCS_HIP(launch_fill_zero(grid, sizeof(float) * (size_t)pl->Np * pl->Nt, s));
-    WCS_HIP(launch_raster_fused(pl, dd, n, event_id, rw, grid, s));
+    if (ev)
+        WCS_HIP(hipEventRecord(ev[1], s));
+    WCS_HIP(launch_raster_fused(pl, dd, n, event_id, rw, grid, s, ev ? ev + 2 : nullptr));
     const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
     const size_t out_bytes = sizeof(float) * (size_t)nout * pl->Nt;
     // Host output: the spectrum buffer of pass A is free once pass B has run
     // and is at least as large as the output.
     float *dst = (out_mem == WCSIM_MEM_HOST) ? (float *)conv : out;
-    WCS_HIP(launch_convolve(pl, grid, dst, out_kind, conv, s));
+    WCS_HIP(launch_convolve(pl, grid, dst, out_kind, conv, s, ev ? ev + 5 : nullptr));
     if (out_mem == WCSIM_MEM_HOST) {
         WCS_HIP(hipMemcpyAsync(out, dst, out_bytes, hipMemcpyDeviceToHost, s));
         WCS_HIP(hipStreamSynchronize(s));
     }
     return WCSIM_OK;
+}
+
+wcsim_status wcsim_simulate_event(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                                  wcsim_mem depo_mem, uint64_t event_id, float *out,
+                                  wcsim_out out_kind, wcsim_mem out_mem, void *workspace,
+                                  void *stream)
+{
+    return simulate_event(pl, depos, n, depo_mem, event_id, out, out_kind, out_mem, workspace,
+                          stream, nullptr);
+}
+
+wcsim_status wcsim_simulate_event_profiled(const wcsim_plane *pl, const wcsim_depo *depos,
+                                           int64_t n, wcsim_mem depo_mem, uint64_t event_id,
+                                           float *out, wcsim_out out_kind, wcsim_mem out_mem,
+                                           void *workspace, void *stream, void *const *events)
+{
+    if (!events)
+        return fail(WCSIM_E_INVALID, "NULL event array");
+    for (int i = 0; i < WCSIM_NUM_STAGE_EVENTS; ++i)
+        if (!events[i])
+            return fail(WCSIM_E_INVALID, "NULL event in the event array");
+    return simulate_event(pl, depos, n, depo_mem, event_id, out, out_kind, out_mem, workspace,
+                          stream, (const hipEvent_t *)events);
 }
 
 size_t wcsim_batch_workspace_bytes(const wcsim_plane *const *planes, const int64_t *n,

@@ -18,7 +18,9 @@
 // No step is a dense contraction, so there is no MFMA: the transforms are
 // mixed-radix (2, 3, 4, 5, 8) self-sorting Stockham passes over LDS, each pass
 // staging its butterflies in registers between two barriers so one LDS buffer
-// suffices.  Twiddles come from FP64-derived float32 tables.
+// suffices.  Twiddles come from two small FP64-derived tables per transform
+// size held in LDS (W^j = Hi[j / 64] Lo[j mod 64]), so no pass waits on global
+// memory, and every global<->LDS copy issues its loads in batches.
 #include <math.h>
 
 #include <vector>
@@ -29,6 +31,7 @@ namespace wcs {
 namespace {
 
 constexpr int kRegComplex = 32;  // complex values a thread stages per pass
+constexpr int kTwLo = 64;        // low table of a two-level twiddle table
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -40,6 +43,13 @@ __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // * (-i)
 __device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }  // * (+i)
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// exp(-2 pi i j / n) from a two-level table in LDS: tab[0..63] = W^l,
+// tab[64 + h] = W^(64 h).
+__device__ __forceinline__ float2 tw_at(const float2 *tab, int j)
+{
+    return cmul(tab[kTwLo + (j >> 6)], tab[j & (kTwLo - 1)]);
+}
 
 // Forward DFTs of length R in registers: X_m = sum_t x_t exp(-2 pi i t m / R).
 template <int R>
@@ -123,6 +133,20 @@ __device__ __forceinline__ void dft<5>(float2 *x)
     x[3] = csub(e2, mul_mi(o2));
 }
 
+// Multiply x_t by w^t, t = 1..R-1 (powers by repeated products: a few ulp,
+// far below the float32 transform error).
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 *x, float2 w)
+{
+    float2 wt = w;
+#pragma unroll
+    for (int t = 1; t < R; ++t) {
+        x[t] = cmul(x[t], wt);
+        if (t + 1 < R)
+            wt = (t == 1) ? cmul(w, w) : cmul(wt, w);
+    }
+}
+
 // One self-sorting Stockham pass of radix R over `nseq` sequences of length N
 // held in LDS (element x of sequence s at s*sstride + x*estride).  Sequence s
 // of butterfly g is g mod nseq (nseq a power of two), so neighbouring threads
@@ -131,8 +155,7 @@ __device__ __forceinline__ void dft<5>(float2 *x)
 // exp(-2 pi i t k / (p R)), runs the R-point DFT and writes y[(i-k) R + k + t p].
 template <int R, int MAXB>
 __device__ __forceinline__ void stockham_pass(float2 *buf, int N, int p, int nseq_shift,
-                                              int sstride, int estride,
-                                              const float2 *__restrict__ tw)
+                                              int sstride, int estride, const float2 *tab)
 {
     const int nb = N / R;
     const int total = nb << nseq_shift;
@@ -157,11 +180,8 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, int N, int p, int nse
         if (g < total) {
             const int s = g & nseq_mask, i = g >> nseq_shift;
             const int k = i % p;
-            if (k != 0) {
-#pragma unroll
-                for (int t = 1; t < R; ++t)
-                    v[b][t] = cmul(v[b][t], tw[t * k * twstep]);
-            }
+            if (k != 0)
+                twiddle_powers<R>(v[b], tw_at(tab, k * twstep));
             dft<R>(v[b]);
             float2 *dst = buf + s * sstride + ((i - k) * R + k) * estride;
 #pragma unroll
@@ -172,32 +192,149 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, int N, int p, int nse
     __syncthreads();
 }
 
-// Forward transform of every sequence, pass by pass.
+// Forward transform of every sequence with a runtime plan.
 __device__ void fft_lds(float2 *buf, const FftPlan &plan, int nseq_shift, int sstride,
-                        int estride, const float2 *__restrict__ tw)
+                        int estride, const float2 *tab)
 {
     int p = 1;
     for (int q = 0; q < plan.npass; ++q) {
         const int R = plan.radix[q];
         switch (R) {
         case 8:
-            stockham_pass<8, kRegComplex / 8>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            stockham_pass<8, kRegComplex / 8>(buf, plan.n, p, nseq_shift, sstride, estride, tab);
             break;
         case 4:
-            stockham_pass<4, kRegComplex / 4>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            stockham_pass<4, kRegComplex / 4>(buf, plan.n, p, nseq_shift, sstride, estride, tab);
             break;
         case 2:
-            stockham_pass<2, kRegComplex / 2>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            stockham_pass<2, kRegComplex / 2>(buf, plan.n, p, nseq_shift, sstride, estride, tab);
             break;
         case 5:
-            stockham_pass<5, kRegComplex / 5>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            stockham_pass<5, kRegComplex / 5>(buf, plan.n, p, nseq_shift, sstride, estride, tab);
             break;
         default:
-            stockham_pass<3, kRegComplex / 3>(buf, plan.n, p, nseq_shift, sstride, estride, tw);
+            stockham_pass<3, kRegComplex / 3>(buf, plan.n, p, nseq_shift, sstride, estride, tab);
             break;
         }
         p *= R;
     }
+}
+
+// Runtime-plan transform as a policy object (any supported size).
+struct FftRt {
+    static constexpr int kMaxThreads = 1024;
+    FftPlan plan;
+    int nseq_shift, sstride, estride;
+    __device__ __forceinline__ void run(float2 *buf, const float2 *tab) const
+    {
+        fft_lds(buf, plan, nseq_shift, sstride, estride, tab);
+    }
+};
+
+// Compile-time Stockham pass: sizes, strides and the radix are constants, so
+// the index arithmetic folds and the butterflies unroll.
+template <int N, int R, int P, int NSS, int SS, int ES, int NT>
+__device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab)
+{
+    constexpr int NB = N / R;
+    constexpr int TOTAL = NB << NSS;
+    constexpr int MAXB = (TOTAL + NT - 1) / NT;
+    constexpr int TWSTEP = N / (P * R);
+    constexpr int MASK = (1 << NSS) - 1;
+    const int tid = threadIdx.x;
+    float2 v[MAXB][R];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int g = tid + b * NT;
+        if ((TOTAL % NT) == 0 || g < TOTAL) {
+            const int s = g & MASK, i = g >> NSS;
+            const float2 *src = buf + s * SS + i * ES;
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                v[b][t] = src[t * NB * ES];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int g = tid + b * NT;
+        if ((TOTAL % NT) == 0 || g < TOTAL) {
+            const int s = g & MASK, i = g >> NSS;
+            const int k = (P == 1) ? 0 : i % P;
+            if (P > 1)
+                twiddle_powers<R>(v[b], tw_at(tab, k * TWSTEP));
+            dft<R>(v[b]);
+            float2 *dst = buf + s * SS + ((i - k) * R + k) * ES;
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                dst[t * P * ES] = v[b][t];
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int NSS, int SS, int ES, int NT, int P, int R, int... Rest>
+__device__ __forceinline__ void ct_fft(float2 *buf, const float2 *tab)
+{
+    ct_pass<N, R, P, NSS, SS, ES, NT>(buf, tab);
+    if constexpr (sizeof...(Rest) > 0)
+        ct_fft<N, NSS, SS, ES, NT, P * R, Rest...>(buf, tab);
+}
+
+// Compile-time transform as a policy object.
+template <int N, int NSS, int SS, int ES, int NT, int... Rs>
+struct FftCt {
+    static constexpr int kThreads = NT;
+    static constexpr int kMaxThreads = NT;
+    __device__ __forceinline__ void run(float2 *buf, const float2 *tab) const
+    {
+        ct_fft<N, NSS, SS, ES, NT, 1, Rs...>(buf, tab);
+    }
+};
+
+// Copy loop with the global accesses of kBatch iterations issued together:
+// value i = load(i) for i < total, then store(i, value).  A plain loop would
+// wait for each load before the LDS store of the same iteration and expose the
+// full memory latency once per iteration.
+constexpr int kBatch = 8;
+template <class LoadF, class StoreF>
+__device__ __forceinline__ void batched_copy(int total, LoadF load, StoreF store)
+{
+    for (int i0 = threadIdx.x; i0 < total; i0 += kBatch * blockDim.x) {
+        float2 v[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int i = i0 + b * blockDim.x;
+            if (i < total)
+                v[b] = load(i);
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int i = i0 + b * blockDim.x;
+            if (i < total)
+                store(i, v[b]);
+        }
+    }
+}
+
+// Twiddle tables (global) of a kernel, copied into LDS.  Both tables have at
+// most blockDim.x entries (checked on the host).
+struct TwTables {
+    const float2 *a;
+    int na;
+    const float2 *b;
+    int nb;
+};
+
+__device__ __forceinline__ void load_tables(const TwTables &t, float2 *la, float2 *lb)
+{
+    const int tid = threadIdx.x;
+    const float2 va = (tid < t.na) ? t.a[tid] : make_float2(0.0f, 0.0f);
+    const float2 vb = (t.b && tid < t.nb) ? t.b[tid] : make_float2(0.0f, 0.0f);
+    if (tid < t.na)
+        la[tid] = va;
+    if (t.b && tid < t.nb)
+        lb[tid] = vb;
 }
 
 // ---------------------------------------------------------------------------
@@ -207,41 +344,48 @@ __device__ void fft_lds(float2 *buf, const FftPlan &plan, int nseq_shift, int ss
 // E_k = (Z_k + conj Z_{N2-k}) / 2, D_k = (Z_k - conj Z_{N2-k}) / 2 and
 // w = exp(-2 pi i / N').  Output chunk layout X[c][row][f], k = c F + f,
 // frequencies above N2 zero.
+// LDS: rows [RPW][N2 + 1], then the N2 table, then the N' table.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_rows_r2c(const float *__restrict__ in, int nrows,
-                                                  int ncols, int64_t in_stride, int N2,
-                                                  FftPlan plan, const float2 *__restrict__ twN2,
-                                                  const float2 *__restrict__ twHalf,
-                                                  float2 *__restrict__ X, int F_shift, int C,
-                                                  int rpw_shift)
+template <class FFT>
+__global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(const float *__restrict__ in, int nrows,
+                                                  int ncols, int64_t in_stride, int N2, FFT fft,
+                                                  TwTables tw, float2 *__restrict__ X,
+                                                  int F_shift, int C, int rpw_shift)
 {
     extern __shared__ float2 lds[];
     const int RPW = 1 << rpw_shift;
     const int S = N2 + 1;
+    float2 *tabN2 = lds + RPW * S;
+    float2 *tabH = tabN2 + tw.na;
+    load_tables(tw, tabN2, tabH);
     const int row0 = blockIdx.x * RPW;
     const bool vec2 = ((ncols & 1) == 0) && ((in_stride & 1) == 0);
     for (int s = 0; s < RPW; ++s) {
         const int row = row0 + s;
         const float *src = in + (int64_t)row * in_stride;
-        for (int n = threadIdx.x; n < N2; n += blockDim.x) {
-            const int t = 2 * n;
-            float2 v = make_float2(0.0f, 0.0f);
-            if (row < nrows) {
-                if (vec2) {
-                    if (t < ncols)
-                        v = *(const float2 *)(src + t);
-                } else {
-                    if (t < ncols)
-                        v.x = src[t];
-                    if (t + 1 < ncols)
-                        v.y = src[t + 1];
+        const bool live = row < nrows;
+        batched_copy(
+            N2,
+            [&](int n) {
+                const int t = 2 * n;
+                float2 v = make_float2(0.0f, 0.0f);
+                if (live) {
+                    if (vec2) {
+                        if (t < ncols)
+                            v = *(const float2 *)(src + t);
+                    } else {
+                        if (t < ncols)
+                            v.x = src[t];
+                        if (t + 1 < ncols)
+                            v.y = src[t + 1];
+                    }
                 }
-            }
-            lds[s * S + n] = v;
-        }
+                return v;
+            },
+            [&](int n, float2 v) { lds[s * S + n] = v; });
     }
     __syncthreads();
-    fft_lds(lds, plan, rpw_shift, S, 1, twN2);
+    fft.run(lds, tabN2);
     const int half = N2 / 2;
     for (int s = 0; s < RPW; ++s) {
         float2 *b = lds + s * S;
@@ -250,7 +394,7 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float *__restrict__ in,
             const float2 Zk = b[k], Zn = b[kn];
             const float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
             const float2 D = make_float2(0.5f * (Zk.x - Zn.x), 0.5f * (Zk.y + Zn.y));
-            const float2 wD = cmul(twHalf[k], D);
+            const float2 wD = cmul(tw_at(tabH, k), D);
             b[k] = csub(E, mul_pi(wD));
             b[(k == 0) ? N2 : kn] = conjf2(cadd(E, mul_pi(wD)));
         }
@@ -258,16 +402,22 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float *__restrict__ in,
     __syncthreads();
     const int F = 1 << F_shift;
     const int total = C << (F_shift + rpw_shift);
-    for (int g = threadIdx.x; g < total; g += blockDim.x) {
-        const int f = g & (F - 1);
-        const int s = (g >> F_shift) & (RPW - 1);
-        const int c = g >> (F_shift + rpw_shift);
-        const int k = (c << F_shift) + f;
-        const int row = row0 + s;
-        if (row < nrows)
-            X[(((int64_t)c * nrows + row) << F_shift) + f] =
-                (k <= N2) ? lds[s * S + k] : make_float2(0.0f, 0.0f);
-    }
+    batched_copy(
+        total,
+        [&](int g) {
+            const int f = g & (F - 1);
+            const int s = (g >> F_shift) & (RPW - 1);
+            const int k = ((g >> (F_shift + rpw_shift)) << F_shift) + f;
+            return (k <= N2) ? lds[s * S + k] : make_float2(0.0f, 0.0f);
+        },
+        [&](int g, float2 v) {
+            const int f = g & (F - 1);
+            const int s = (g >> F_shift) & (RPW - 1);
+            const int c = g >> (F_shift + rpw_shift);
+            const int row = row0 + s;
+            if (row < nrows)
+                X[(((int64_t)c * nrows + row) << F_shift) + f] = v;
+        });
 }
 
 // ---------------------------------------------------------------------------
@@ -277,10 +427,9 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float *__restrict__ in,
 // z_n = x_{2n} + i x_{2n+1}.  The inverse runs as a forward transform of
 // conj(Z) (conj of the result).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_rows_c2r(const float2 *__restrict__ Y, int nrows,
-                                                  int N2, FftPlan plan,
-                                                  const float2 *__restrict__ twN2,
-                                                  const float2 *__restrict__ twHalf,
+template <class FFT>
+__global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(const float2 *__restrict__ Y, int nrows,
+                                                  int N2, FFT fft, TwTables tw,
                                                   float *__restrict__ out, int ncols,
                                                   int64_t out_stride, int F_shift, int C,
                                                   int rpw_shift)
@@ -288,19 +437,29 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2 *__restrict__ Y,
     extern __shared__ float2 lds[];
     const int RPW = 1 << rpw_shift;
     const int S = N2 + 1;
+    float2 *tabN2 = lds + RPW * S;
+    float2 *tabH = tabN2 + tw.na;
+    load_tables(tw, tabN2, tabH);
     const int row0 = blockIdx.x * RPW;
     const int F = 1 << F_shift;
     const int total = C << (F_shift + rpw_shift);
-    for (int g = threadIdx.x; g < total; g += blockDim.x) {
-        const int f = g & (F - 1);
-        const int s = (g >> F_shift) & (RPW - 1);
-        const int c = g >> (F_shift + rpw_shift);
-        const int k = (c << F_shift) + f;
-        const int row = row0 + s;
-        if (k <= N2)
-            lds[s * S + k] = (row < nrows) ? Y[(((int64_t)c * nrows + row) << F_shift) + f]
-                                           : make_float2(0.0f, 0.0f);
-    }
+    batched_copy(
+        total,
+        [&](int g) {
+            const int f = g & (F - 1);
+            const int s = (g >> F_shift) & (RPW - 1);
+            const int c = g >> (F_shift + rpw_shift);
+            const int row = row0 + s;
+            return (row < nrows) ? Y[(((int64_t)c * nrows + row) << F_shift) + f]
+                                 : make_float2(0.0f, 0.0f);
+        },
+        [&](int g, float2 v) {
+            const int f = g & (F - 1);
+            const int s = (g >> F_shift) & (RPW - 1);
+            const int k = ((g >> (F_shift + rpw_shift)) << F_shift) + f;
+            if (k <= N2)
+                lds[s * S + k] = v;
+        });
     __syncthreads();
     const int half = N2 / 2;
     for (int s = 0; s < RPW; ++s) {
@@ -310,14 +469,14 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2 *__restrict__ Y,
             const float2 Xk = b[k], Xn = b[kn];
             const float2 A = make_float2(Xk.x + Xn.x, Xk.y - Xn.y);
             const float2 B = make_float2(Xk.x - Xn.x, Xk.y + Xn.y);
-            const float2 wB = cmul(conjf2(twHalf[k]), B);
+            const float2 wB = cmul(conjf2(tw_at(tabH, k)), B);
             b[k] = conjf2(cadd(A, mul_pi(wB)));
             if (k != 0)
                 b[kn] = csub(A, mul_pi(wB));  // conj of conj(A - i conj(w) B)
         }
     }
     __syncthreads();
-    fft_lds(lds, plan, rpw_shift, S, 1, twN2);
+    fft.run(lds, tabN2);
     const bool vec2 = ((ncols & 1) == 0) && ((out_stride & 1) == 0);
     for (int s = 0; s < RPW; ++s) {
         const int row = row0 + s;
@@ -350,12 +509,15 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2 *__restrict__ Y,
 // workgroups of one XCD walk the pitch blocks of one chunk before the next, so
 // the chunk's response spectrum and the rows shared by neighbouring blocks are
 // re-read from that XCD's L2.
+// LDS: the block [L][F], then the L table.
 // ---------------------------------------------------------------------------
-__global__ void k_pitch_conv(const float2 *__restrict__ X, int nrows_in,
-                             const float2 *__restrict__ K, float2 *__restrict__ Y,
-                             int nrows_out, int L, int V, int Rp, int r0, int nblocks, int C,
-                             int F_shift, FftPlan plan, const float2 *__restrict__ twL, int mode,
-                             int nimpact, float scale)
+template <class FFT>
+__global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(const float2 *__restrict__ X, int nrows_in,
+                                                    const float2 *__restrict__ K,
+                                                    float2 *__restrict__ Y, int nrows_out, int L,
+                                                    int V, int Rp, int r0, int nblocks, int C,
+                                                    int F_shift, FFT fft, TwTables tw, int mode,
+                                                    int nimpact, float scale)
 {
     extern __shared__ float2 lds[];
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
@@ -365,16 +527,21 @@ __global__ void k_pitch_conv(const float2 *__restrict__ X, int nrows_in,
         return;
     const int F = 1 << F_shift;
     const int LF = L << F_shift;
+    float2 *tabL = lds + LF;
+    load_tables(tw, tabL, nullptr);
     const int P0 = blk * V;
     const int in0 = (mode == 2) ? 0 : P0 + r0 - (Rp - 1);
     const float2 *src = X + ((int64_t)c * nrows_in << F_shift);
-    for (int g = threadIdx.x; g < LF; g += blockDim.x) {
-        const int row = in0 + (g >> F_shift);
-        lds[g] = (row >= 0 && row < nrows_in) ? src[((int64_t)row << F_shift) + (g & (F - 1))]
-                                              : make_float2(0.0f, 0.0f);
-    }
+    batched_copy(
+        LF,
+        [&](int g) {
+            const int row = in0 + (g >> F_shift);
+            return (row >= 0 && row < nrows_in) ? src[((int64_t)row << F_shift) + (g & (F - 1))]
+                                                : make_float2(0.0f, 0.0f);
+        },
+        [&](int g, float2 v) { lds[g] = v; });
     __syncthreads();
-    fft_lds(lds, plan, F_shift, 1, F, twL);
+    fft.run(lds, tabL);
     if (mode == 2) {
         float2 *dst = Y + (int64_t)c * LF;
         for (int g = threadIdx.x; g < LF; g += blockDim.x)
@@ -382,10 +549,11 @@ __global__ void k_pitch_conv(const float2 *__restrict__ X, int nrows_in,
         return;
     }
     const float2 *Kc = K + (int64_t)c * LF;
-    for (int g = threadIdx.x; g < LF; g += blockDim.x)
-        lds[g] = conjf2(cmul(lds[g], Kc[g]));
+    batched_copy(
+        LF, [&](int g) { return Kc[g]; },
+        [&](int g, float2 k) { lds[g] = conjf2(cmul(lds[g], k)); });
     __syncthreads();
-    fft_lds(lds, plan, F_shift, 1, F, twL);
+    fft.run(lds, tabL);
     float2 *dst = Y + ((int64_t)c * nrows_out << F_shift);
     const int first = (Rp - 1) << F_shift;
     for (int g = first + threadIdx.x; g < LF; g += blockDim.x) {
@@ -430,50 +598,135 @@ int threads_for(const FftPlan &plan, int nseq)
 
 constexpr int kRowsPerBlock = 2;  // rows per workgroup in passes A and C (power of two)
 
+// Compile-time transforms for the sizes the default schedules use:
+//   tick axis N2 = 3125 (N' = 6250, 6000-tick planes) and N2 = 600 (N' = 1200,
+//   1000-tick planes), two rows per workgroup;
+//   pitch axis L = 1024 with 8-column chunks and L = 512 with 16-column chunks.
+using TickCt3125 = FftCt<3125, 1, 3126, 1, 256, 5, 5, 5, 5, 5>;
+using TickCt600 = FftCt<600, 1, 601, 1, 256, 8, 5, 5, 3>;
+using PitchCt1024x8 = FftCt<1024, 3, 1, 8, 256, 8, 8, 4, 4>;
+using PitchCt512x16 = FftCt<512, 4, 1, 16, 256, 8, 8, 8>;
+
+int table_len(int m) { return kTwLo + (m + kTwLo - 1) / kTwLo; }
+
+TwTables tick_tables(const wcsim_plane *pl)
+{
+    return {pl->twT, table_len(pl->N2), pl->twHalf, table_len(pl->N2 + 1)};
+}
+
+template <class FFT>
+void launch_r2c(const wcsim_plane *pl, FFT fft, int threads, const float *in, int nrows,
+                int ncols, int64_t in_stride, float2 *X, hipStream_t s)
+{
+    const TwTables tw = tick_tables(pl);
+    const size_t lds = sizeof(float2) * ((size_t)(pl->N2 + 1) * kRowsPerBlock + tw.na + tw.nb);
+    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL(k_rows_r2c<FFT>, dim3(blocks), dim3(threads), lds, s, in, nrows, ncols,
+                       in_stride, pl->N2, fft, tw, X, ilog2(pl->F), pl->C, ilog2(kRowsPerBlock));
+}
+
+template <class FFT>
+void launch_c2r(const wcsim_plane *pl, FFT fft, int threads, const float2 *Y, int nrows,
+                float *out, int ncols, int64_t out_stride, hipStream_t s)
+{
+    const TwTables tw = tick_tables(pl);
+    const size_t lds = sizeof(float2) * ((size_t)(pl->N2 + 1) * kRowsPerBlock + tw.na + tw.nb);
+    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL(k_rows_c2r<FFT>, dim3(blocks), dim3(threads), lds, s, Y, nrows, pl->N2,
+                       fft, tw, out, ncols, out_stride, ilog2(pl->F), pl->C,
+                       ilog2(kRowsPerBlock));
+}
+
+bool plan_is(const FftPlan &p, std::initializer_list<int> radices)
+{
+    if (p.npass != (int)radices.size())
+        return false;
+    int q = 0;
+    for (int r : radices)
+        if (p.radix[q++] != r)
+            return false;
+    return true;
+}
+
+FftRt runtime_fft(const FftPlan &plan, int nseq_shift, int sstride, int estride)
+{
+    FftRt f;
+    f.plan = plan;
+    f.nseq_shift = nseq_shift;
+    f.sstride = sstride;
+    f.estride = estride;
+    return f;
+}
+
+int tick_threads(const wcsim_plane *pl)
+{
+    return std::min(1024, std::max(256, threads_for(pl->planT, kRowsPerBlock)));
+}
+
+int pitch_threads(const wcsim_plane *pl)
+{
+    return std::min(1024, std::max(256, threads_for(pl->planL, pl->F)));
+}
+
 hipError_t rows_r2c(const wcsim_plane *pl, const float *in, int nrows, int ncols,
                     int64_t in_stride, float2 *X, hipStream_t s)
 {
-    const int rpw_shift = ilog2(kRowsPerBlock);
-    const int threads = std::min(1024, std::max(256, threads_for(pl->planT, kRowsPerBlock)));
-    const size_t lds = sizeof(float2) * (size_t)(pl->N2 + 1) * kRowsPerBlock;
-    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
-    hipLaunchKernelGGL(k_rows_r2c, dim3(blocks), dim3(threads), lds, s, in, nrows, ncols,
-                       in_stride, pl->N2, pl->planT, pl->twT, pl->twHalf, X, ilog2(pl->F), pl->C,
-                       rpw_shift);
+    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
+        launch_r2c(pl, TickCt3125(), TickCt3125::kThreads, in, nrows, ncols, in_stride, X, s);
+    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
+        launch_r2c(pl, TickCt600(), TickCt600::kThreads, in, nrows, ncols, in_stride, X, s);
+    else
+        launch_r2c(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
+                   tick_threads(pl), in, nrows, ncols, in_stride, X, s);
     return hipGetLastError();
 }
 
 hipError_t rows_c2r(const wcsim_plane *pl, const float2 *Y, int nrows, float *out, int ncols,
                     int64_t out_stride, hipStream_t s)
 {
-    const int rpw_shift = ilog2(kRowsPerBlock);
-    const int threads = std::min(1024, std::max(256, threads_for(pl->planT, kRowsPerBlock)));
-    const size_t lds = sizeof(float2) * (size_t)(pl->N2 + 1) * kRowsPerBlock;
-    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
-    hipLaunchKernelGGL(k_rows_c2r, dim3(blocks), dim3(threads), lds, s, Y, nrows, pl->N2,
-                       pl->planT, pl->twT, pl->twHalf, out, ncols, out_stride, ilog2(pl->F), pl->C,
-                       rpw_shift);
+    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
+        launch_c2r(pl, TickCt3125(), TickCt3125::kThreads, Y, nrows, out, ncols, out_stride, s);
+    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
+        launch_c2r(pl, TickCt600(), TickCt600::kThreads, Y, nrows, out, ncols, out_stride, s);
+    else
+        launch_c2r(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
+                   tick_threads(pl), Y, nrows, out, ncols, out_stride, s);
     return hipGetLastError();
+}
+
+template <class FFT>
+void launch_pitch(const wcsim_plane *pl, FFT fft, int threads, const float2 *X, int nrows_in,
+                  const float2 *K, float2 *Y, int nrows_out, int nblocks, int mode, float scale,
+                  hipStream_t s)
+{
+    const TwTables tw = {pl->twL, table_len(pl->L), nullptr, 0};
+    const size_t lds = sizeof(float2) * ((size_t)pl->L * pl->F + tw.na);
+    const int xcd_chunks = (pl->C + 7) / 8;
+    const unsigned blocks = (unsigned)(8 * xcd_chunks * nblocks);
+    hipLaunchKernelGGL(k_pitch_conv<FFT>, dim3(blocks), dim3(threads), lds, s, X, nrows_in, K, Y,
+                       nrows_out, pl->L, pl->V, pl->Rp, pl->r0, nblocks, pl->C, ilog2(pl->F), fft,
+                       tw, mode, (int)pl->kp.nimpact, scale);
 }
 
 hipError_t pitch_pass(const wcsim_plane *pl, const float2 *X, int nrows_in, const float2 *K,
                       float2 *Y, int nrows_out, int nblocks, int mode, float scale, hipStream_t s)
 {
-    const int F_shift = ilog2(pl->F);
-    const int threads = std::min(1024, std::max(256, threads_for(pl->planL, pl->F)));
-    const size_t lds = sizeof(float2) * (size_t)pl->L * pl->F;
-    const int xcd_chunks = (pl->C + 7) / 8;
-    const unsigned blocks = (unsigned)(8 * xcd_chunks * nblocks);
-    hipLaunchKernelGGL(k_pitch_conv, dim3(blocks), dim3(threads), lds, s, X, nrows_in, K, Y,
-                       nrows_out, pl->L, pl->V, pl->Rp, pl->r0, nblocks, pl->C, F_shift,
-                       pl->planL, pl->twL, mode, (int)pl->kp.nimpact, scale);
+    if (pl->L == 1024 && pl->F == 8 && plan_is(pl->planL, {8, 8, 4, 4}))
+        launch_pitch(pl, PitchCt1024x8(), PitchCt1024x8::kThreads, X, nrows_in, K, Y, nrows_out,
+                     nblocks, mode, scale, s);
+    else if (pl->L == 512 && pl->F == 16 && plan_is(pl->planL, {8, 8, 8}))
+        launch_pitch(pl, PitchCt512x16(), PitchCt512x16::kThreads, X, nrows_in, K, Y, nrows_out,
+                     nblocks, mode, scale, s);
+    else
+        launch_pitch(pl, runtime_fft(pl->planL, ilog2(pl->F), 1, pl->F), pitch_threads(pl), X,
+                     nrows_in, K, Y, nrows_out, nblocks, mode, scale, s);
     return hipGetLastError();
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Plans
+// Plans and tables
 // ---------------------------------------------------------------------------
 bool make_plan(int n, FftPlan *plan)
 {
@@ -481,13 +734,41 @@ bool make_plan(int n, FftPlan *plan)
     plan->npass = 0;
     if (n < 2)
         return false;
-    int m = n;
-    const int order[] = {8, 4, 2, 5, 3};
-    for (int r : order) {
+    // Powers of two as radix-8 passes, with a trailing 2 * 8 = 16 split as
+    // 4 * 4; then radices 5 and 3.
+    int m = n, twos = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++twos;
+    }
+    int eights = twos / 3, rest = twos % 3;
+    if (rest == 1 && eights > 0) {
+        --eights;
+        rest = 4;  // 2^4 = 4 * 4
+    }
+    auto push = [&](int r) {
+        if (plan->npass >= kMaxPass)
+            return false;
+        plan->radix[plan->npass++] = r;
+        return true;
+    };
+    for (int k = 0; k < eights; ++k)
+        if (!push(8))
+            return false;
+    if (rest == 4) {
+        if (!push(4) || !push(4))
+            return false;
+    } else if (rest == 2) {
+        if (!push(4))
+            return false;
+    } else if (rest == 1) {
+        if (!push(2))
+            return false;
+    }
+    for (int r : {5, 3}) {
         while (m % r == 0) {
-            if (plan->npass >= kMaxPass)
+            if (!push(r))
                 return false;
-            plan->radix[plan->npass++] = r;
             m /= r;
         }
     }
@@ -504,6 +785,8 @@ int smallest_smooth_even(int nmin)
     }
 }
 
+int twiddle_table_len(int m) { return table_len(m); }
+
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind)
 {
     const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
@@ -512,19 +795,24 @@ size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind)
 }
 
 hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
-                           wcsim_out out_kind, void *work, hipStream_t s)
+                           wcsim_out out_kind, void *work, hipStream_t s, const hipEvent_t *ev)
 {
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
     float2 *X = (float2 *)work;
     float2 *Y = (float2 *)((char *)work +
                            align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)pl->Np));
     hipError_t e;
-    if ((e = rows_r2c(pl, grid, (int)pl->Np, (int)pl->Nt, pl->Nt, X, s)) != hipSuccess)
+    if ((e = rows_r2c(pl, grid, (int)pl->Np, (int)pl->Nt, pl->Nt, X, s)) != hipSuccess ||
+        (e = mark(0)) != hipSuccess)
         return e;
     if ((e = pitch_pass(pl, X, (int)pl->Np, pl->K, Y, (int)nout, pl->nblocks,
-                        out_kind == WCSIM_OUT_WIRE ? 1 : 0, 1.0f, s)) != hipSuccess)
+                        out_kind == WCSIM_OUT_WIRE ? 1 : 0, 1.0f, s)) != hipSuccess ||
+        (e = mark(1)) != hipSuccess)
         return e;
-    return rows_c2r(pl, Y, (int)nout, out, (int)pl->Nt, pl->Nt, s);
+    if ((e = rows_c2r(pl, Y, (int)nout, out, (int)pl->Nt, pl->Nt, s)) != hipSuccess)
+        return e;
+    return mark(2);
 }
 
 size_t response_work_bytes(const wcsim_plane *pl)

@@ -57,7 +57,7 @@ __device__ __forceinline__ float word_to_uniform(uint32_t r)
 // v_sin/v_cos take their argument in revolutions, so theta = 2 pi u is u.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &zc, float &zs)
 {
-    const float rho = sqrtf(-2.0f * __logf(word_to_uniform(a)));
+    const float rho = __builtin_amdgcn_sqrtf(-2.0f * __logf(word_to_uniform(a)));
     const float u = word_to_uniform(b);
     zc = rho * __builtin_amdgcn_cosf(u);
     zs = rho * __builtin_amdgcn_sinf(u);
@@ -178,7 +178,7 @@ __device__ __forceinline__ void wave_weights(const Win &w, float *Wp, float *Wt,
 __device__ __forceinline__ float fluct_value(float q, float p, float z)
 {
     const float qp = q * p;
-    return fmaxf(0.0f, qp + z * sqrtf(qp * (1.0f - p)));
+    return fmaxf(0.0f, qp + z * __builtin_amdgcn_sqrtf(qp * (1.0f - p)));
 }
 
 __device__ __forceinline__ int quad_of(int J) { return J >> 2; }  // floor(J / 4)
@@ -478,9 +478,17 @@ __global__ __launch_bounds__(256) void k_scatter_flat(int64_t n, const int32_t *
 // ---------------------------------------------------------------------------
 // Fused path: tile binning and LDS-staged rasterization
 // ---------------------------------------------------------------------------
-constexpr int kHaloP = 32, kHaloT = 16;  // patches up to 33 x 17 bins fit a tile region
-constexpr int kFastMax = 63;             // window limit of the one-wave-per-patch path
-constexpr int kFluctItems = 4;           // Philox calls per lane held in registers
+constexpr int kHaloP = 32, kHaloT = 16;   // LDS region = tile + halo
+constexpr int kRecP = kHaloP + 1;         // longest pitch window of the tile path
+constexpr int kRecT = kHaloT + 1;         // longest tick window of the tile path
+constexpr int kRecWords = 64;             // floats per depo record (256 bytes)
+constexpr int kRecWp = 8;                 // record offset of the pitch weights
+constexpr int kRecWt = kRecWp + kRecP;    // record offset of the tick weights
+static_assert(kRecWt + kRecT <= kRecWords, "depo record overflow");
+constexpr int kChunk = 64;                // depos per tile work item
+constexpr int kFluctItems = 4;            // Philox calls per lane held in registers
+// A tile-path patch has at most kRecP * (kRecT / 4 + 2) = 231 Philox calls.
+static_assert(kRecP * (kRecT / 4 + 2) <= 64 * kFluctItems, "fluctuation items overflow");
 
 struct TileGeom {
     int tp, tt, rp, rt, ntt;
@@ -489,112 +497,255 @@ struct TileGeom {
 __device__ __forceinline__ bool fits_tile(const Win &w, int p0, int t0, const TileGeom &g,
                                           const PlaneParams &P)
 {
-    if (w.n_p > kFastMax || w.n_t > kFastMax)
+    if (w.n_p > kRecP || w.n_t > kRecT)
         return false;
-    if (min(w.lo_p + w.n_p, P.Np) > p0 + g.rp || min(w.lo_t + w.n_t, P.Nt) > t0 + g.rt)
-        return false;
-    if (P.fluct) {
-        const int nq = quad_of(w.lo_t + w.n_t - 1) - quad_of(w.lo_t) + 1;
-        if (w.n_p * nq > 64 * kFluctItems)
-            return false;
-    }
-    return true;
+    return min(w.lo_p + w.n_p, P.Np) <= p0 + g.rp && min(w.lo_t + w.n_t, P.Nt) <= t0 + g.rt;
 }
 
-__global__ void k_prep_bin(const wcsim_depo *depos, int64_t n, PlaneParams P, TileGeom g,
-                           int32_t *counters, int32_t *tile_count, int32_t *depo_tile,
-                           int32_t *depo_slot, int32_t *large)
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
+
+// Window and tile of every depo.  Slots in a tile's list come from one atomic
+// per distinct tile per wavefront (consecutive depos of a track share tiles).
+__global__ __launch_bounds__(256) void k_prep_bin(const wcsim_depo *depos, int64_t n,
+                                                  PlaneParams P, TileGeom g, int32_t *counters,
+                                                  int32_t *tile_count, int32_t *depo_tile,
+                                                  int32_t *depo_slot, int32_t *large)
 {
     const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (d >= n)
-        return;
-    const Win w = depo_window(depos[d], P);
-    int tile = -1, slot = 0;
-    if (w.status == 1 || w.status == 3) {
-        atomicAdd(&counters[0], 1);
-    } else if (w.status == 0) {
-        const int tp = min(max(w.lo_p, 0), P.Np - 1) / g.tp;
-        const int tt = min(max(w.lo_t, 0), P.Nt - 1) / g.tt;
-        if (fits_tile(w, tp * g.tp, tt * g.tt, g, P)) {
-            tile = tp * g.ntt + tt;
-            slot = atomicAdd(&tile_count[tile], 1);
-        } else {
-            large[atomicAdd(&counters[1], 1)] = (int32_t)d;
+    const int lane = threadIdx.x & 63;
+    int tile = -1;
+    bool bad = false, big = false;
+    if (d < n) {
+        const Win w = depo_window(depos[d], P);
+        if (w.status == 1 || w.status == 3) {
+            bad = true;
+        } else if (w.status == 0) {
+            const int tp = min(max(w.lo_p, 0), P.Np - 1) / g.tp;
+            const int tt = min(max(w.lo_t, 0), P.Nt - 1) / g.tt;
+            if (fits_tile(w, tp * g.tp, tt * g.tt, g, P))
+                tile = tp * g.ntt + tt;
+            else
+                big = true;
         }
     }
-    depo_tile[d] = tile;
-    depo_slot[d] = slot;
+    const uint64_t badm = __ballot(bad);
+    if (lane == 0 && badm)
+        atomicAdd(&counters[0], __popcll(badm));
+    const uint64_t bigm = __ballot(big);
+    if (bigm) {
+        int base = 0;
+        const int leader = __ffsll((unsigned long long)bigm) - 1;
+        if (lane == leader)
+            base = atomicAdd(&counters[1], __popcll(bigm));
+        base = __shfl(base, leader);
+        if (big)
+            large[base + __popcll(bigm & lanemask_lt(lane))] = (int32_t)d;
+    }
+    int slot = 0;
+    uint64_t active = __ballot(tile >= 0);
+    while (active) {
+        const int leader = __ffsll((unsigned long long)active) - 1;
+        const int lt = __shfl(tile, leader);
+        const uint64_t same = __ballot(tile == lt);
+        int base = 0;
+        if (lane == leader)
+            base = atomicAdd(&tile_count[lt], __popcll(same));
+        base = __shfl(base, leader);
+        if (tile == lt)
+            slot = base + __popcll(same & lanemask_lt(lane));
+        active &= ~same;
+    }
+    if (d < n) {
+        depo_tile[d] = tile;
+        depo_slot[d] = slot;
+    }
 }
 
-__global__ void k_fill_list(int64_t n, const int32_t *depo_tile, const int32_t *depo_slot,
-                            const int32_t *tile_off, int32_t *list)
+// Exclusive scan of one int per thread over a 1024-thread block.
+__device__ int block1024_exclusive(int v, int *sh, int *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += u;
+    }
+    if (lane == 63)
+        sh[wave] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        base += (k < wave) ? sh[k] : 0;
+        tot += sh[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+// One workgroup: per-tile depo counts -> exclusive list offsets (in place,
+// ntiles + 1 entries), and the list of (tile, chunk) work items of at most
+// kChunk depos each.  counters[2] = number of work items.
+constexpr int kSchedPer = 16;
+__global__ __launch_bounds__(1024) void k_tile_schedule(int32_t *tile_count, int ntiles,
+                                                        int2 *items, int32_t *counters)
+{
+    __shared__ int sh[16];
+    int carry_t = 0, carry_c = 0;
+    const int total_entries = ntiles + 1;
+    for (int base = 0; base < total_entries; base += 1024 * kSchedPer) {
+        const int first = base + threadIdx.x * kSchedPer;
+        int cnt[kSchedPer];
+        int sum_t = 0, sum_c = 0;
+#pragma unroll
+        for (int k = 0; k < kSchedPer; ++k) {
+            const int idx = first + k;
+            cnt[k] = (idx < ntiles) ? tile_count[idx] : 0;
+            sum_t += cnt[k];
+            sum_c += (cnt[k] + kChunk - 1) / kChunk;
+        }
+        int tot_t, tot_c;
+        int off_t = block1024_exclusive(sum_t, sh, &tot_t) + carry_t;
+        int off_c = block1024_exclusive(sum_c, sh, &tot_c) + carry_c;
+#pragma unroll
+        for (int k = 0; k < kSchedPer; ++k) {
+            const int idx = first + k;
+            if (idx < total_entries)
+                tile_count[idx] = off_t;
+            const int nch = (cnt[k] + kChunk - 1) / kChunk;
+            for (int j = 0; j < nch; ++j)
+                items[off_c + j] = make_int2(idx, j);
+            off_t += cnt[k];
+            off_c += nch;
+        }
+        carry_t += tot_t;
+        carry_c += tot_c;
+    }
+    if (threadIdx.x == 0)
+        counters[2] = carry_c;
+}
+
+// Weights of one axis computed by one thread into a record: erf at the n + 1
+// bin edges, normalised in FP64 by the window total 1/2 (E_n - E_0).
+__device__ __forceinline__ void thread_axis_weights(int lo, int n, double mu, double s, float *W)
+{
+    if (s == 0.0) {
+        W[0] = 1.0f;
+        return;
+    }
+    double e_lo = edge_erf(lo, 0, mu, s);
+    const double sum = 0.5 * (edge_erf(lo, n, mu, s) - e_lo);
+    for (int i = 0; i < n; ++i) {
+        const double e_hi = edge_erf(lo, i + 1, mu, s);
+        W[i] = (float)((0.5 * (e_hi - e_lo)) / sum);
+        e_lo = e_hi;
+    }
+}
+
+// Depo records in tile-list order: header {lo_p, lo_t, n_p, n_t, depo index,
+// charge} and the two weight vectors.
+__global__ __launch_bounds__(256) void k_fill_records(const wcsim_depo *depos, int64_t n,
+                                                      PlaneParams P, const int32_t *depo_tile,
+                                                      const int32_t *depo_slot,
+                                                      const int32_t *tile_off, float *records)
 {
     const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (d >= n)
         return;
     const int t = depo_tile[d];
-    if (t >= 0)
-        list[tile_off[t] + depo_slot[d]] = (int32_t)d;
+    if (t < 0)
+        return;
+    const int64_t pos = (int64_t)tile_off[t] + depo_slot[d];
+    const Win w = depo_window(depos[d], P);
+    float *rec = records + pos * kRecWords;
+    *(int4 *)rec = make_int4(w.lo_p, w.lo_t, w.n_p, w.n_t);
+    ((int *)rec)[4] = (int)d;
+    rec[5] = (float)w.q;
+    thread_axis_weights(w.lo_p, w.n_p, w.mu_p, w.s_p, rec + kRecWp);
+    thread_axis_weights(w.lo_t, w.n_t, w.mu_t, w.s_t, rec + kRecWt);
 }
 
+// floor(a / b) for 0 <= a < 4096 and 1 <= b <= 64 by a multiply-shift with
+// m = ceil(2^20 / b): the error term a (m b - 2^20) / (b 2^20) stays below 1/b.
+__device__ __forceinline__ int div_small(int a, int m) { return (a * m) >> 20; }
+__device__ __forceinline__ int magic_small(int b) { return ((1 << 20) + b - 1) / b; }
+
+// One workgroup per (tile, chunk of <= kChunk depos): the waves rasterize one
+// patch each at a time into the LDS copy of the tile region (tile + halo) and
+// the region's non-zero cells are then added to the grid with float atomics.
 template <int TP, int TT>
-__global__ __launch_bounds__(256) void k_raster_tiles(const wcsim_depo *depos,
-                                                      const int32_t *tile_off,
-                                                      const int32_t *list, PlaneParams P,
-                                                      uint32_t event, int ntt, float *grid)
+__global__ __launch_bounds__(256) void k_raster_tiles(const float *__restrict__ records,
+                                                      const int2 *__restrict__ items,
+                                                      const int32_t *__restrict__ tile_off,
+                                                      const int32_t *__restrict__ counters,
+                                                      PlaneParams P, uint32_t event, int ntt,
+                                                      float *grid)
 {
     constexpr int RP = TP + kHaloP, RT = TT + kHaloT, NW = 4;
     __shared__ float acc[RP * RT];
-    __shared__ float Wsh[NW][2][64];
-    const int tile = blockIdx.x;
-    const int beg = tile_off[tile], end = tile_off[tile + 1];
-    if (beg == end)
+    __shared__ float rsh[NW][kRecWords];
+    if ((int)blockIdx.x >= counters[2])
         return;
+    const int2 it2 = items[blockIdx.x];
+    const int tile = it2.x;
+    const int beg = tile_off[tile] + it2.y * kChunk;
+    const int end = min(beg + kChunk, tile_off[tile + 1]);
     for (int c = threadIdx.x; c < RP * RT; c += 256)
         acc[c] = 0.0f;
     __syncthreads();
     const int p0 = (tile / ntt) * TP, t0 = (tile % ntt) * TT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float *Wp = Wsh[wave][0], *Wt = Wsh[wave][1];
+    float *rec = rsh[wave];
+    const int *reci = (const int *)rec;
 
+    // The next record of this wave is loaded while the current patch is
+    // rasterized.
+    float next = (beg + wave < end) ? records[(int64_t)(beg + wave) * kRecWords + lane] : 0.0f;
     for (int k = beg + wave; k < end; k += NW) {
-        const int d = list[k];
-        const Win w = depo_window(depos[d], P);
-        wave_weights(w, Wp, Wt, lane);
-        const float qf = (float)w.q;
+        rec[lane] = next;
+        wave_lds_sync();
+        if (k + NW < end)
+            next = records[(int64_t)(k + NW) * kRecWords + lane];
+        const int lo_p = reci[0], lo_t = reci[1], n_p = reci[2], n_t = reci[3], d = reci[4];
+        const float qf = rec[5];
+        const float *Wp = rec + kRecWp, *Wt = rec + kRecWt;
         if (!P.fluct) {
-            const int cnt = w.n_p * w.n_t;
+            const int cnt = n_p * n_t, m = magic_small(n_t);
             for (int it = lane; it < cnt; it += 64) {
-                const int i = it / w.n_t, j = it - i * w.n_t;
-                const int I = w.lo_p + i, J = w.lo_t + j;
+                const int i = div_small(it, m), j = it - i * n_t;
+                const int I = lo_p + i, J = lo_t + j;
                 if ((unsigned)I < (unsigned)P.Np && (unsigned)J < (unsigned)P.Nt)
                     atomicAdd(&acc[(I - p0) * RT + (J - t0)], qf * Wp[i] * Wt[j]);
             }
         } else {
-            const int qlo = quad_of(w.lo_t), nq = quad_of(w.lo_t + w.n_t - 1) - qlo + 1;
-            const int items = w.n_p * nq;
+            const int qlo = quad_of(lo_t), nq = quad_of(lo_t + n_t - 1) - qlo + 1;
+            const int items_n = n_p * nq, m = magic_small(nq);
             float F[kFluctItems][4];
             float S = 0.0f;
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b) {
                 const int it = lane + 64 * b;
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    F[b][m] = 0.0f;
-                if (it < items) {
-                    const int i = it / nq, qd = qlo + (it - i * nq);
+                for (int mm = 0; mm < 4; ++mm)
+                    F[b][mm] = 0.0f;
+                if (it < items_n) {
+                    const int i = div_small(it, m), qd = qlo + (it - i * nq);
                     const uint4 r = philox4x32_10(
-                        make_uint4((uint32_t)qd, (uint32_t)(w.lo_p + i), (uint32_t)d, event),
+                        make_uint4((uint32_t)qd, (uint32_t)(lo_p + i), (uint32_t)d, event),
                         P.key0, P.key1);
                     float z[4];
                     box_muller(r.x, r.y, z[0], z[1]);
                     box_muller(r.z, r.w, z[2], z[3]);
+                    const float wp = Wp[i];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int j = 4 * qd + m - w.lo_t;
-                        if (j >= 0 && j < w.n_t) {
-                            F[b][m] = fluct_value(qf, Wp[i] * Wt[j], z[m]);
-                            S += F[b][m];
+                    for (int mm = 0; mm < 4; ++mm) {
+                        const int j = 4 * qd + mm - lo_t;
+                        if (j >= 0 && j < n_t) {
+                            F[b][mm] = fluct_value(qf, wp * Wt[j], z[mm]);
+                            S += F[b][mm];
                         }
                     }
                 }
@@ -604,22 +755,23 @@ __global__ __launch_bounds__(256) void k_raster_tiles(const wcsim_depo *depos,
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b) {
                 const int it = lane + 64 * b;
-                if (it < items) {
-                    const int i = it / nq, qd = qlo + (it - i * nq);
-                    const int I = w.lo_p + i;
+                if (it < items_n) {
+                    const int i = div_small(it, m), qd = qlo + (it - i * nq);
+                    const int I = lo_p + i;
+                    if ((unsigned)I < (unsigned)P.Np) {
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int J = 4 * qd + m, j = J - w.lo_t;
-                        if (j >= 0 && j < w.n_t && (unsigned)I < (unsigned)P.Np &&
-                            (unsigned)J < (unsigned)P.Nt) {
-                            const float v = (S > 0.0f) ? F[b][m] * scale : qf * Wp[i] * Wt[j];
-                            atomicAdd(&acc[(I - p0) * RT + (J - t0)], v);
+                        for (int mm = 0; mm < 4; ++mm) {
+                            const int J = 4 * qd + mm, j = J - lo_t;
+                            if (j >= 0 && j < n_t && (unsigned)J < (unsigned)P.Nt) {
+                                const float v = (S > 0.0f) ? F[b][mm] * scale : qf * Wp[i] * Wt[j];
+                                atomicAdd(&acc[(I - p0) * RT + (J - t0)], v);
+                            }
                         }
                     }
                 }
             }
         }
-        wave_lds_sync();  // weights are rewritten by the next patch
+        wave_lds_sync();  // the record buffer is rewritten by the next patch
     }
     __syncthreads();
     for (int c = threadIdx.x; c < RP * RT; c += 256) {
@@ -727,11 +879,17 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
     return hipGetLastError();
 }
 
+static size_t items_cap(const wcsim_plane *pl, int64_t n)
+{
+    return (size_t)pl->ntiles + (size_t)(std::max<int64_t>(n, 1) / kChunk) + 1;
+}
+
 size_t raster_work_bytes(const wcsim_plane *pl, int64_t n)
 {
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     return align_up(256) + align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1)) +
-           4 * align_up(sizeof(int32_t) * nn) + scan_scratch_bytes(pl->ntiles + 1);
+           align_up(sizeof(int2) * items_cap(pl, n)) + 3 * align_up(sizeof(int32_t) * nn) +
+           align_up(sizeof(float) * kRecWords * nn);
 }
 
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
@@ -743,29 +901,35 @@ RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
     p += align_up(256);
     w.tile_count = (int32_t *)p;
     p += align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1));
+    w.items = (int2 *)p;
+    p += align_up(sizeof(int2) * items_cap(pl, n));
     w.depo_tile = (int32_t *)p;
     p += align_up(sizeof(int32_t) * nn);
     w.depo_slot = (int32_t *)p;
     p += align_up(sizeof(int32_t) * nn);
-    w.list = (int32_t *)p;
-    p += align_up(sizeof(int32_t) * nn);
     w.large = (int32_t *)p;
     p += align_up(sizeof(int32_t) * nn);
-    w.scan_scratch = p;
+    w.records = (float *)p;
     return w;
 }
 
 hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
-                               uint64_t event_id, const RasterWork &w, float *grid, hipStream_t s)
+                               uint64_t event_id, const RasterWork &w, float *grid, hipStream_t s,
+                               const hipEvent_t *ev)
 {
     hipError_t e;
-    if ((e = launch_fill_zero(w.counters, 256, s)) != hipSuccess)
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+    // counters and tile counts are adjacent: one clear
+    const size_t clear = (size_t)((char *)w.tile_count - (char *)w.counters) +
+                         sizeof(int32_t) * (size_t)(pl->ntiles + 1);
+    if ((e = launch_fill_zero(w.counters, align_up(clear, 16), s)) != hipSuccess)
         return e;
-    if ((e = launch_fill_zero(w.tile_count, sizeof(int32_t) * (size_t)(pl->ntiles + 1), s)) !=
-        hipSuccess)
-        return e;
-    if (n <= 0)
+    if (n <= 0) {
+        for (int i = 0; i < 3; ++i)
+            if ((e = mark(i)) != hipSuccess)
+                return e;
         return hipSuccess;
+    }
     TileGeom g;
     g.tp = pl->ts.tp;
     g.tt = pl->ts.tt;
@@ -774,32 +938,41 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
     g.ntt = pl->ntt;
     hipLaunchKernelGGL(k_prep_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, depos, n, pl->kp, g,
                        w.counters, w.tile_count, w.depo_tile, w.depo_slot, w.large);
-    if ((e = launch_exclusive_scan_i32(w.tile_count, pl->ntiles + 1, w.scan_scratch, s)) !=
-        hipSuccess)
+    hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(1024), 0, s, w.tile_count, (int)pl->ntiles,
+                       w.items, w.counters);
+    hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(n, 256)), dim3(256), 0, s, depos, n,
+                       pl->kp, w.depo_tile, w.depo_slot, w.tile_count, w.records);
+    if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_fill_list, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.depo_tile,
-                       w.depo_slot, w.tile_count, w.list);
-    const uint32_t ev = (uint32_t)event_id;
+    const uint32_t evid = (uint32_t)event_id;
+    const unsigned grid_items = (unsigned)items_cap(pl, n);
     switch (pl->tile) {
     case 1:
-        hipLaunchKernelGGL((k_raster_tiles<64, 128>), dim3((unsigned)pl->ntiles), dim3(256), 0, s,
-                           depos, w.tile_count, w.list, pl->kp, ev, pl->ntt, grid);
+        hipLaunchKernelGGL((k_raster_tiles<64, 128>), dim3(grid_items), dim3(256), 0, s,
+                           w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
+                           grid);
         break;
     case 2:
-        hipLaunchKernelGGL((k_raster_tiles<32, 128>), dim3((unsigned)pl->ntiles), dim3(256), 0, s,
-                           depos, w.tile_count, w.list, pl->kp, ev, pl->ntt, grid);
+        hipLaunchKernelGGL((k_raster_tiles<32, 128>), dim3(grid_items), dim3(256), 0, s,
+                           w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
+                           grid);
         break;
     default:
-        hipLaunchKernelGGL((k_raster_tiles<64, 64>), dim3((unsigned)pl->ntiles), dim3(256), 0, s,
-                           depos, w.tile_count, w.list, pl->kp, ev, pl->ntt, grid);
+        hipLaunchKernelGGL((k_raster_tiles<64, 64>), dim3(grid_items), dim3(256), 0, s,
+                           w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
+                           grid);
         break;
     }
+    if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess)
+        return e;
     // Depos whose patch does not fit a tile region: one workgroup each, direct
     // atomics.  The grid is persistent over the device-side count.
     const unsigned lg = (unsigned)std::min<int64_t>(n, 2048);
     hipLaunchKernelGGL((k_patch_generic<256, false>), dim3(lg), dim3(256), 0, s, depos, w.large,
-                       w.counters + 1, (int64_t)0, pl->kp, ev, nullptr, nullptr, grid);
-    return hipGetLastError();
+                       w.counters + 1, (int64_t)0, pl->kp, evid, nullptr, nullptr, grid);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    return mark(2);
 }
 
 }  // namespace wcs

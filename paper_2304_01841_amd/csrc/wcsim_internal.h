@@ -53,6 +53,7 @@ struct FftPlan {
 };
 
 bool make_plan(int n, FftPlan *plan);     // factor n into radices {8,4,2,5,3}
+int twiddle_table_len(int count);         // entries of a two-level twiddle table
 int smallest_smooth_even(int nmin);      // smallest even n >= nmin with n/2 plannable
 
 // Raster tile shapes (pitch x tick tile; the LDS region adds a halo).
@@ -78,9 +79,9 @@ struct wcsim_plane {
     int Nfft, N2, H, F, C, L, V, nblocks;
     int Rp, Rt, r0;
     wcs::FftPlan planT, planL;
-    float2 *twT;     // exp(-2 pi i j / N2), j < N2
-    float2 *twHalf;  // exp(-2 pi i k / N'), k <= N2
-    float2 *twL;     // exp(-2 pi i j / L), j < L
+    float2 *twT;     // two-level table of exp(-2 pi i j / N2), j < N2
+    float2 *twHalf;  // two-level table of exp(-2 pi i k / N'), k <= N2
+    float2 *twL;     // two-level table of exp(-2 pi i j / L), j < L
     float2 *K;       // response spectrum [C][L][F], scaled by 1/(L N')
     int tile;
     wcs::TileShape ts;
@@ -123,24 +124,28 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
 
 // fused raster + LDS-staged scatter
 struct RasterWork {
-    int32_t *counters;    // [0] invalid, [1] large count
-    int32_t *tile_count;  // [ntiles + 1] -> exclusive offsets after the scan
-    int32_t *depo_tile;   // [n]
-    int32_t *depo_slot;   // [n]
-    int32_t *list;        // [n]
-    int32_t *large;       // [n]
-    void *scan_scratch;
+    int32_t *counters;    // [0] invalid depos, [1] large-patch depos, [2] tile work items
+    int32_t *tile_count;  // [ntiles + 1] counts -> exclusive list offsets
+    int2 *items;          // (tile, chunk) work items
+    int32_t *depo_tile;   // [n] tile of each depo (-1: none)
+    int32_t *depo_slot;   // [n] position in its tile's list
+    int32_t *large;       // [n] depos of the large-patch path
+    float *records;       // [n][64] depo records in tile-list order
 };
 size_t raster_work_bytes(const wcsim_plane *pl, int64_t n);
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base);
+// `ev` (nullable): 3 events recorded after binning, after the LDS-tiled
+// raster kernel and after the large-patch kernel.
 hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
                                uint64_t event_id, const RasterWork &w, float *grid,
-                               hipStream_t s);
+                               hipStream_t s, const hipEvent_t *ev = nullptr);
 
 // FFT convolution passes
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind);
+// `ev` (nullable): 3 events recorded after passes A, B and C.
 hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
-                           wcsim_out out_kind, void *work, hipStream_t s);
+                           wcsim_out out_kind, void *work, hipStream_t s,
+                           const hipEvent_t *ev = nullptr);
 hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void *work,
                                    hipStream_t s);
 size_t response_work_bytes(const wcsim_plane *pl);

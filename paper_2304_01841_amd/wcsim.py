@@ -94,6 +94,8 @@ _SIGS = {
     "wcsim_convolve": (_st, [_P, _P, _P, _i32, _P, _P]),
     "wcsim_simulate_workspace_bytes": (_sz, [_P, _i64, _i32]),
     "wcsim_simulate_event": (_st, [_P, _P, _i64, _i32, _u64, _P, _i32, _i32, _P, _P]),
+    "wcsim_simulate_event_profiled": (_st, [_P, _P, _i64, _i32, _u64, _P, _i32, _i32, _P, _P,
+                                            _P]),
     "wcsim_workspace_grid": (_P, [_P, _P, _i64]),
     "wcsim_workspace_invalid_count": (_st, [_P, _P, _P]),
     "wcsim_batch_workspace_bytes": (_sz, [_P, _P, _i32, _i32]),
@@ -333,6 +335,53 @@ def simulate_event(plane: Plane, depos, event_id: int = 0, out=None, kind: int =
                                      out_ptr, kind, out_mem, _dev_ptr(workspace, what="workspace"),
                                      _stream(stream)))
     return out
+
+
+NUM_STAGE_EVENTS = 8
+STAGE_NAMES = ("clear_grid", "bin_depos", "raster_tiles", "raster_large", "fft_ticks",
+               "conv_pitch", "ifft_ticks")
+
+
+def simulate_event_profiled(plane: Plane, depos: torch.Tensor, event_id: int, out: torch.Tensor,
+                            kind: int, workspace: torch.Tensor, events, stream=None):
+    """simulate_event (device output) recording the stage events (raw
+    hipEvent_t handles, NUM_STAGE_EVENTS of them) on `stream`."""
+    ptr, n, mem, _keep = _depo_arg(depos)
+    arr = (ctypes.c_void_p * NUM_STAGE_EVENTS)(*events)
+    _check(_lib.wcsim_simulate_event_profiled(plane.handle, ptr, n, mem,
+                                              int(event_id) & (2**64 - 1),
+                                              _dev_ptr(out, torch.float32, "out"), kind,
+                                              MEM_DEVICE, _dev_ptr(workspace, what="workspace"),
+                                              _stream(stream), arr))
+    return out
+
+
+class HipEvents:
+    """Raw HIP events from the HIP runtime (timing enabled)."""
+
+    def __init__(self, count: int):
+        self._hip = ctypes.CDLL("libamdhip64.so")
+        self._hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self._hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                  ctypes.c_void_p]
+        self._hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.handles = []
+        for _ in range(count):
+            h = ctypes.c_void_p()
+            if self._hip.hipEventCreate(ctypes.byref(h)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.handles.append(h.value)
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        ms = ctypes.c_float()
+        if self._hip.hipEventElapsedTime(ctypes.byref(ms), self.handles[a], self.handles[b]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def destroy(self):
+        for h in self.handles:
+            self._hip.hipEventDestroy(h)
+        self.handles = []
 
 
 def batch_workspace(planes, ns, kind: int = OUT_WIRE, device="cuda") -> torch.Tensor:

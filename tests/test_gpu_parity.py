@@ -173,6 +173,7 @@ def test_convolve_schedules_agree(ws):
     ref = O.convolve(G.astype(np.float64), R.astype(np.float64), 25)
     g = torch.from_numpy(G).cuda()
     for sc in ({}, {"fft_ticks": 1024}, {"fft_ticks": 1000, "freq_chunk": 8},
+               {"fft_pitch": 512, "freq_chunk": 16}, {"fft_ticks": 1250},
                {"fft_pitch": 128}, {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 240}):
         P = ws.Plane(pl, W.physics(False), R, r0=25, schedule=sc)
         out = ws.convolve(P, g, kind=ws.OUT_PITCH)
