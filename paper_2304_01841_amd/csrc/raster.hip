@@ -482,11 +482,11 @@ constexpr int kHaloP = 32, kHaloT = 16;   // LDS region = tile + halo
 constexpr int kRecP = kHaloP + 1;         // longest pitch window of the tile path
 constexpr int kRecT = kHaloT + 1;         // longest tick window of the tile path
 constexpr int kRecWords = 64;             // floats per depo record (256 bytes)
-constexpr int kRecWp = 8;                 // record offset of the pitch weights
+constexpr int kRecWp = 12;                // record offset of the pitch weights
 constexpr int kRecWt = kRecWp + kRecP;    // record offset of the tick weights
 static_assert(kRecWt + kRecT <= kRecWords, "depo record overflow");
-constexpr int kChunk = 64;                // depos per tile work item
-constexpr int kFluctItems = 4;            // Philox calls per lane held in registers
+constexpr int kChunk = 16;                // depos per tile work item (one wavefront)
+constexpr int kFluctItems = 4;            // work items per lane held in registers
 // A tile-path patch has at most kRecP * (kRecT / 4 + 2) = 231 Philox calls.
 static_assert(kRecP * (kRecT / 4 + 2) <= 64 * kFluctItems, "fluctuation items overflow");
 
@@ -561,71 +561,71 @@ __global__ __launch_bounds__(256) void k_prep_bin(const wcsim_depo *depos, int64
     }
 }
 
-// Exclusive scan of one int per thread over a 1024-thread block.
-__device__ int block1024_exclusive(int v, int *sh, int *total)
+// Tile schedule, two kernels over blocks of kSchedTiles tiles: per-tile depo
+// counts -> exclusive list offsets (in place, ntiles + 1 entries, the scan of
+// Sec. 4.3), and the list of (tile, chunk) work items of at most kChunk depos.
+// counters[2] = number of work items.
+constexpr int kSchedThreads = 256, kSchedPer = 16, kSchedTiles = kSchedThreads * kSchedPer;
+
+__device__ __forceinline__ int chunks_of(int count) { return (count + kChunk - 1) / kChunk; }
+
+// Block totals of depos and of work items.
+__global__ __launch_bounds__(kSchedThreads) void k_tile_sums(const int32_t *tile_count, int ntiles,
+                                                            int2 *block_tot)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int inc = v;
+    __shared__ int sh[kSchedThreads / 64];
+    const int first = blockIdx.x * kSchedTiles + threadIdx.x * kSchedPer;
+    int st = 0, sc = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(inc, o, 64);
-        if (lane >= o)
-            inc += u;
+    for (int k = 0; k < kSchedPer; ++k) {
+        const int idx = first + k;
+        const int c = (idx < ntiles) ? tile_count[idx] : 0;
+        st += c;
+        sc += chunks_of(c);
     }
-    if (lane == 63)
-        sh[wave] = inc;
-    __syncthreads();
-    int base = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        base += (k < wave) ? sh[k] : 0;
-        tot += sh[k];
-    }
-    __syncthreads();
-    *total = tot;
-    return base + inc - v;
+    int tot_t, tot_c;
+    block_exclusive_scan<int>(st, sh, &tot_t);
+    block_exclusive_scan<int>(sc, sh, &tot_c);
+    if (threadIdx.x == 0)
+        block_tot[blockIdx.x] = make_int2(tot_t, tot_c);
 }
 
-// One workgroup: per-tile depo counts -> exclusive list offsets (in place,
-// ntiles + 1 entries), and the list of (tile, chunk) work items of at most
-// kChunk depos each.  counters[2] = number of work items.
-constexpr int kSchedPer = 16;
-__global__ __launch_bounds__(1024) void k_tile_schedule(int32_t *tile_count, int ntiles,
-                                                        int2 *items, int32_t *counters)
+__global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_count, int ntiles,
+                                                                const int2 *block_tot,
+                                                                int2 *items, int32_t *counters)
 {
-    __shared__ int sh[16];
-    int carry_t = 0, carry_c = 0;
-    const int total_entries = ntiles + 1;
-    for (int base = 0; base < total_entries; base += 1024 * kSchedPer) {
-        const int first = base + threadIdx.x * kSchedPer;
-        int cnt[kSchedPer];
-        int sum_t = 0, sum_c = 0;
-#pragma unroll
-        for (int k = 0; k < kSchedPer; ++k) {
-            const int idx = first + k;
-            cnt[k] = (idx < ntiles) ? tile_count[idx] : 0;
-            sum_t += cnt[k];
-            sum_c += (cnt[k] + kChunk - 1) / kChunk;
-        }
-        int tot_t, tot_c;
-        int off_t = block1024_exclusive(sum_t, sh, &tot_t) + carry_t;
-        int off_c = block1024_exclusive(sum_c, sh, &tot_c) + carry_c;
-#pragma unroll
-        for (int k = 0; k < kSchedPer; ++k) {
-            const int idx = first + k;
-            if (idx < total_entries)
-                tile_count[idx] = off_t;
-            const int nch = (cnt[k] + kChunk - 1) / kChunk;
-            for (int j = 0; j < nch; ++j)
-                items[off_c + j] = make_int2(idx, j);
-            off_t += cnt[k];
-            off_c += nch;
-        }
-        carry_t += tot_t;
-        carry_c += tot_c;
+    __shared__ int sh[kSchedThreads / 64];
+    int base_t = 0, base_c = 0;
+    for (int b = 0; b < (int)blockIdx.x; ++b) {
+        base_t += block_tot[b].x;
+        base_c += block_tot[b].y;
     }
-    if (threadIdx.x == 0)
-        counters[2] = carry_c;
+    const int first = blockIdx.x * kSchedTiles + threadIdx.x * kSchedPer;
+    int cnt[kSchedPer];
+    int st = 0, sc = 0;
+#pragma unroll
+    for (int k = 0; k < kSchedPer; ++k) {
+        const int idx = first + k;
+        cnt[k] = (idx < ntiles) ? tile_count[idx] : 0;
+        st += cnt[k];
+        sc += chunks_of(cnt[k]);
+    }
+    int tot_t, tot_c;
+    int off_t = block_exclusive_scan<int>(st, sh, &tot_t) + base_t;
+    int off_c = block_exclusive_scan<int>(sc, sh, &tot_c) + base_c;
+#pragma unroll
+    for (int k = 0; k < kSchedPer; ++k) {
+        const int idx = first + k;
+        if (idx <= ntiles)
+            tile_count[idx] = off_t;
+        const int nch = chunks_of(cnt[k]);
+        for (int j = 0; j < nch; ++j)
+            items[off_c + j] = make_int2(idx, j);
+        off_t += cnt[k];
+        off_c += nch;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kSchedThreads - 1)
+        counters[2] = off_c;
 }
 
 // Weights of one axis computed by one thread into a record: erf at the n + 1
@@ -645,8 +645,18 @@ __device__ __forceinline__ void thread_axis_weights(int lo, int n, double mu, do
     }
 }
 
-// Depo records in tile-list order: header {lo_p, lo_t, n_p, n_t, depo index,
-// charge} and the two weight vectors.
+// floor(a / b) for 0 <= a < 4096 and 1 <= b <= 64 by a multiply-shift with
+// m = ceil(2^20 / b): the error term a (m b - 2^20) / (b 2^20) stays below 1/b.
+__device__ __forceinline__ int div_small(int a, int m) { return (int)(__umul24(a, m) >> 20); }
+__device__ __forceinline__ int magic_small(int b) { return ((1 << 20) + b - 1) / b; }
+
+// Depo records in tile-list order.  Header words: lo_p, lo_t, n_p, n_t, depo
+// index, charge (float), first tick quad, tick quads, the division magics of
+// the quad count and of n_t, the Philox work items n_p * quads and the bins
+// n_p * n_t; then the pitch and tick weight vectors.
+enum { kHLoP, kHLoT, kHNp, kHNt, kHDepo, kHQ, kHQlo, kHNq, kHMq, kHMt, kHItemsF, kHItemsP };
+static_assert(kHItemsP < kRecWp, "record header overflow");
+
 __global__ __launch_bounds__(256) void k_fill_records(const wcsim_depo *depos, int64_t n,
                                                       PlaneParams P, const int32_t *depo_tile,
                                                       const int32_t *depo_slot,
@@ -661,68 +671,73 @@ __global__ __launch_bounds__(256) void k_fill_records(const wcsim_depo *depos, i
     const int64_t pos = (int64_t)tile_off[t] + depo_slot[d];
     const Win w = depo_window(depos[d], P);
     float *rec = records + pos * kRecWords;
-    *(int4 *)rec = make_int4(w.lo_p, w.lo_t, w.n_p, w.n_t);
-    ((int *)rec)[4] = (int)d;
-    rec[5] = (float)w.q;
+    int *h = (int *)rec;
+    const int qlo = quad_of(w.lo_t), nq = quad_of(w.lo_t + w.n_t - 1) - qlo + 1;
+    *(int4 *)h = make_int4(w.lo_p, w.lo_t, w.n_p, w.n_t);
+    h[kHDepo] = (int)d;
+    rec[kHQ] = (float)w.q;
+    h[kHQlo] = qlo;
+    h[kHNq] = nq;
+    h[kHMq] = magic_small(nq);
+    h[kHMt] = magic_small(w.n_t);
+    h[kHItemsF] = w.n_p * nq;
+    h[kHItemsP] = w.n_p * w.n_t;
     thread_axis_weights(w.lo_p, w.n_p, w.mu_p, w.s_p, rec + kRecWp);
     thread_axis_weights(w.lo_t, w.n_t, w.mu_t, w.s_t, rec + kRecWt);
 }
 
-// floor(a / b) for 0 <= a < 4096 and 1 <= b <= 64 by a multiply-shift with
-// m = ceil(2^20 / b): the error term a (m b - 2^20) / (b 2^20) stays below 1/b.
-__device__ __forceinline__ int div_small(int a, int m) { return (a * m) >> 20; }
-__device__ __forceinline__ int magic_small(int b) { return ((1 << 20) + b - 1) / b; }
-
-// One workgroup per (tile, chunk of <= kChunk depos): the waves rasterize one
-// patch each at a time into the LDS copy of the tile region (tile + halo) and
-// the region's non-zero cells are then added to the grid with float atomics.
+// One wavefront per (tile, chunk of <= kChunk depos), rasterizing one patch
+// at a time into its own LDS copy of the tile region (tile + halo).  The bins
+// of one patch are distinct, so the deposits are plain read-add-write LDS
+// accesses; no other wavefront touches the region.  The region's non-zero
+// cells are then added to the grid with float atomics.
 template <int TP, int TT>
-__global__ __launch_bounds__(256) void k_raster_tiles(const float *__restrict__ records,
-                                                      const int2 *__restrict__ items,
-                                                      const int32_t *__restrict__ tile_off,
-                                                      const int32_t *__restrict__ counters,
-                                                      PlaneParams P, uint32_t event, int ntt,
-                                                      float *grid)
+__global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
+                                                     const int2 *__restrict__ items,
+                                                     const int32_t *__restrict__ tile_off,
+                                                     const int32_t *__restrict__ counters,
+                                                     PlaneParams P, uint32_t event, int ntt,
+                                                     float *grid)
 {
-    constexpr int RP = TP + kHaloP, RT = TT + kHaloT, NW = 4;
+    // Odd LDS row stride: the deposits of one wavefront step through rows and
+    // tick quads, and an even stride would fold them onto a few banks.
+    constexpr int RP = TP + kHaloP, RT = TT + kHaloT + 1;
     __shared__ float acc[RP * RT];
-    __shared__ float rsh[NW][kRecWords];
+    __shared__ float rec[kRecWords];
     if ((int)blockIdx.x >= counters[2])
         return;
     const int2 it2 = items[blockIdx.x];
     const int tile = it2.x;
     const int beg = tile_off[tile] + it2.y * kChunk;
     const int end = min(beg + kChunk, tile_off[tile + 1]);
-    for (int c = threadIdx.x; c < RP * RT; c += 256)
+    const int lane = threadIdx.x;
+    float next = records[(int64_t)beg * kRecWords + lane];
+    for (int c = lane; c < RP * RT; c += 64)
         acc[c] = 0.0f;
-    __syncthreads();
     const int p0 = (tile / ntt) * TP, t0 = (tile % ntt) * TT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float *rec = rsh[wave];
     const int *reci = (const int *)rec;
 
-    // The next record of this wave is loaded while the current patch is
-    // rasterized.
-    float next = (beg + wave < end) ? records[(int64_t)(beg + wave) * kRecWords + lane] : 0.0f;
-    for (int k = beg + wave; k < end; k += NW) {
+    for (int k = beg; k < end; ++k) {
         rec[lane] = next;
         wave_lds_sync();
-        if (k + NW < end)
-            next = records[(int64_t)(k + NW) * kRecWords + lane];
-        const int lo_p = reci[0], lo_t = reci[1], n_p = reci[2], n_t = reci[3], d = reci[4];
-        const float qf = rec[5];
+        // the next record is loaded while this patch is rasterized
+        if (k + 1 < end)
+            next = records[(int64_t)(k + 1) * kRecWords + lane];
+        const int lo_p = reci[kHLoP], lo_t = reci[kHLoT], n_t = reci[kHNt];
+        const int d = reci[kHDepo];
+        const float qf = rec[kHQ];
         const float *Wp = rec + kRecWp, *Wt = rec + kRecWt;
         if (!P.fluct) {
-            const int cnt = n_p * n_t, m = magic_small(n_t);
+            const int cnt = reci[kHItemsP], m = reci[kHMt];
             for (int it = lane; it < cnt; it += 64) {
                 const int i = div_small(it, m), j = it - i * n_t;
                 const int I = lo_p + i, J = lo_t + j;
                 if ((unsigned)I < (unsigned)P.Np && (unsigned)J < (unsigned)P.Nt)
-                    atomicAdd(&acc[(I - p0) * RT + (J - t0)], qf * Wp[i] * Wt[j]);
+                    acc[(I - p0) * RT + (J - t0)] += qf * Wp[i] * Wt[j];
             }
         } else {
-            const int qlo = quad_of(lo_t), nq = quad_of(lo_t + n_t - 1) - qlo + 1;
-            const int items_n = n_p * nq, m = magic_small(nq);
+            const int qlo = reci[kHQlo], nq = reci[kHNq];
+            const int items_n = reci[kHItemsF], m = reci[kHMq];
             float F[kFluctItems][4];
             float S = 0.0f;
 #pragma unroll
@@ -764,7 +779,7 @@ __global__ __launch_bounds__(256) void k_raster_tiles(const float *__restrict__ 
                             const int J = 4 * qd + mm, j = J - lo_t;
                             if (j >= 0 && j < n_t && (unsigned)J < (unsigned)P.Nt) {
                                 const float v = (S > 0.0f) ? F[b][mm] * scale : qf * Wp[i] * Wt[j];
-                                atomicAdd(&acc[(I - p0) * RT + (J - t0)], v);
+                                acc[(I - p0) * RT + (J - t0)] += v;
                             }
                         }
                     }
@@ -773,8 +788,7 @@ __global__ __launch_bounds__(256) void k_raster_tiles(const float *__restrict__ 
         }
         wave_lds_sync();  // the record buffer is rewritten by the next patch
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c < RP * RT; c += 256) {
+    for (int c = lane; c < RP * RT; c += 64) {
         const float v = acc[c];
         if (v != 0.0f) {
             const int I = p0 + c / RT, J = t0 + c % RT;
@@ -798,11 +812,11 @@ TileShape tile_shape(int id)
 {
     switch (id) {
     case 1:
-        return {64, 128, kHaloP, kHaloT};
-    case 2:
-        return {32, 128, kHaloP, kHaloT};
-    default:
         return {64, 64, kHaloP, kHaloT};
+    case 2:
+        return {32, 64, kHaloP, kHaloT};
+    default:
+        return {32, 32, kHaloP, kHaloT};
     }
 }
 
@@ -879,6 +893,11 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
     return hipGetLastError();
 }
 
+static size_t sched_blocks_of(const wcsim_plane *pl)
+{
+    return (size_t)((pl->ntiles + 1 + kSchedTiles - 1) / kSchedTiles);
+}
+
 static size_t items_cap(const wcsim_plane *pl, int64_t n)
 {
     return (size_t)pl->ntiles + (size_t)(std::max<int64_t>(n, 1) / kChunk) + 1;
@@ -888,8 +907,8 @@ size_t raster_work_bytes(const wcsim_plane *pl, int64_t n)
 {
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     return align_up(256) + align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1)) +
-           align_up(sizeof(int2) * items_cap(pl, n)) + 3 * align_up(sizeof(int32_t) * nn) +
-           align_up(sizeof(float) * kRecWords * nn);
+           align_up(sizeof(int2) * sched_blocks_of(pl)) + align_up(sizeof(int2) * items_cap(pl, n)) +
+           3 * align_up(sizeof(int32_t) * nn) + align_up(sizeof(float) * kRecWords * nn);
 }
 
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
@@ -901,6 +920,8 @@ RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
     p += align_up(256);
     w.tile_count = (int32_t *)p;
     p += align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1));
+    w.block_tot = (int2 *)p;
+    p += align_up(sizeof(int2) * sched_blocks_of(pl));
     w.items = (int2 *)p;
     p += align_up(sizeof(int2) * items_cap(pl, n));
     w.depo_tile = (int32_t *)p;
@@ -938,8 +959,11 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
     g.ntt = pl->ntt;
     hipLaunchKernelGGL(k_prep_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, depos, n, pl->kp, g,
                        w.counters, w.tile_count, w.depo_tile, w.depo_slot, w.large);
-    hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(1024), 0, s, w.tile_count, (int)pl->ntiles,
-                       w.items, w.counters);
+    const unsigned sched_blocks = (unsigned)((pl->ntiles + 1 + kSchedTiles - 1) / kSchedTiles);
+    hipLaunchKernelGGL(k_tile_sums, dim3(sched_blocks), dim3(kSchedThreads), 0, s, w.tile_count,
+                       (int)pl->ntiles, w.block_tot);
+    hipLaunchKernelGGL(k_tile_schedule, dim3(sched_blocks), dim3(kSchedThreads), 0, s,
+                       w.tile_count, (int)pl->ntiles, w.block_tot, w.items, w.counters);
     hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(n, 256)), dim3(256), 0, s, depos, n,
                        pl->kp, w.depo_tile, w.depo_slot, w.tile_count, w.records);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
@@ -948,17 +972,17 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
     const unsigned grid_items = (unsigned)items_cap(pl, n);
     switch (pl->tile) {
     case 1:
-        hipLaunchKernelGGL((k_raster_tiles<64, 128>), dim3(grid_items), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_raster_tiles<64, 64>), dim3(grid_items), dim3(64), 0, s,
                            w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
                            grid);
         break;
     case 2:
-        hipLaunchKernelGGL((k_raster_tiles<32, 128>), dim3(grid_items), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_raster_tiles<32, 64>), dim3(grid_items), dim3(64), 0, s,
                            w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
                            grid);
         break;
     default:
-        hipLaunchKernelGGL((k_raster_tiles<64, 64>), dim3(grid_items), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_raster_tiles<32, 32>), dim3(grid_items), dim3(64), 0, s,
                            w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
                            grid);
         break;

@@ -126,6 +126,7 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
 struct RasterWork {
     int32_t *counters;    // [0] invalid depos, [1] large-patch depos, [2] tile work items
     int32_t *tile_count;  // [ntiles + 1] counts -> exclusive list offsets
+    int2 *block_tot;      // per schedule block: depos and work items
     int2 *items;          // (tile, chunk) work items
     int32_t *depo_tile;   // [n] tile of each depo (-1: none)
     int32_t *depo_slot;   // [n] position in its tile's list
