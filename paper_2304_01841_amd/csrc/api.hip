@@ -618,14 +618,148 @@ wcsim_status wcsim_simulate_event_profiled(const wcsim_plane *pl, const wcsim_de
                           stream, (const hipEvent_t *)events);
 }
 
+}  // extern "C"
+
+namespace wcs {
+namespace {
+
+// Layout of a batch workspace for events `idx` (all of one schedule class).
+struct BatchLayout {
+    int64_t n_total = 0, ntiles_total = 0;
+    int nblk_r = 0, nblk_p = 0, nblk_c = 0;
+    size_t off_ev = 0, off_bases = 0, off_raster = 0, off_grid = 0, off_X = 0, off_Y = 0;
+    size_t grid_bytes = 0, total = 0;
+    std::vector<EventCtx> ev;
+    std::vector<int32_t> bases;  // 5 arrays of nev + 1
+};
+
+BatchLayout plan_batch(const wcsim_plane *const *planes, const int64_t *n,
+                       const std::vector<int> &idx, wcsim_out kind)
+{
+    BatchLayout L;
+    const int nev = (int)idx.size();
+    L.ev.resize((size_t)nev);
+    L.bases.assign(5 * (size_t)(nev + 1), 0);
+    int32_t *bd = &L.bases[0], *bt = bd + (nev + 1), *br = bt + (nev + 1), *bp = br + (nev + 1),
+            *bc = bp + (nev + 1);
+    size_t grid_off = 0, x_off = 0, y_off = 0;
+    for (int k = 0; k < nev; ++k) {
+        const wcsim_plane *pl = planes[idx[(size_t)k]];
+        const int64_t nout = (kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
+        EventCtx &e = L.ev[(size_t)k];
+        e = EventCtx{};
+        e.kp = pl->kp;
+        e.K = pl->K;
+        e.depo_base = L.n_total;
+        e.n = (int32_t)n[idx[(size_t)k]];
+        e.tile_base = (int32_t)L.ntiles_total;
+        e.ntt = pl->ntt;
+        e.nout = (int32_t)nout;
+        e.nblocks = pl->nblocks;
+        e.mode = (kind == WCSIM_OUT_WIRE) ? 1 : 0;
+        // device offsets, turned into pointers once the base is known
+        e.grid = (float *)(uintptr_t)grid_off;
+        e.X = (float2 *)(uintptr_t)x_off;
+        e.Y = (float2 *)(uintptr_t)y_off;
+        grid_off += align_up(sizeof(float) * (size_t)pl->Np * pl->Nt);
+        x_off += align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)pl->Np);
+        y_off += align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)nout);
+        bd[k] = (int32_t)L.n_total;
+        bt[k] = (int32_t)L.ntiles_total;
+        br[k] = L.nblk_r;
+        bp[k] = L.nblk_p;
+        bc[k] = L.nblk_c;
+        L.n_total += n[idx[(size_t)k]];
+        L.ntiles_total += pl->ntiles;
+        L.nblk_r += rows_blocks((int)pl->Np);
+        L.nblk_p += pitch_blocks_total(pl);
+        L.nblk_c += rows_blocks((int)nout);
+    }
+    bd[nev] = (int32_t)L.n_total;
+    bt[nev] = (int32_t)L.ntiles_total;
+    br[nev] = L.nblk_r;
+    bp[nev] = L.nblk_p;
+    bc[nev] = L.nblk_c;
+    const wcsim_plane *pl0 = planes[idx[0]];
+    L.off_ev = 0;
+    L.off_bases = align_up(sizeof(EventCtx) * (size_t)nev);
+    L.off_raster = L.off_bases + align_up(sizeof(int32_t) * L.bases.size());
+    L.off_grid = L.off_raster + raster_work_bytes_batch(pl0, L.n_total, L.ntiles_total);
+    L.grid_bytes = grid_off;
+    L.off_X = L.off_grid + grid_off;
+    L.off_Y = L.off_X + x_off;
+    L.total = L.off_Y + y_off;
+    return L;
+}
+
+// Pinned host staging of the descriptor tables of this thread's batches; the
+// event marks when the last upload from it has completed.
+struct HostStaging {
+    void *buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    ~HostStaging()
+    {
+        if (done)
+            (void)hipEventSynchronize(done);
+        if (buf)
+            (void)hipHostFree(buf);
+        if (done)
+            (void)hipEventDestroy(done);
+    }
+};
+thread_local HostStaging g_staging;
+
+wcsim_status stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s)
+{
+    HostStaging &h = g_staging;
+    if (!h.done)
+        WCS_HIP(hipEventCreateWithFlags(&h.done, hipEventDisableTiming));
+    WCS_HIP(hipEventSynchronize(h.done));  // the previous upload has left the buffer
+    if (h.cap < bytes) {
+        if (h.buf)
+            WCS_HIP(hipHostFree(h.buf));
+        h.buf = nullptr;
+        h.cap = 0;
+        WCS_HIP(hipHostMalloc(&h.buf, bytes, hipHostMallocDefault));
+        h.cap = bytes;
+    }
+    memcpy(h.buf, src, bytes);
+    WCS_HIP(hipMemcpyAsync(dst, h.buf, bytes, hipMemcpyHostToDevice, s));
+    WCS_HIP(hipEventRecord(h.done, s));
+    return WCSIM_OK;
+}
+
+std::vector<std::vector<int>> schedule_groups(const wcsim_plane *const *planes, int nevents)
+{
+    std::vector<std::vector<int>> groups;
+    for (int e = 0; e < nevents; ++e) {
+        bool placed = false;
+        for (auto &g : groups)
+            if (same_schedule_class(planes[g[0]], planes[e])) {
+                g.push_back(e);
+                placed = true;
+                break;
+            }
+        if (!placed)
+            groups.push_back({e});
+    }
+    return groups;
+}
+
+}  // namespace
+}  // namespace wcs
+
+extern "C" {
+
 size_t wcsim_batch_workspace_bytes(const wcsim_plane *const *planes, const int64_t *n,
                                    int32_t nevents, wcsim_out out_kind)
 {
     if (!planes || !n || nevents <= 0)
         return 0;
     size_t m = 0;
-    for (int32_t e = 0; e < nevents; ++e)
-        m = std::max(m, wcsim_simulate_workspace_bytes(planes[e], n[e], out_kind));
+    for (const auto &g : schedule_groups(planes, nevents))
+        m = std::max(m, plan_batch(planes, n, g, out_kind).total);
     return m;
 }
 
@@ -636,12 +770,55 @@ wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
 {
     if (!planes || !depos || !n || !event_ids || !outs || !workspace || nevents < 0)
         return fail(WCSIM_E_INVALID, "bad batch arguments");
+    if (out_kind != WCSIM_OUT_WIRE && out_kind != WCSIM_OUT_PITCH)
+        return fail(WCSIM_E_INVALID, "bad output kind");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(WCSIM_E_INVALID, "workspace must be 256-byte aligned");
+    int64_t n_all = 0;
     for (int32_t e = 0; e < nevents; ++e) {
-        wcsim_status st = wcsim_simulate_event(planes[e], depos[e], n[e], WCSIM_MEM_DEVICE,
-                                               event_ids[e], outs[e], out_kind, WCSIM_MEM_DEVICE,
-                                               workspace, stream);
+        if (!planes[e])
+            return fail(WCSIM_E_STATE, "NULL plane in batch");
+        if (n[e] < 0 || (n[e] > 0 && !depos[e]) || !outs[e])
+            return fail(WCSIM_E_INVALID, "bad depos or output of batch event " + std::to_string(e));
+        n_all += n[e];
+    }
+    if (n_all > (1LL << 31) - 1)
+        return fail(WCSIM_E_INVALID, "too many depos in one batch");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    for (const auto &g : schedule_groups(planes, nevents)) {
+        BatchLayout L = plan_batch(planes, n, g, out_kind);
+        const wcsim_plane *pl0 = planes[g[0]];
+        for (size_t k = 0; k < g.size(); ++k) {
+            EventCtx &e = L.ev[k];
+            e.depos = depos[g[k]];
+            e.event = (uint32_t)event_ids[g[k]];
+            e.out = outs[g[k]];
+            e.grid = (float *)(ws + L.off_grid + (uintptr_t)e.grid);
+            e.X = (float2 *)(ws + L.off_X + (uintptr_t)e.X);
+            e.Y = (float2 *)(ws + L.off_Y + (uintptr_t)e.Y);
+        }
+        std::vector<char> host(L.off_raster);
+        memcpy(host.data() + L.off_ev, L.ev.data(), sizeof(EventCtx) * L.ev.size());
+        memcpy(host.data() + L.off_bases, L.bases.data(), sizeof(int32_t) * L.bases.size());
+        wcsim_status st = stage_upload(host.data(), host.size(), ws, s);
         if (st != WCSIM_OK)
             return st;
+        const int nev = (int)g.size();
+        BatchTables bt;
+        bt.ev = (const EventCtx *)(ws + L.off_ev);
+        const int32_t *b0 = (const int32_t *)(ws + L.off_bases);
+        bt.depo_base = b0;
+        bt.tile_base = b0 + (nev + 1);
+        bt.rblk_base = b0 + 2 * (nev + 1);
+        bt.pblk_base = b0 + 3 * (nev + 1);
+        bt.cblk_base = b0 + 4 * (nev + 1);
+        bt.nev = nev;
+        const RasterWork rw =
+            raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, ws + L.off_raster);
+        WCS_HIP(launch_fill_zero(ws + L.off_grid, L.grid_bytes, s));
+        WCS_HIP(launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, s));
+        WCS_HIP(launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, s));
     }
     return WCSIM_OK;
 }

@@ -346,19 +346,42 @@ __device__ __forceinline__ void load_tables(const TwTables &t, float2 *la, float
 // frequencies above N2 zero.
 // LDS: rows [RPW][N2 + 1], then the N2 table, then the N' table.
 // ---------------------------------------------------------------------------
-template <class FFT>
-__global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(const float *__restrict__ in, int nrows,
-                                                  int ncols, int64_t in_stride, int N2, FFT fft,
-                                                  TwTables tw, float2 *__restrict__ X,
-                                                  int F_shift, int C, int rpw_shift)
+// Rows of one tick-axis forward launch; in a batch, taken from the event that
+// owns the workgroup.
+struct R2CIo {
+    const float *in;
+    int nrows, ncols;
+    int64_t in_stride;
+    float2 *X;
+};
+
+template <class FFT, bool BATCH>
+__global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTables bt, int N2,
+                                                              FFT fft, TwTables tw, int F_shift,
+                                                              int C, int rpw_shift)
 {
     extern __shared__ float2 lds[];
+    int blk = blockIdx.x;
+    if (BATCH) {
+        const int e = find_event(bt.rblk_base, bt.nev, blk);
+        const EventCtx &E = bt.ev[e];
+        io.in = E.grid;
+        io.nrows = E.kp.Np;
+        io.ncols = E.kp.Nt;
+        io.in_stride = E.kp.Nt;
+        io.X = E.X;
+        blk -= bt.rblk_base[e];
+    }
+    const float *__restrict__ in = io.in;
+    const int nrows = io.nrows, ncols = io.ncols;
+    const int64_t in_stride = io.in_stride;
+    float2 *__restrict__ X = io.X;
     const int RPW = 1 << rpw_shift;
     const int S = N2 + 1;
     float2 *tabN2 = lds + RPW * S;
     float2 *tabH = tabN2 + tw.na;
     load_tables(tw, tabN2, tabH);
-    const int row0 = blockIdx.x * RPW;
+    const int row0 = blk * RPW;
     const bool vec2 = ((ncols & 1) == 0) && ((in_stride & 1) == 0);
     for (int s = 0; s < RPW; ++s) {
         const int row = row0 + s;
@@ -427,20 +450,41 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(const float *__re
 // z_n = x_{2n} + i x_{2n+1}.  The inverse runs as a forward transform of
 // conj(Z) (conj of the result).
 // ---------------------------------------------------------------------------
-template <class FFT>
-__global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(const float2 *__restrict__ Y, int nrows,
-                                                  int N2, FFT fft, TwTables tw,
-                                                  float *__restrict__ out, int ncols,
-                                                  int64_t out_stride, int F_shift, int C,
-                                                  int rpw_shift)
+struct C2RIo {
+    const float2 *Y;
+    int nrows;
+    float *out;
+    int ncols;
+    int64_t out_stride;
+};
+
+template <class FFT, bool BATCH>
+__global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(C2RIo io, BatchTables bt, int N2,
+                                                              FFT fft, TwTables tw, int F_shift,
+                                                              int C, int rpw_shift)
 {
     extern __shared__ float2 lds[];
+    int blk = blockIdx.x;
+    if (BATCH) {
+        const int e = find_event(bt.cblk_base, bt.nev, blk);
+        const EventCtx &E = bt.ev[e];
+        io.Y = E.Y;
+        io.nrows = E.nout;
+        io.out = E.out;
+        io.ncols = E.kp.Nt;
+        io.out_stride = E.kp.Nt;
+        blk -= bt.cblk_base[e];
+    }
+    const float2 *__restrict__ Y = io.Y;
+    const int nrows = io.nrows, ncols = io.ncols;
+    float *__restrict__ out = io.out;
+    const int64_t out_stride = io.out_stride;
     const int RPW = 1 << rpw_shift;
     const int S = N2 + 1;
     float2 *tabN2 = lds + RPW * S;
     float2 *tabH = tabN2 + tw.na;
     load_tables(tw, tabN2, tabH);
-    const int row0 = blockIdx.x * RPW;
+    const int row0 = blk * RPW;
     const int F = 1 << F_shift;
     const int total = C << (F_shift + rpw_shift);
     batched_copy(
@@ -511,16 +555,42 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(const float2 *__r
 // re-read from that XCD's L2.
 // LDS: the block [L][F], then the L table.
 // ---------------------------------------------------------------------------
-template <class FFT>
-__global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(const float2 *__restrict__ X, int nrows_in,
-                                                    const float2 *__restrict__ K,
-                                                    float2 *__restrict__ Y, int nrows_out, int L,
-                                                    int V, int Rp, int r0, int nblocks, int C,
-                                                    int F_shift, FFT fft, TwTables tw, int mode,
-                                                    int nimpact, float scale)
+struct PitchIo {
+    const float2 *X;
+    int nrows_in;
+    const float2 *K;
+    float2 *Y;
+    int nrows_out, nblocks, mode;
+};
+
+template <class FFT, bool BATCH>
+__global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, BatchTables bt, int L,
+                                                                int V, int Rp, int r0, int C,
+                                                                int F_shift, FFT fft, TwTables tw,
+                                                                int nimpact, float scale)
 {
     extern __shared__ float2 lds[];
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    int gblk = blockIdx.x;
+    if (BATCH) {
+        // every event's range is a multiple of 8 workgroups, so the XCD of a
+        // workgroup is the same in global and event-local numbering
+        const int e = find_event(bt.pblk_base, bt.nev, gblk);
+        const EventCtx &E = bt.ev[e];
+        io.X = E.X;
+        io.nrows_in = E.kp.Np;
+        io.K = E.K;
+        io.Y = E.Y;
+        io.nrows_out = E.nout;
+        io.nblocks = E.nblocks;
+        io.mode = E.mode;
+        gblk -= bt.pblk_base[e];
+    }
+    const float2 *__restrict__ X = io.X;
+    const int nrows_in = io.nrows_in, nrows_out = io.nrows_out, nblocks = io.nblocks;
+    const int mode = io.mode;
+    const float2 *__restrict__ K = io.K;
+    float2 *__restrict__ Y = io.Y;
+    const int xcd = gblk & 7, slot = gblk >> 3;
     const int lc = slot / nblocks, blk = slot - lc * nblocks;
     const int c = lc * 8 + xcd;
     if (c >= C)
@@ -614,27 +684,25 @@ TwTables tick_tables(const wcsim_plane *pl)
     return {pl->twT, table_len(pl->N2), pl->twHalf, table_len(pl->N2 + 1)};
 }
 
-template <class FFT>
-void launch_r2c(const wcsim_plane *pl, FFT fft, int threads, const float *in, int nrows,
-                int ncols, int64_t in_stride, float2 *X, hipStream_t s)
+// `blocks` = workgroups of the launch; a batch passes its total and tables.
+template <class FFT, bool B>
+void launch_r2c(const wcsim_plane *pl, FFT fft, int threads, const R2CIo &io,
+                const BatchTables &bt, unsigned blocks, hipStream_t s)
 {
     const TwTables tw = tick_tables(pl);
     const size_t lds = sizeof(float2) * ((size_t)(pl->N2 + 1) * kRowsPerBlock + tw.na + tw.nb);
-    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
-    hipLaunchKernelGGL(k_rows_r2c<FFT>, dim3(blocks), dim3(threads), lds, s, in, nrows, ncols,
-                       in_stride, pl->N2, fft, tw, X, ilog2(pl->F), pl->C, ilog2(kRowsPerBlock));
+    hipLaunchKernelGGL((k_rows_r2c<FFT, B>), dim3(blocks), dim3(threads), lds, s, io, bt, pl->N2,
+                       fft, tw, ilog2(pl->F), pl->C, ilog2(kRowsPerBlock));
 }
 
-template <class FFT>
-void launch_c2r(const wcsim_plane *pl, FFT fft, int threads, const float2 *Y, int nrows,
-                float *out, int ncols, int64_t out_stride, hipStream_t s)
+template <class FFT, bool B>
+void launch_c2r(const wcsim_plane *pl, FFT fft, int threads, const C2RIo &io,
+                const BatchTables &bt, unsigned blocks, hipStream_t s)
 {
     const TwTables tw = tick_tables(pl);
     const size_t lds = sizeof(float2) * ((size_t)(pl->N2 + 1) * kRowsPerBlock + tw.na + tw.nb);
-    const unsigned blocks = (unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
-    hipLaunchKernelGGL(k_rows_c2r<FFT>, dim3(blocks), dim3(threads), lds, s, Y, nrows, pl->N2,
-                       fft, tw, out, ncols, out_stride, ilog2(pl->F), pl->C,
-                       ilog2(kRowsPerBlock));
+    hipLaunchKernelGGL((k_rows_c2r<FFT, B>), dim3(blocks), dim3(threads), lds, s, io, bt, pl->N2,
+                       fft, tw, ilog2(pl->F), pl->C, ilog2(kRowsPerBlock));
 }
 
 bool plan_is(const FftPlan &p, std::initializer_list<int> radices)
@@ -668,59 +736,81 @@ int pitch_threads(const wcsim_plane *pl)
     return std::min(1024, std::max(256, threads_for(pl->planL, pl->F)));
 }
 
+template <bool B>
+hipError_t rows_r2c_any(const wcsim_plane *pl, const R2CIo &io, const BatchTables &bt,
+                        unsigned blocks, hipStream_t s)
+{
+    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
+        launch_r2c<TickCt3125, B>(pl, TickCt3125(), TickCt3125::kThreads, io, bt, blocks, s);
+    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
+        launch_r2c<TickCt600, B>(pl, TickCt600(), TickCt600::kThreads, io, bt, blocks, s);
+    else
+        launch_r2c<FftRt, B>(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
+                             tick_threads(pl), io, bt, blocks, s);
+    return hipGetLastError();
+}
+
+template <bool B>
+hipError_t rows_c2r_any(const wcsim_plane *pl, const C2RIo &io, const BatchTables &bt,
+                        unsigned blocks, hipStream_t s)
+{
+    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
+        launch_c2r<TickCt3125, B>(pl, TickCt3125(), TickCt3125::kThreads, io, bt, blocks, s);
+    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
+        launch_c2r<TickCt600, B>(pl, TickCt600(), TickCt600::kThreads, io, bt, blocks, s);
+    else
+        launch_c2r<FftRt, B>(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
+                             tick_threads(pl), io, bt, blocks, s);
+    return hipGetLastError();
+}
+
 hipError_t rows_r2c(const wcsim_plane *pl, const float *in, int nrows, int ncols,
                     int64_t in_stride, float2 *X, hipStream_t s)
 {
-    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
-        launch_r2c(pl, TickCt3125(), TickCt3125::kThreads, in, nrows, ncols, in_stride, X, s);
-    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
-        launch_r2c(pl, TickCt600(), TickCt600::kThreads, in, nrows, ncols, in_stride, X, s);
-    else
-        launch_r2c(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
-                   tick_threads(pl), in, nrows, ncols, in_stride, X, s);
-    return hipGetLastError();
+    const R2CIo io = {in, nrows, ncols, in_stride, X};
+    return rows_r2c_any<false>(pl, io, BatchTables{}, (unsigned)rows_blocks(nrows), s);
 }
 
 hipError_t rows_c2r(const wcsim_plane *pl, const float2 *Y, int nrows, float *out, int ncols,
                     int64_t out_stride, hipStream_t s)
 {
-    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
-        launch_c2r(pl, TickCt3125(), TickCt3125::kThreads, Y, nrows, out, ncols, out_stride, s);
-    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
-        launch_c2r(pl, TickCt600(), TickCt600::kThreads, Y, nrows, out, ncols, out_stride, s);
-    else
-        launch_c2r(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
-                   tick_threads(pl), Y, nrows, out, ncols, out_stride, s);
-    return hipGetLastError();
+    const C2RIo io = {Y, nrows, out, ncols, out_stride};
+    return rows_c2r_any<false>(pl, io, BatchTables{}, (unsigned)rows_blocks(nrows), s);
 }
 
-template <class FFT>
-void launch_pitch(const wcsim_plane *pl, FFT fft, int threads, const float2 *X, int nrows_in,
-                  const float2 *K, float2 *Y, int nrows_out, int nblocks, int mode, float scale,
-                  hipStream_t s)
+template <class FFT, bool B>
+void launch_pitch(const wcsim_plane *pl, FFT fft, int threads, const PitchIo &io,
+                  const BatchTables &bt, unsigned blocks, float scale, hipStream_t s)
 {
     const TwTables tw = {pl->twL, table_len(pl->L), nullptr, 0};
     const size_t lds = sizeof(float2) * ((size_t)pl->L * pl->F + tw.na);
-    const int xcd_chunks = (pl->C + 7) / 8;
-    const unsigned blocks = (unsigned)(8 * xcd_chunks * nblocks);
-    hipLaunchKernelGGL(k_pitch_conv<FFT>, dim3(blocks), dim3(threads), lds, s, X, nrows_in, K, Y,
-                       nrows_out, pl->L, pl->V, pl->Rp, pl->r0, nblocks, pl->C, ilog2(pl->F), fft,
-                       tw, mode, (int)pl->kp.nimpact, scale);
+    hipLaunchKernelGGL((k_pitch_conv<FFT, B>), dim3(blocks), dim3(threads), lds, s, io, bt,
+                       pl->L, pl->V, pl->Rp, pl->r0, pl->C, ilog2(pl->F), fft, tw,
+                       (int)pl->kp.nimpact, scale);
+}
+
+template <bool B>
+hipError_t pitch_any(const wcsim_plane *pl, const PitchIo &io, const BatchTables &bt,
+                     unsigned blocks, float scale, hipStream_t s)
+{
+    if (pl->L == 1024 && pl->F == 8 && plan_is(pl->planL, {8, 8, 4, 4}))
+        launch_pitch<PitchCt1024x8, B>(pl, PitchCt1024x8(), PitchCt1024x8::kThreads, io, bt,
+                                       blocks, scale, s);
+    else if (pl->L == 512 && pl->F == 16 && plan_is(pl->planL, {8, 8, 8}))
+        launch_pitch<PitchCt512x16, B>(pl, PitchCt512x16(), PitchCt512x16::kThreads, io, bt,
+                                       blocks, scale, s);
+    else
+        launch_pitch<FftRt, B>(pl, runtime_fft(pl->planL, ilog2(pl->F), 1, pl->F),
+                               pitch_threads(pl), io, bt, blocks, scale, s);
+    return hipGetLastError();
 }
 
 hipError_t pitch_pass(const wcsim_plane *pl, const float2 *X, int nrows_in, const float2 *K,
                       float2 *Y, int nrows_out, int nblocks, int mode, float scale, hipStream_t s)
 {
-    if (pl->L == 1024 && pl->F == 8 && plan_is(pl->planL, {8, 8, 4, 4}))
-        launch_pitch(pl, PitchCt1024x8(), PitchCt1024x8::kThreads, X, nrows_in, K, Y, nrows_out,
-                     nblocks, mode, scale, s);
-    else if (pl->L == 512 && pl->F == 16 && plan_is(pl->planL, {8, 8, 8}))
-        launch_pitch(pl, PitchCt512x16(), PitchCt512x16::kThreads, X, nrows_in, K, Y, nrows_out,
-                     nblocks, mode, scale, s);
-    else
-        launch_pitch(pl, runtime_fft(pl->planL, ilog2(pl->F), 1, pl->F), pitch_threads(pl), X,
-                     nrows_in, K, Y, nrows_out, nblocks, mode, scale, s);
-    return hipGetLastError();
+    const PitchIo io = {X, nrows_in, K, Y, nrows_out, nblocks, mode};
+    const unsigned blocks = (unsigned)(8 * ((pl->C + 7) / 8) * nblocks);
+    return pitch_any<false>(pl, io, BatchTables{}, blocks, scale, s);
 }
 
 }  // namespace
@@ -786,6 +876,31 @@ int smallest_smooth_even(int nmin)
 }
 
 int twiddle_table_len(int m) { return table_len(m); }
+
+int rows_blocks(int nrows) { return (nrows + kRowsPerBlock - 1) / kRowsPerBlock; }
+
+int pitch_blocks_total(const wcsim_plane *pl)
+{
+    return 8 * ((pl->C + 7) / 8) * pl->nblocks;
+}
+
+bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b)
+{
+    return a->Nfft == b->Nfft && a->L == b->L && a->F == b->F && a->Rp == b->Rp &&
+           a->Rt == b->Rt && a->r0 == b->r0 && a->tile == b->tile && a->Nt == b->Nt &&
+           a->kp.nimpact == b->kp.nimpact && a->device == b->device;
+}
+
+hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
+                                 int nblk_p, int nblk_c, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = rows_r2c_any<true>(pl, R2CIo{}, bt, (unsigned)nblk_r, s)) != hipSuccess)
+        return e;
+    if ((e = pitch_any<true>(pl, PitchIo{}, bt, (unsigned)nblk_p, 1.0f, s)) != hipSuccess)
+        return e;
+    return rows_c2r_any<true>(pl, C2RIo{}, bt, (unsigned)nblk_c, s);
+}
 
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind)
 {

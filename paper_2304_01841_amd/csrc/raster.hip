@@ -361,21 +361,24 @@ __device__ void block_axis_weights(int lo, int n, double mu, double s, float *W,
 // With fluctuation the rescaling needs the patch total before any value is
 // final: FLAT stores the clamped draws and rescales them in place; the grid
 // variant draws twice (same counters, same numbers).
-template <int NT, bool FLAT>
-__global__ __launch_bounds__(NT) void k_patch_generic(const wcsim_depo *depos,
+template <int NT, bool FLAT, bool B>
+__global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables bt,
                                                       const int32_t *index_list,
                                                       const int32_t *list_count, int64_t n_direct,
-                                                      PlaneParams P, uint32_t event,
-                                                      const int64_t *offsets, float *values,
-                                                      float *grid)
+                                                      const int64_t *offsets, float *values)
 {
     __shared__ float Wp[kMaxWindow], Wt[kMaxWindow];
     __shared__ double E[kMaxWindow + 1];
     __shared__ double red[NT / 64];
     const int64_t count = index_list ? (int64_t)*list_count : n_direct;
     for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
-        const int d = index_list ? index_list[k] : (int)k;
-        const Win w = depo_window(depos[d], P);
+        const int gd = index_list ? index_list[k] : (int)k;
+        const EventCtx &Ev = B ? bt.ev[find_event(bt.depo_base, bt.nev, gd)] : e0;
+        const PlaneParams &P = Ev.kp;
+        const uint32_t event = Ev.event;
+        float *grid = Ev.grid;
+        const int d = gd - (int)Ev.depo_base;  // index in the event's own depo array
+        const Win w = depo_window(Ev.depos[d], P);
         if (w.status != 0)
             continue;
         block_axis_weights<NT>(w.lo_p, w.n_p, w.mu_p, w.s_p, Wp, E, red);
@@ -506,8 +509,12 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane
 
 // Window and tile of every depo.  Slots in a tile's list come from one atomic
 // per distinct tile per wavefront (consecutive depos of a track share tiles).
-__global__ __launch_bounds__(256) void k_prep_bin(const wcsim_depo *depos, int64_t n,
-                                                  PlaneParams P, TileGeom g, int32_t *counters,
+// Depos and tiles carry global indices: in a batch, depo gd belongs to the
+// event whose depo_base range holds it, and tile numbers continue across
+// events from each event's tile_base.
+template <bool B>
+__global__ __launch_bounds__(256) void k_prep_bin(EventCtx e0, BatchTables bt, int64_t ntotal,
+                                                  TileGeom g, int32_t *counters,
                                                   int32_t *tile_count, int32_t *depo_tile,
                                                   int32_t *depo_slot, int32_t *large)
 {
@@ -515,15 +522,17 @@ __global__ __launch_bounds__(256) void k_prep_bin(const wcsim_depo *depos, int64
     const int lane = threadIdx.x & 63;
     int tile = -1;
     bool bad = false, big = false;
-    if (d < n) {
-        const Win w = depo_window(depos[d], P);
+    if (d < ntotal) {
+        const EventCtx &E = B ? bt.ev[find_event(bt.depo_base, bt.nev, (int)d)] : e0;
+        const PlaneParams &P = E.kp;
+        const Win w = depo_window(E.depos[d - E.depo_base], P);
         if (w.status == 1 || w.status == 3) {
             bad = true;
         } else if (w.status == 0) {
             const int tp = min(max(w.lo_p, 0), P.Np - 1) / g.tp;
             const int tt = min(max(w.lo_t, 0), P.Nt - 1) / g.tt;
             if (fits_tile(w, tp * g.tp, tt * g.tt, g, P))
-                tile = tp * g.ntt + tt;
+                tile = E.tile_base + tp * E.ntt + tt;
             else
                 big = true;
         }
@@ -555,7 +564,7 @@ __global__ __launch_bounds__(256) void k_prep_bin(const wcsim_depo *depos, int64
             slot = base + __popcll(same & lanemask_lt(lane));
         active &= ~same;
     }
-    if (d < n) {
+    if (d < ntotal) {
         depo_tile[d] = tile;
         depo_slot[d] = slot;
     }
@@ -657,19 +666,22 @@ __device__ __forceinline__ int magic_small(int b) { return ((1 << 20) + b - 1) /
 enum { kHLoP, kHLoT, kHNp, kHNt, kHDepo, kHQ, kHQlo, kHNq, kHMq, kHMt, kHItemsF, kHItemsP };
 static_assert(kHItemsP < kRecWp, "record header overflow");
 
-__global__ __launch_bounds__(256) void k_fill_records(const wcsim_depo *depos, int64_t n,
-                                                      PlaneParams P, const int32_t *depo_tile,
+template <bool B>
+__global__ __launch_bounds__(256) void k_fill_records(EventCtx e0, BatchTables bt, int64_t ntotal,
+                                                      const int32_t *depo_tile,
                                                       const int32_t *depo_slot,
                                                       const int32_t *tile_off, float *records)
 {
-    const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (d >= n)
+    const int64_t gd = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gd >= ntotal)
         return;
-    const int t = depo_tile[d];
+    const int t = depo_tile[gd];
     if (t < 0)
         return;
-    const int64_t pos = (int64_t)tile_off[t] + depo_slot[d];
-    const Win w = depo_window(depos[d], P);
+    const EventCtx &E = B ? bt.ev[find_event(bt.depo_base, bt.nev, (int)gd)] : e0;
+    const int64_t d = gd - E.depo_base;  // index in the event's own depo array
+    const int64_t pos = (int64_t)tile_off[t] + depo_slot[gd];
+    const Win w = depo_window(E.depos[d], E.kp);
     float *rec = records + pos * kRecWords;
     int *h = (int *)rec;
     const int qlo = quad_of(w.lo_t), nq = quad_of(w.lo_t + w.n_t - 1) - qlo + 1;
@@ -691,13 +703,12 @@ __global__ __launch_bounds__(256) void k_fill_records(const wcsim_depo *depos, i
 // of one patch are distinct, so the deposits are plain read-add-write LDS
 // accesses; no other wavefront touches the region.  The region's non-zero
 // cells are then added to the grid with float atomics.
-template <int TP, int TT>
+template <int TP, int TT, bool B>
 __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
                                                      const int2 *__restrict__ items,
                                                      const int32_t *__restrict__ tile_off,
                                                      const int32_t *__restrict__ counters,
-                                                     PlaneParams P, uint32_t event, int ntt,
-                                                     float *grid)
+                                                     EventCtx e0, BatchTables bt)
 {
     // Odd LDS row stride: the deposits of one wavefront step through rows and
     // tick quads, and an even stride would fold them onto a few banks.
@@ -714,7 +725,12 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     float next = records[(int64_t)beg * kRecWords + lane];
     for (int c = lane; c < RP * RT; c += 64)
         acc[c] = 0.0f;
-    const int p0 = (tile / ntt) * TP, t0 = (tile % ntt) * TT;
+    const EventCtx &E = B ? bt.ev[find_event(bt.tile_base, bt.nev, tile)] : e0;
+    const PlaneParams P = E.kp;
+    const uint32_t event = E.event;
+    float *grid = E.grid;
+    const int local = tile - E.tile_base;
+    const int p0 = (local / E.ntt) * TP, t0 = (local % E.ntt) * TT;
     const int *reci = (const int *)rec;
 
     for (int k = beg; k < end; ++k) {
@@ -798,6 +814,22 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     }
 }
 
+// Descriptor of a single event (kernel argument; no table lookups).
+EventCtx single_event(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                      uint64_t event_id, float *grid)
+{
+    EventCtx e{};
+    e.kp = pl->kp;
+    e.depos = depos;
+    e.grid = grid;
+    e.depo_base = 0;
+    e.n = (int32_t)n;
+    e.event = (uint32_t)event_id;
+    e.tile_base = 0;
+    e.ntt = pl->ntt;
+    return e;
+}
+
 unsigned blocks_for(int64_t n, int threads)
 {
     return (unsigned)((n + threads - 1) / threads);
@@ -877,8 +909,9 @@ hipError_t launch_patch_values(const wcsim_plane *pl, const wcsim_depo *depos, i
     if (n <= 0)
         return hipSuccess;
     const unsigned grid = (unsigned)std::min<int64_t>(n, 1 << 20);
-    hipLaunchKernelGGL((k_patch_generic<64, true>), dim3(grid), dim3(64), 0, s, depos, nullptr,
-                       nullptr, n, pl->kp, (uint32_t)event_id, offsets, values, nullptr);
+    const EventCtx e0 = single_event(pl, depos, n, event_id, nullptr);
+    hipLaunchKernelGGL((k_patch_generic<64, true, false>), dim3(grid), dim3(64), 0, s, e0,
+                       BatchTables{}, nullptr, nullptr, n, offsets, values);
     return hipGetLastError();
 }
 
@@ -893,37 +926,40 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
     return hipGetLastError();
 }
 
-static size_t sched_blocks_of(const wcsim_plane *pl)
+static size_t sched_blocks_of(int64_t ntiles)
 {
-    return (size_t)((pl->ntiles + 1 + kSchedTiles - 1) / kSchedTiles);
+    return (size_t)((ntiles + 1 + kSchedTiles - 1) / kSchedTiles);
 }
 
-static size_t items_cap(const wcsim_plane *pl, int64_t n)
+static size_t items_cap(int64_t ntiles, int64_t n)
 {
-    return (size_t)pl->ntiles + (size_t)(std::max<int64_t>(n, 1) / kChunk) + 1;
+    return (size_t)ntiles + (size_t)(std::max<int64_t>(n, 1) / kChunk) + 1;
 }
 
-size_t raster_work_bytes(const wcsim_plane *pl, int64_t n)
+size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles)
 {
+    (void)pl;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
-    return align_up(256) + align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1)) +
-           align_up(sizeof(int2) * sched_blocks_of(pl)) + align_up(sizeof(int2) * items_cap(pl, n)) +
-           3 * align_up(sizeof(int32_t) * nn) + align_up(sizeof(float) * kRecWords * nn);
+    return align_up(256) + align_up(sizeof(int32_t) * (size_t)(ntiles + 1)) +
+           align_up(sizeof(int2) * sched_blocks_of(ntiles)) +
+           align_up(sizeof(int2) * items_cap(ntiles, n)) + 3 * align_up(sizeof(int32_t) * nn) +
+           align_up(sizeof(float) * kRecWords * nn);
 }
 
-RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
+RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles, void *base)
 {
+    (void)pl;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     char *p = (char *)base;
     RasterWork w;
     w.counters = (int32_t *)p;
     p += align_up(256);
     w.tile_count = (int32_t *)p;
-    p += align_up(sizeof(int32_t) * (size_t)(pl->ntiles + 1));
+    p += align_up(sizeof(int32_t) * (size_t)(ntiles + 1));
     w.block_tot = (int2 *)p;
-    p += align_up(sizeof(int2) * sched_blocks_of(pl));
+    p += align_up(sizeof(int2) * sched_blocks_of(ntiles));
     w.items = (int2 *)p;
-    p += align_up(sizeof(int2) * items_cap(pl, n));
+    p += align_up(sizeof(int2) * items_cap(ntiles, n));
     w.depo_tile = (int32_t *)p;
     p += align_up(sizeof(int32_t) * nn);
     w.depo_slot = (int32_t *)p;
@@ -934,15 +970,29 @@ RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
     return w;
 }
 
-hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
-                               uint64_t event_id, const RasterWork &w, float *grid, hipStream_t s,
-                               const hipEvent_t *ev)
+size_t raster_work_bytes(const wcsim_plane *pl, int64_t n)
+{
+    return raster_work_bytes_batch(pl, n, pl->ntiles);
+}
+
+RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
+{
+    return raster_work_carve_batch(pl, n, pl->ntiles, base);
+}
+
+// The launch sequence shared by single events and batches: clear counters,
+// window + tile per depo, tile schedule, depo records, LDS-tiled raster,
+// large-patch raster.  `ev` (single events only) receives three stage marks.
+template <bool B>
+static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
+                                  const BatchTables &bt, int64_t n, int64_t ntiles,
+                                  const RasterWork &w, hipStream_t s, const hipEvent_t *ev)
 {
     hipError_t e;
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     // counters and tile counts are adjacent: one clear
     const size_t clear = (size_t)((char *)w.tile_count - (char *)w.counters) +
-                         sizeof(int32_t) * (size_t)(pl->ntiles + 1);
+                         sizeof(int32_t) * (size_t)(ntiles + 1);
     if ((e = launch_fill_zero(w.counters, align_up(clear, 16), s)) != hipSuccess)
         return e;
     if (n <= 0) {
@@ -957,34 +1007,30 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
     g.rp = pl->ts.tp + kHaloP;
     g.rt = pl->ts.tt + kHaloT;
     g.ntt = pl->ntt;
-    hipLaunchKernelGGL(k_prep_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, depos, n, pl->kp, g,
+    hipLaunchKernelGGL(k_prep_bin<B>, dim3(blocks_for(n, 256)), dim3(256), 0, s, e0, bt, n, g,
                        w.counters, w.tile_count, w.depo_tile, w.depo_slot, w.large);
-    const unsigned sched_blocks = (unsigned)((pl->ntiles + 1 + kSchedTiles - 1) / kSchedTiles);
+    const unsigned sched_blocks = (unsigned)sched_blocks_of(ntiles);
     hipLaunchKernelGGL(k_tile_sums, dim3(sched_blocks), dim3(kSchedThreads), 0, s, w.tile_count,
-                       (int)pl->ntiles, w.block_tot);
+                       (int)ntiles, w.block_tot);
     hipLaunchKernelGGL(k_tile_schedule, dim3(sched_blocks), dim3(kSchedThreads), 0, s,
-                       w.tile_count, (int)pl->ntiles, w.block_tot, w.items, w.counters);
-    hipLaunchKernelGGL(k_fill_records, dim3(blocks_for(n, 256)), dim3(256), 0, s, depos, n,
-                       pl->kp, w.depo_tile, w.depo_slot, w.tile_count, w.records);
+                       w.tile_count, (int)ntiles, w.block_tot, w.items, w.counters);
+    hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 256)), dim3(256), 0, s, e0, bt, n,
+                       w.depo_tile, w.depo_slot, w.tile_count, w.records);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
-    const uint32_t evid = (uint32_t)event_id;
-    const unsigned grid_items = (unsigned)items_cap(pl, n);
+    const unsigned grid_items = (unsigned)items_cap(ntiles, n);
     switch (pl->tile) {
     case 1:
-        hipLaunchKernelGGL((k_raster_tiles<64, 64>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
-                           grid);
+        hipLaunchKernelGGL((k_raster_tiles<64, 64, B>), dim3(grid_items), dim3(64), 0, s,
+                           w.records, w.items, w.tile_count, w.counters, e0, bt);
         break;
     case 2:
-        hipLaunchKernelGGL((k_raster_tiles<32, 64>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
-                           grid);
+        hipLaunchKernelGGL((k_raster_tiles<32, 64, B>), dim3(grid_items), dim3(64), 0, s,
+                           w.records, w.items, w.tile_count, w.counters, e0, bt);
         break;
     default:
-        hipLaunchKernelGGL((k_raster_tiles<32, 32>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.tile_count, w.counters, pl->kp, evid, pl->ntt,
-                           grid);
+        hipLaunchKernelGGL((k_raster_tiles<32, 32, B>), dim3(grid_items), dim3(64), 0, s,
+                           w.records, w.items, w.tile_count, w.counters, e0, bt);
         break;
     }
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess)
@@ -992,11 +1038,25 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
     // Depos whose patch does not fit a tile region: one workgroup each, direct
     // atomics.  The grid is persistent over the device-side count.
     const unsigned lg = (unsigned)std::min<int64_t>(n, 2048);
-    hipLaunchKernelGGL((k_patch_generic<256, false>), dim3(lg), dim3(256), 0, s, depos, w.large,
-                       w.counters + 1, (int64_t)0, pl->kp, evid, nullptr, nullptr, grid);
+    hipLaunchKernelGGL((k_patch_generic<256, false, B>), dim3(lg), dim3(256), 0, s, e0, bt,
+                       w.large, w.counters + 1, (int64_t)0, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     return mark(2);
+}
+
+hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
+                               uint64_t event_id, const RasterWork &w, float *grid, hipStream_t s,
+                               const hipEvent_t *ev)
+{
+    const EventCtx e0 = single_event(pl, depos, n, event_id, grid);
+    return raster_sequence<false>(pl, e0, BatchTables{}, n, pl->ntiles, w, s, ev);
+}
+
+hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
+                               int64_t ntiles_total, const RasterWork &w, hipStream_t s)
+{
+    return raster_sequence<true>(pl, EventCtx{}, bt, n_total, ntiles_total, w, s, nullptr);
 }
 
 }  // namespace wcs

@@ -43,6 +43,51 @@ struct PlaneParams {
 constexpr int kMaxWindow = 1024;
 
 // ---------------------------------------------------------------------------
+// Batched execution: one descriptor per event in device memory, and prefix
+// bases (nev + 1 entries each) that map a global index of each kind of work
+// to its event: depos, tiles, and the workgroups of the three FFT passes.
+// ---------------------------------------------------------------------------
+struct EventCtx {
+    PlaneParams kp;
+    const wcsim_depo *depos;
+    float *grid;       // [Np][Nt]
+    const float2 *K;   // response spectrum of the event's plane
+    float2 *X;         // [C][Np][F]
+    float2 *Y;         // [C][nout][F]
+    float *out;        // [nout][Nt]
+    int64_t depo_base;
+    int32_t n;
+    uint32_t event;
+    int32_t tile_base, ntt;
+    int32_t nout, nblocks, mode;
+    int32_t pad_;
+};
+
+struct BatchTables {
+    const EventCtx *ev;
+    const int32_t *depo_base;  // global depo index of each event's depo 0 (fits int32: < 2^31)
+    const int32_t *tile_base;
+    const int32_t *rblk_base;  // tick-axis forward pass workgroups
+    const int32_t *pblk_base;  // pitch-axis pass workgroups
+    const int32_t *cblk_base;  // tick-axis inverse pass workgroups
+    int32_t nev;
+};
+
+// Largest e with base[e] <= key (base ascending, base[0] = 0).
+__device__ __forceinline__ int find_event(const int32_t *base, int nev, int key)
+{
+    int lo = 0, hi = nev - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= key)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
 // FFT plans
 // ---------------------------------------------------------------------------
 constexpr int kMaxPass = 12;
@@ -140,6 +185,13 @@ RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base);
 hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
                                uint64_t event_id, const RasterWork &w, float *grid,
                                hipStream_t s, const hipEvent_t *ev = nullptr);
+// Batched: events of planes sharing one schedule class (pl = any of them);
+// n_total depos, ntiles_total tiles over all events.
+size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n_total, int64_t ntiles_total);
+RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n_total, int64_t ntiles_total,
+                                   void *base);
+hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
+                               int64_t ntiles_total, const RasterWork &w, hipStream_t s);
 
 // FFT convolution passes
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind);
@@ -150,6 +202,13 @@ hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
 hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void *work,
                                    hipStream_t s);
 size_t response_work_bytes(const wcsim_plane *pl);
+// Batched convolution: the three passes over every event of the tables;
+// nblk_* = total workgroups of each pass (the last entries of the bases).
+hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
+                                 int nblk_p, int nblk_c, hipStream_t s);
+int rows_blocks(int nrows);                       // workgroups of a tick-axis pass
+int pitch_blocks_total(const wcsim_plane *pl);    // workgroups of the pitch pass
+bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b);
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
