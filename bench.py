@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kind", choices=["wire", "pitch"], default="wire")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-event batched vs plain comparison")
+    ap.add_argument("--batch-events", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy kernel "
                          "whose HBM counters scale the kernels' FETCH_SIZE / WRITE_SIZE)")
@@ -121,6 +124,61 @@ def cpu_baseline(w, kind_wire: bool) -> dict:
     return {"value": dep.shape[0] / dt, "unit": "depos/s", "cores": 1, "kind": "oracle",
             "sample": "one whole event (%d depos, %d x %d grid) in %.2f s, 1 thread"
                       % (dep.shape[0], pl["nwires"] * pl["nimpact"], pl["nticks"], dt)}
+
+
+def batch_comparison(wcsim, W, dev, nevents: int, rounds: int = 3) -> dict:
+    """The batch workload (uneven events: depo counts log-uniform in
+    10^4..10^6, 100/480/800/960 wires x 6000 ticks): `nevents` plain
+    per-event launches against one captured batch, both timed over whole
+    rounds with inputs resident in HBM."""
+    import torch
+
+    evs = W.batch_events(nevents=nevents)
+    phys = W.physics(True)
+    planes = {}
+    for e in evs:
+        nw = e["plane"]["nwires"]
+        if nw not in planes:
+            planes[nw] = wcsim.Plane(e["plane"], phys, e["response"])
+    pl = [planes[e["plane"]["nwires"]] for e in evs]
+    deps = [torch.from_numpy(e["depos"]).to(dev) for e in evs]
+    ids = [e["event_id"] for e in evs]
+    outs = [torch.empty((p.nwires, p.nticks), dtype=torch.float32, device=dev) for p in pl]
+    ntot = sum(d.shape[0] for d in deps)
+    wsp = wcsim.simulate_workspace(pl[int(np.argmax([p.npitch * 10**7 + d.shape[0]
+                                                     for p, d in zip(pl, deps)]))],
+                                   max(d.shape[0] for d in deps), wcsim.OUT_WIRE, dev)
+    # the largest workspace covers every event run in sequence
+    need = max(wcsim._lib.wcsim_simulate_workspace_bytes(p.handle, d.shape[0], 0)
+               for p, d in zip(pl, deps))
+    if wsp.numel() < need:
+        wsp = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def plain():
+        for p, d, i, o in zip(pl, deps, ids, outs):
+            wcsim.simulate_event(p, d, i, out=o, workspace=wsp)
+
+    batch = wcsim.Batch(pl, [d.shape[0] for d in deps])
+
+    def batched():
+        batch.run(deps, ids, outs)
+
+    res = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / rounds
+        res[name] = {"ms_per_batch": dt * 1e3, "depos_per_s": ntot / dt,
+                     "planes_per_s": nevents / dt}
+    batch.destroy()
+    res["events"] = nevents
+    res["depos"] = int(ntot)
+    res["speedup"] = res["plain"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    return res
 
 
 def main():
@@ -207,6 +265,10 @@ def main():
                     "avg_ms": stages[dom]}
     per_stage_hbm = {s: alg[s] / (stages[s] * 1e-3) / 1e9 for s in alg if stages.get(s, 0) > 0}
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_comparison(wcsim, W, dev, args.batch_events)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, kind == wcsim.OUT_WIRE)
@@ -236,6 +298,7 @@ def main():
         "stage_ms": stages,
         "stage_hbm_gbs": per_stage_hbm,
         "roofline": roofline,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

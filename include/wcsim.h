@@ -240,6 +240,25 @@ wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
                                   float *const *outs, wcsim_out out_kind, void *workspace,
                                   void *stream);
 
+/* Captured batch (hipGraph): the launch sequence of a batch of up to
+ * capacity[e] depos per event on the given planes is captured once; each run
+ * then uploads only the event descriptors (depo pointers and counts, event ids,
+ * outputs) and replays the graph, so repeated batches of this shape pay no
+ * per-kernel launch cost and no re-capture.  `workspace` (device, at least
+ * wcsim_batch_workspace_bytes(planes, capacity, nevents, out_kind) bytes,
+ * 256-byte aligned) stays bound to the batch until wcsim_batch_destroy.
+ * Runs on one batch object are serialised (a run waits until the previous
+ * run's descriptors have been uploaded).  Errors: WCSIM_E_INVALID for bad
+ * arguments or counts above capacity. */
+typedef struct wcsim_batch wcsim_batch;
+wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t *capacity,
+                                int32_t nevents, wcsim_out out_kind, void *workspace,
+                                wcsim_batch **out);
+wcsim_status wcsim_batch_run(wcsim_batch *batch, const wcsim_depo *const *depos,
+                             const int64_t *n, const uint64_t *event_ids, float *const *outs,
+                             void *stream);
+void wcsim_batch_destroy(wcsim_batch *batch);
+
 /* Diagnostic: the Philox4x32-10 generator the fluctuation uses (Sec. 4.1,
  * random123), evaluated on the GPU: out[i] = Philox4x32-10(ctr[i], key[i]).
  * ctr/out: n x 4 uint32, key: n x 2 uint32, all device memory. */

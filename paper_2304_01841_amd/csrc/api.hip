@@ -710,6 +710,38 @@ struct HostStaging {
 };
 thread_local HostStaging g_staging;
 
+}  // namespace
+}  // namespace wcs
+
+struct wcsim_batch {
+    std::vector<const wcsim_plane *> planes;
+    std::vector<int64_t> capacity;
+    wcsim_out kind;
+    char *ws = nullptr;
+    std::vector<std::vector<int>> groups;
+    std::vector<wcs::BatchLayout> layouts;
+    std::vector<size_t> host_off;
+    void *pinned = nullptr;
+    hipEvent_t done = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace wcs {
+namespace {
+
+void destroy_batch(wcsim_batch *b)
+{
+    if (b->done)
+        (void)hipEventSynchronize(b->done);
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->pinned)
+        (void)hipHostFree(b->pinned);
+    if (b->done)
+        (void)hipEventDestroy(b->done);
+    delete b;
+}
+
 wcsim_status stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s)
 {
     HostStaging &h = g_staging;
@@ -727,6 +759,81 @@ wcsim_status stage_upload(const void *src, size_t bytes, void *dst, hipStream_t 
     memcpy(h.buf, src, bytes);
     WCS_HIP(hipMemcpyAsync(dst, h.buf, bytes, hipMemcpyHostToDevice, s));
     WCS_HIP(hipEventRecord(h.done, s));
+    return WCSIM_OK;
+}
+
+// Per-run fields of the descriptors and the device pointers of the layout.
+void fill_descriptors(BatchLayout &L, const std::vector<int> &g, char *ws,
+                      const wcsim_depo *const *depos, const int64_t *n, const uint64_t *event_ids,
+                      float *const *outs)
+{
+    for (size_t k = 0; k < g.size(); ++k) {
+        EventCtx &e = L.ev[k];
+        e.depos = depos[g[k]];
+        e.n = (int32_t)n[g[k]];
+        e.event = (uint32_t)event_ids[g[k]];
+        e.out = outs[g[k]];
+        e.grid = (float *)(ws + L.off_grid + (uintptr_t)e.grid);
+        e.X = (float2 *)(ws + L.off_X + (uintptr_t)e.X);
+        e.Y = (float2 *)(ws + L.off_Y + (uintptr_t)e.Y);
+    }
+}
+
+void pack_tables(const BatchLayout &L, char *host)
+{
+    memcpy(host + L.off_ev, L.ev.data(), sizeof(EventCtx) * L.ev.size());
+    memcpy(host + L.off_bases, L.bases.data(), sizeof(int32_t) * L.bases.size());
+}
+
+BatchTables tables_of(const BatchLayout &L, char *ws)
+{
+    const int nev = (int)L.ev.size();
+    BatchTables bt;
+    bt.ev = (const EventCtx *)(ws + L.off_ev);
+    const int32_t *b0 = (const int32_t *)(ws + L.off_bases);
+    bt.depo_base = b0;
+    bt.tile_base = b0 + (nev + 1);
+    bt.rblk_base = b0 + 2 * (nev + 1);
+    bt.pblk_base = b0 + 3 * (nev + 1);
+    bt.cblk_base = b0 + 4 * (nev + 1);
+    bt.nev = nev;
+    return bt;
+}
+
+// Kernels of one group (its tables already uploaded to the workspace head).
+hipError_t launch_batch_group(const wcsim_plane *pl0, const BatchLayout &L, char *ws,
+                              hipStream_t s)
+{
+    const BatchTables bt = tables_of(L, ws);
+    const RasterWork rw = raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, ws + L.off_raster);
+    hipError_t e;
+    if ((e = launch_fill_zero(ws + L.off_grid, L.grid_bytes, s)) != hipSuccess)
+        return e;
+    if ((e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, s)) != hipSuccess)
+        return e;
+    return launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, s);
+}
+
+wcsim_status check_batch_args(const wcsim_plane *const *planes, const wcsim_depo *const *depos,
+                              const int64_t *n, const uint64_t *event_ids, int32_t nevents,
+                              float *const *outs, wcsim_out out_kind, void *workspace)
+{
+    if (!planes || !depos || !n || !event_ids || !outs || !workspace || nevents < 0)
+        return fail(WCSIM_E_INVALID, "bad batch arguments");
+    if (out_kind != WCSIM_OUT_WIRE && out_kind != WCSIM_OUT_PITCH)
+        return fail(WCSIM_E_INVALID, "bad output kind");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(WCSIM_E_INVALID, "workspace must be 256-byte aligned");
+    int64_t n_all = 0;
+    for (int32_t e = 0; e < nevents; ++e) {
+        if (!planes[e])
+            return fail(WCSIM_E_STATE, "NULL plane in batch");
+        if (n[e] < 0 || (n[e] > 0 && !depos[e]) || !outs[e])
+            return fail(WCSIM_E_INVALID, "bad depos or output of batch event " + std::to_string(e));
+        n_all += n[e];
+    }
+    if (n_all > (1LL << 31) - 1)
+        return fail(WCSIM_E_INVALID, "too many depos in one batch");
     return WCSIM_OK;
 }
 
@@ -768,8 +875,31 @@ wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
                                   const uint64_t *event_ids, int32_t nevents, float *const *outs,
                                   wcsim_out out_kind, void *workspace, void *stream)
 {
-    if (!planes || !depos || !n || !event_ids || !outs || !workspace || nevents < 0)
+    wcsim_status st = check_batch_args(planes, depos, n, event_ids, nevents, outs, out_kind,
+                                       workspace);
+    if (st != WCSIM_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    for (const auto &g : schedule_groups(planes, nevents)) {
+        BatchLayout L = plan_batch(planes, n, g, out_kind);
+        fill_descriptors(L, g, ws, depos, n, event_ids, outs);
+        std::vector<char> host(L.off_raster);
+        pack_tables(L, host.data());
+        if ((st = stage_upload(host.data(), host.size(), ws, s)) != WCSIM_OK)
+            return st;
+        WCS_HIP(launch_batch_group(planes[g[0]], L, ws, s));
+    }
+    return WCSIM_OK;
+}
+
+wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t *capacity,
+                                int32_t nevents, wcsim_out out_kind, void *workspace,
+                                wcsim_batch **out)
+{
+    if (!out || !planes || !capacity || nevents <= 0 || !workspace)
         return fail(WCSIM_E_INVALID, "bad batch arguments");
+    *out = nullptr;
     if (out_kind != WCSIM_OUT_WIRE && out_kind != WCSIM_OUT_PITCH)
         return fail(WCSIM_E_INVALID, "bad output kind");
     if (((uintptr_t)workspace & 255) != 0)
@@ -778,49 +908,90 @@ wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
     for (int32_t e = 0; e < nevents; ++e) {
         if (!planes[e])
             return fail(WCSIM_E_STATE, "NULL plane in batch");
-        if (n[e] < 0 || (n[e] > 0 && !depos[e]) || !outs[e])
-            return fail(WCSIM_E_INVALID, "bad depos or output of batch event " + std::to_string(e));
-        n_all += n[e];
+        if (capacity[e] < 0)
+            return fail(WCSIM_E_INVALID, "negative capacity");
+        n_all += capacity[e];
     }
     if (n_all > (1LL << 31) - 1)
         return fail(WCSIM_E_INVALID, "too many depos in one batch");
-    hipStream_t s = (hipStream_t)stream;
-    char *ws = (char *)workspace;
-    for (const auto &g : schedule_groups(planes, nevents)) {
-        BatchLayout L = plan_batch(planes, n, g, out_kind);
-        const wcsim_plane *pl0 = planes[g[0]];
-        for (size_t k = 0; k < g.size(); ++k) {
-            EventCtx &e = L.ev[k];
-            e.depos = depos[g[k]];
-            e.event = (uint32_t)event_ids[g[k]];
-            e.out = outs[g[k]];
-            e.grid = (float *)(ws + L.off_grid + (uintptr_t)e.grid);
-            e.X = (float2 *)(ws + L.off_X + (uintptr_t)e.X);
-            e.Y = (float2 *)(ws + L.off_Y + (uintptr_t)e.Y);
-        }
-        std::vector<char> host(L.off_raster);
-        memcpy(host.data() + L.off_ev, L.ev.data(), sizeof(EventCtx) * L.ev.size());
-        memcpy(host.data() + L.off_bases, L.bases.data(), sizeof(int32_t) * L.bases.size());
-        wcsim_status st = stage_upload(host.data(), host.size(), ws, s);
-        if (st != WCSIM_OK)
-            return st;
-        const int nev = (int)g.size();
-        BatchTables bt;
-        bt.ev = (const EventCtx *)(ws + L.off_ev);
-        const int32_t *b0 = (const int32_t *)(ws + L.off_bases);
-        bt.depo_base = b0;
-        bt.tile_base = b0 + (nev + 1);
-        bt.rblk_base = b0 + 2 * (nev + 1);
-        bt.pblk_base = b0 + 3 * (nev + 1);
-        bt.cblk_base = b0 + 4 * (nev + 1);
-        bt.nev = nev;
-        const RasterWork rw =
-            raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, ws + L.off_raster);
-        WCS_HIP(launch_fill_zero(ws + L.off_grid, L.grid_bytes, s));
-        WCS_HIP(launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, s));
-        WCS_HIP(launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, s));
+    wcsim_batch *b = new (std::nothrow) wcsim_batch();
+    if (!b)
+        return fail(WCSIM_E_NOMEM, "host allocation failed");
+    b->planes.assign(planes, planes + nevents);
+    b->capacity.assign(capacity, capacity + nevents);
+    b->kind = out_kind;
+    b->ws = (char *)workspace;
+    b->groups = schedule_groups(planes, nevents);
+    size_t host_bytes = 0;
+    for (const auto &g : b->groups) {
+        b->layouts.push_back(plan_batch(planes, capacity, g, out_kind));
+        b->host_off.push_back(host_bytes);
+        host_bytes += align_up(b->layouts.back().off_raster);
     }
+    auto bail = [&](wcsim_status st) {
+        destroy_batch(b);
+        return st;
+    };
+    hipError_t e;
+    if ((e = hipHostMalloc(&b->pinned, std::max<size_t>(host_bytes, 256), hipHostMallocDefault)) !=
+        hipSuccess)
+        return bail(check_hip(e, "hipHostMalloc(batch tables)"));
+    if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess)
+        return bail(check_hip(e, "hipEventCreate"));
+    hipStream_t cs = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+        return bail(check_hip(e, "hipStreamCreate"));
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (size_t k = 0; e == hipSuccess && k < b->groups.size(); ++k) {
+        const BatchLayout &L = b->layouts[k];
+        e = hipMemcpyAsync(b->ws, (char *)b->pinned + b->host_off[k], L.off_raster,
+                           hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess)
+            e = launch_batch_group(planes[b->groups[k][0]], L, b->ws, cs);
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess)
+        e = e2;
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess)
+        return bail(check_hip(e, "batch graph capture"));
+    *out = b;
     return WCSIM_OK;
+}
+
+wcsim_status wcsim_batch_run(wcsim_batch *b, const wcsim_depo *const *depos, const int64_t *n,
+                             const uint64_t *event_ids, float *const *outs, void *stream)
+{
+    if (!b)
+        return fail(WCSIM_E_STATE, "NULL batch");
+    const int32_t nev = (int32_t)b->planes.size();
+    wcsim_status st = check_batch_args(b->planes.data(), depos, n, event_ids, nev, outs, b->kind,
+                                       b->ws);
+    if (st != WCSIM_OK)
+        return st;
+    for (int32_t e = 0; e < nev; ++e)
+        if (n[e] > b->capacity[(size_t)e])
+            return fail(WCSIM_E_INVALID, "event " + std::to_string(e) + " exceeds its capacity");
+    WCS_HIP(hipEventSynchronize(b->done));  // the previous run has read the tables
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+        BatchLayout L = b->layouts[k];
+        fill_descriptors(L, b->groups[k], b->ws, depos, n, event_ids, outs);
+        pack_tables(L, (char *)b->pinned + b->host_off[k]);
+    }
+    WCS_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    WCS_HIP(hipEventRecord(b->done, (hipStream_t)stream));
+    return WCSIM_OK;
+}
+
+void wcsim_batch_destroy(wcsim_batch *b)
+{
+    if (b)
+        destroy_batch(b);
 }
 
 }  // extern "C"

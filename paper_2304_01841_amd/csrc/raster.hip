@@ -525,7 +525,9 @@ __global__ __launch_bounds__(256) void k_prep_bin(EventCtx e0, BatchTables bt, i
     if (d < ntotal) {
         const EventCtx &E = B ? bt.ev[find_event(bt.depo_base, bt.nev, (int)d)] : e0;
         const PlaneParams &P = E.kp;
-        const Win w = depo_window(E.depos[d - E.depo_base], P);
+        const int64_t dl = d - E.depo_base;
+        // a batch reserves capacity per event; depos past its count are absent
+        const Win w = (dl < E.n) ? depo_window(E.depos[dl], P) : Win{0, 0, 0, 0, 0, 0, 0, 0, 0, 2};
         if (w.status == 1 || w.status == 3) {
             bad = true;
         } else if (w.status == 0) {

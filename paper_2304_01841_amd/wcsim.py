@@ -100,6 +100,9 @@ _SIGS = {
     "wcsim_workspace_invalid_count": (_st, [_P, _P, _P]),
     "wcsim_batch_workspace_bytes": (_sz, [_P, _P, _i32, _i32]),
     "wcsim_simulate_batch": (_st, [_P, _P, _P, _P, _i32, _P, _i32, _P, _P]),
+    "wcsim_batch_create": (_st, [_P, _P, _i32, _i32, _P, _P]),
+    "wcsim_batch_run": (_st, [_P, _P, _P, _P, _P, _P]),
+    "wcsim_batch_destroy": (None, [_P]),
     "wcsim_philox4x32_10": (_st, [_P, _P, _i64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -406,6 +409,47 @@ def simulate_batch(planes, depos_list, event_ids, outs, kind: int = OUT_WIRE,
     _check(_lib.wcsim_simulate_batch(arr_p, arr_d, arr_n, arr_e, ne, arr_o, kind,
                                      _dev_ptr(workspace, what="workspace"), _stream(stream)))
     return outs
+
+
+class Batch:
+    """hipGraph-captured batch (wcsim_batch_create / wcsim_batch_run): events
+    on `planes` with up to `capacity[e]` depos each."""
+
+    def __init__(self, planes, capacity, kind: int = OUT_WIRE, device="cuda"):
+        self.planes = list(planes)
+        self.kind = kind
+        ne = len(self.planes)
+        arr_p = (ctypes.c_void_p * ne)(*[p.handle.value for p in self.planes])
+        arr_c = (ctypes.c_int64 * ne)(*[int(c) for c in capacity])
+        nbytes = _lib.wcsim_batch_workspace_bytes(arr_p, arr_c, ne, kind)
+        self.workspace = _workspace(nbytes, device)
+        h = ctypes.c_void_p()
+        _check(_lib.wcsim_batch_create(arr_p, arr_c, ne, kind,
+                                       _dev_ptr(self.workspace, what="workspace"),
+                                       ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, depos_list, event_ids, outs, stream=None):
+        ne = len(self.planes)
+        for d in depos_list:
+            _dev_ptr(d, torch.float64, "depos")
+        arr_d = (ctypes.c_void_p * ne)(*[d.data_ptr() for d in depos_list])
+        arr_n = (ctypes.c_int64 * ne)(*[d.shape[0] for d in depos_list])
+        arr_e = (ctypes.c_uint64 * ne)(*[int(e) & (2**64 - 1) for e in event_ids])
+        arr_o = (ctypes.c_void_p * ne)(*[_dev_ptr(o, torch.float32, "out") for o in outs])
+        _check(_lib.wcsim_batch_run(self.handle, arr_d, arr_n, arr_e, arr_o, _stream(stream)))
+        return outs
+
+    def destroy(self):
+        if self.handle:
+            _lib.wcsim_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def philox4x32_10(ctr: torch.Tensor, key: torch.Tensor, stream=None) -> torch.Tensor:

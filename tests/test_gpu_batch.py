@@ -88,3 +88,27 @@ def test_batch_event_workload_sample(ws):
     for p, d, e, o in zip(planes, deps, evs, outs):
         single = ws.simulate_event(p, d, e["event_id"]).cpu().numpy()
         assert normwise(o.cpu().numpy(), single) <= 1e-5
+
+
+def test_graph_batch_replays(ws):
+    """The captured batch reproduces the plain batch, and replays with new
+    inputs (fewer depos, other event ids) without re-capture."""
+    print("case: graph batch", flush=True)
+    phys = W.physics(True)
+    R = W.response("bipolar", Rp=41, Rt=40, r0=20)
+    evs = _events(31, [(30, 5000), (12, 800), (44, 6000)], 600)
+    planes = [ws.Plane(e["plane"], phys, R, r0=20) for e in evs]
+    deps = [torch.from_numpy(e["depos"]).cuda() for e in evs]
+    b = ws.Batch(planes, [d.shape[0] for d in deps])
+    for rnd in range(3):
+        cut = [d[: max(1, d.shape[0] // (rnd + 1))].contiguous() for d in deps]
+        ids = [7 * rnd + k for k in range(len(deps))]
+        outs = [torch.full((p.nwires, p.nticks), -1.0, device="cuda") for p in planes]
+        b.run(cut, ids, outs)
+        torch.cuda.synchronize()
+        for p, d, i, o in zip(planes, cut, ids, outs):
+            single = ws.simulate_event(p, d, i).cpu().numpy()
+            assert normwise(o.cpu().numpy(), single) <= 1e-5
+    with pytest.raises(ws.WcsimError):
+        b.run([torch.cat([d, d]) for d in deps], [0, 1, 2], outs)
+    b.destroy()
