@@ -132,6 +132,17 @@ wcsim_status wcsim_plane_create_with_schedule(const wcsim_plane_desc *desc,
                                               const wcsim_schedule *sched, void *stream,
                                               wcsim_plane **out);
 
+/* Same as wcsim_plane_create, but when `donor` has the same response (shape,
+ * origin and values) and a tick-axis transform long enough for this plane,
+ * the new plane takes the donor's transform sizes and shares its resident
+ * response spectrum (reference counted) instead of building one: planes of
+ * any wire count with one response then cost no spectrum memory or set-up
+ * (the spectrum does not depend on the number of wires).  Otherwise it
+ * builds its own.  WCSIM_E_INVALID for a NULL donor. */
+wcsim_status wcsim_plane_create_sharing(const wcsim_plane_desc *desc, const wcsim_physics *phys,
+                                        const wcsim_plane *donor, void *stream,
+                                        wcsim_plane **out);
+
 /* Frees the plane (synchronises the device first).  NULL is ignored. */
 void wcsim_plane_destroy(wcsim_plane *plane);
 

@@ -12,6 +12,21 @@
 
 #include "wcsim_internal.h"
 
+// Device buffers of a response spectrum and its twiddle tables, with the
+// host response they were built from (to recognise a compatible donor).
+struct wcs_spectrum {
+    float2 *K = nullptr, *twT = nullptr, *twHalf = nullptr, *twL = nullptr;
+    std::vector<float> response;
+    int Rp = 0, Rt = 0, r0 = 0, Nfft = 0, L = 0, F = 0, device = -1;
+    ~wcs_spectrum()
+    {
+        (void)hipFree(K);
+        (void)hipFree(twT);
+        (void)hipFree(twHalf);
+        (void)hipFree(twL);
+    }
+};
+
 namespace wcs {
 
 namespace {
@@ -104,13 +119,7 @@ std::vector<float2> twiddles(int n, int count)
 
 void free_plane(wcsim_plane *p)
 {
-    if (!p)
-        return;
-    (void)hipFree(p->twT);
-    (void)hipFree(p->twHalf);
-    (void)hipFree(p->twL);
-    (void)hipFree(p->K);
-    delete p;
+    delete p;  // device buffers belong to the (possibly shared) spectrum
 }
 
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -181,7 +190,8 @@ wcsim_status upload(T **dst, const std::vector<T> &src, hipStream_t s)
 }
 
 wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phys,
-                          const wcsim_schedule *sched, void *stream, wcsim_plane **out)
+                          const wcsim_schedule *sched, const wcsim_plane *donor, void *stream,
+                          wcsim_plane **out)
 {
     if (!out)
         return fail(WCSIM_E_INVALID, "NULL output handle");
@@ -227,6 +237,21 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
         free_plane(pl);
         return st;
     }
+    const size_t nresp = (size_t)pl->Rp * pl->Rt;
+    if (donor && donor->spectrum) {
+        const wcs_spectrum &d = *donor->spectrum;
+        if (d.Rp == pl->Rp && d.Rt == pl->Rt && d.r0 == pl->r0 && d.Nfft == pl->Nfft &&
+            d.L == pl->L && d.F == pl->F && d.device == pl->device &&
+            memcmp(d.response.data(), desc->response, sizeof(float) * nresp) == 0) {
+            pl->spectrum = donor->spectrum;
+            pl->K = d.K;
+            pl->twT = d.twT;
+            pl->twHalf = d.twHalf;
+            pl->twL = d.twL;
+            *out = pl;
+            return WCSIM_OK;
+        }
+    }
     float *resp = nullptr;
     void *work = nullptr;
     auto cleanup = [&](wcsim_status r) {
@@ -236,15 +261,29 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
             free_plane(pl);
         return r;
     };
-    if ((st = upload(&pl->twT, twiddles(pl->N2, pl->N2), s)) != WCSIM_OK ||
-        (st = upload(&pl->twHalf, twiddles(pl->Nfft, pl->N2 + 1), s)) != WCSIM_OK ||
-        (st = upload(&pl->twL, twiddles(pl->L, pl->L), s)) != WCSIM_OK)
+    auto spec = std::make_shared<wcs_spectrum>();
+    pl->spectrum = spec;
+    spec->response.assign(desc->response, desc->response + nresp);
+    spec->Rp = pl->Rp;
+    spec->Rt = pl->Rt;
+    spec->r0 = pl->r0;
+    spec->Nfft = pl->Nfft;
+    spec->L = pl->L;
+    spec->F = pl->F;
+    spec->device = pl->device;
+    if ((st = upload(&spec->twT, twiddles(pl->N2, pl->N2), s)) != WCSIM_OK ||
+        (st = upload(&spec->twHalf, twiddles(pl->Nfft, pl->N2 + 1), s)) != WCSIM_OK ||
+        (st = upload(&spec->twL, twiddles(pl->L, pl->L), s)) != WCSIM_OK)
         return cleanup(st);
+    pl->twT = spec->twT;
+    pl->twHalf = spec->twHalf;
+    pl->twL = spec->twL;
     hipError_t e;
     const size_t kbytes = sizeof(float2) * (size_t)pl->C * pl->L * pl->F;
-    if ((e = hipMalloc((void **)&pl->K, kbytes)) != hipSuccess)
+    if ((e = hipMalloc((void **)&spec->K, kbytes)) != hipSuccess)
         return cleanup(check_hip(e, "hipMalloc(response spectrum)"));
-    const size_t rbytes = sizeof(float) * (size_t)pl->Rp * pl->Rt;
+    pl->K = spec->K;
+    const size_t rbytes = sizeof(float) * nresp;
     if ((e = hipMalloc((void **)&resp, rbytes)) != hipSuccess)
         return cleanup(check_hip(e, "hipMalloc(response)"));
     if ((e = hipMalloc(&work, response_work_bytes(pl))) != hipSuccess)
@@ -298,7 +337,7 @@ const char *wcsim_last_error(void) { return g_last_error.c_str(); }
 wcsim_status wcsim_plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phys,
                                 void *stream, wcsim_plane **out)
 {
-    return plane_create(desc, phys, nullptr, stream, out);
+    return plane_create(desc, phys, nullptr, nullptr, stream, out);
 }
 
 wcsim_status wcsim_plane_create_with_schedule(const wcsim_plane_desc *desc,
@@ -306,7 +345,23 @@ wcsim_status wcsim_plane_create_with_schedule(const wcsim_plane_desc *desc,
                                               const wcsim_schedule *sched, void *stream,
                                               wcsim_plane **out)
 {
-    return plane_create(desc, phys, sched, stream, out);
+    return plane_create(desc, phys, sched, nullptr, stream, out);
+}
+
+wcsim_status wcsim_plane_create_sharing(const wcsim_plane_desc *desc, const wcsim_physics *phys,
+                                        const wcsim_plane *donor, void *stream, wcsim_plane **out)
+{
+    if (!donor)
+        return fail(WCSIM_E_INVALID, "NULL spectrum donor");
+    wcsim_schedule sc;
+    sc.fft_ticks = donor->Nfft;
+    sc.fft_pitch = donor->L;
+    sc.freq_chunk = donor->F;
+    sc.tile = donor->tile;
+    // the donor's transform may be too short for a longer readout
+    if (desc && donor->Nfft < desc->nticks + desc->resp_nticks - 1)
+        return plane_create(desc, phys, nullptr, nullptr, stream, out);
+    return plane_create(desc, phys, &sc, donor, stream, out);
 }
 
 void wcsim_plane_destroy(wcsim_plane *plane)

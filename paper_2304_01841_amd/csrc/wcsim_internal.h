@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
+#include <vector>
 
 #include "wcsim.h"
 
@@ -128,6 +130,9 @@ struct wcsim_plane {
     float2 *twHalf;  // two-level table of exp(-2 pi i k / N'), k <= N2
     float2 *twL;     // two-level table of exp(-2 pi i j / L), j < L
     float2 *K;       // response spectrum [C][L][F], scaled by 1/(L N')
+    // owner of K and the twiddle tables; planes with the same response and
+    // transform sizes share one
+    std::shared_ptr<struct wcs_spectrum> spectrum;
     int tile;
     wcs::TileShape ts;
     int ntp, ntt;

@@ -82,6 +82,7 @@ _SIGS = {
     "wcsim_last_error": (ctypes.c_char_p, []),
     "wcsim_plane_create": (_st, [_P, _P, _P, _P]),
     "wcsim_plane_create_with_schedule": (_st, [_P, _P, _P, _P, _P]),
+    "wcsim_plane_create_sharing": (_st, [_P, _P, _P, _P, _P]),
     "wcsim_plane_destroy": (None, [_P]),
     "wcsim_plane_get_info": (_st, [_P, _P]),
     "wcsim_rasterize": (_st, [_P, _P, _i64, _i32, _u64, _P, _P]),
@@ -150,7 +151,7 @@ class Plane:
     """A plane with its resident response spectrum (wcsim_plane)."""
 
     def __init__(self, plane: dict, phys: dict, response: np.ndarray, r0: int | None = None,
-                 schedule: dict | None = None, stream=None):
+                 schedule: dict | None = None, stream=None, share: "Plane | None" = None):
         resp = np.ascontiguousarray(response, dtype=np.float32)
         Rp, Rt = resp.shape
         if r0 is None:
@@ -163,7 +164,10 @@ class Plane:
                       resp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
         ph = physics_struct(phys)
         h = ctypes.c_void_p()
-        if schedule:
+        if share is not None:
+            st = _lib.wcsim_plane_create_sharing(ctypes.byref(d), ctypes.byref(ph), share.handle,
+                                                 _stream(stream), ctypes.byref(h))
+        elif schedule:
             sc = Schedule(int(schedule.get("fft_ticks", 0)), int(schedule.get("fft_pitch", 0)),
                           int(schedule.get("freq_chunk", 0)), int(schedule.get("tile", 0)))
             st = _lib.wcsim_plane_create_with_schedule(ctypes.byref(d), ctypes.byref(ph),

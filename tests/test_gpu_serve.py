@@ -1,0 +1,91 @@
+"""Served form: continuous batching under the HBM budget.  Every request's
+result must be the same alone and in the mix (normwise 1e-5), and the
+scheduler must actually mix (groups of several requests, overlapping groups)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2304_01841_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_01841_amd import serve, wcsim
+    return serve, wcsim
+
+
+def normwise(got, ref):
+    ref = np.asarray(ref, np.float64)
+    return np.abs(np.asarray(got, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def _requests(n, seed=11, nticks=1500):
+    reqs = W.serve_requests(seed=seed, nreq=n, lo=3.0, hi=4.3, nticks=nticks)
+    for r in reqs:  # keep the test small: at most 300 wires per plane
+        for pl in r["planes"]:
+            pl["nwires"] = min(pl["nwires"], 300)
+        rng = np.random.default_rng(r["event_id"])
+        box = (W.BOX_X * nticks / 6000.0, W.BOX_Y, max(p["nwires"] for p in r["planes"]) * W.PITCH)
+        r["depos"] = W.clipped_track_depos(rng, r["depos"].shape[0], box)
+    return reqs
+
+
+def _alone(wcsim, server, r):
+    outs = []
+    for d, R in zip(r["planes"], r["responses"]):
+        p = server.plane(d, R)
+        outs.append(wcsim.simulate_event(p, torch.from_numpy(r["depos"]).cuda(),
+                                         r["event_id"]).cpu().numpy())
+    return outs
+
+
+def test_serve_mix_equals_alone(mods):
+    serve, wcsim = mods
+    print("case: serve mix", flush=True)
+    reqs = _requests(24)
+    srv = serve.Server(W.physics(True), slots=3, max_batch=6)
+    arr = W.poisson_arrivals(3, len(reqs), qps=4000.0)
+    res = srv.serve(reqs, arr)
+    assert all(r.error is None for r in res)
+    assert srv.stats["max_group"] >= 2
+    assert srv.stats["max_inflight_groups"] >= 2
+    for r, q in zip(res, reqs):
+        alone = _alone(wcsim, srv, q)
+        assert len(r.outputs) == len(alone)
+        for got, ref in zip(r.outputs, alone):
+            assert normwise(got, ref) <= 1e-5
+    s = serve.latency_summary(res)
+    assert s["requests"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_serve_budget_serialises_and_rejects(mods):
+    serve, wcsim = mods
+    print("case: serve budget", flush=True)
+    reqs = _requests(6, seed=21)
+    probe = serve.Server(W.physics(True))
+    need = [probe.request_bytes([probe.plane(d, R) for d, R in zip(q["planes"], q["responses"])],
+                                q["depos"].shape[0]) for q in reqs]
+    # a budget below any two requests together: admission serialises, and
+    # requests larger than the budget are rejected instead of run
+    two = sorted(need)
+    budget = two[0] + two[1] - 1
+    srv = serve.Server(W.physics(True), hbm_budget=budget, slots=4, max_batch=4)
+    res = srv.serve(reqs)
+    assert srv.stats["max_group"] == 1
+    assert srv.stats["max_inflight_groups"] == 1
+    assert srv.stats["max_inflight_bytes"] <= budget
+    for r, q, nb in zip(res, reqs, need):
+        if nb > budget:
+            assert r.error is not None and not r.outputs
+            continue
+        assert r.error is None
+        for got, ref in zip(r.outputs, _alone(wcsim, srv, q)):
+            assert normwise(got, ref) <= 1e-5
+    # a request larger than the whole budget is rejected, not run
+    tiny = serve.Server(W.physics(True), hbm_budget=min(need) // 2)
+    res = tiny.serve(reqs[:2])
+    assert all(r.error is not None for r in res)
