@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-event batched vs plain comparison")
     ap.add_argument("--batch-events", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served-form measurement")
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy kernel "
                          "whose HBM counters scale the kernels' FETCH_SIZE / WRITE_SIZE)")
@@ -181,6 +184,27 @@ def batch_comparison(wcsim, W, dev, nevents: int, rounds: int = 3) -> dict:
     return res
 
 
+def serve_measurement(W, nreq: int) -> dict:
+    """The serving workload (requests of 1-3 planes of 100-960 wires x 6000
+    ticks, depo counts log-uniform in 10^3..2x10^6): saturated throughput
+    (all requests at t = 0), then Poisson arrivals at fractions of it."""
+    from paper_2304_01841_amd import serve
+
+    reqs = W.serve_requests(nreq=nreq)
+    srv = serve.Server(W.physics(True), hbm_budget=64 << 30, slots=4, max_batch=8)
+    srv.serve(reqs[: min(8, nreq)])  # plane set-up and allocator warm-up
+    sat = serve.latency_summary(srv.serve(reqs))
+    out = {"requests": nreq, "budget_gb": 64, "slots": 4, "max_group": 8,
+           "depos": int(sum(r["depos"].shape[0] for r in reqs)),
+           "planes": int(sum(len(r["planes"]) for r in reqs)), "saturated": sat}
+    rate = sat["throughput_rps"]
+    for frac in (0.5, 0.8, 0.95):
+        arr = W.poisson_arrivals(77, nreq, frac * rate)
+        out["qps_%.2f" % frac] = dict(serve.latency_summary(srv.serve(reqs, arr)),
+                                      offered_rps=frac * rate)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -269,6 +293,10 @@ def main():
     if not args.no_batch:
         batch = batch_comparison(wcsim, W, dev, args.batch_events)
 
+    served = None
+    if not args.no_serve:
+        served = serve_measurement(W, args.serve_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, kind == wcsim.OUT_WIRE)
@@ -299,6 +327,7 @@ def main():
         "stage_hbm_gbs": per_stage_hbm,
         "roofline": roofline,
         "batch": batch,
+        "serve": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
