@@ -136,12 +136,27 @@ __device__ __forceinline__ double seg_sum(double v)
     return v;
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// DPP lane move within rows of 16 lanes (every source lane exists).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
 {
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1)
-        v += __shfl_xor(v, m, 64);
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Sum over the wavefront, returned as a wave-uniform value: quad swaps and
+// row mirrors give every lane its row's sum, then the four row sums are read
+// out.  The summation order is fixed, so the result is reproducible.
+__device__ __forceinline__ float wave_sum_uniform(float v)
+{
+    v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 // Weights of one axis from `WIDTH` lanes: lane k holds edge k (n <= WIDTH - 1).
@@ -705,6 +720,20 @@ __global__ __launch_bounds__(256) void k_fill_records(EventCtx e0, BatchTables b
 // of one patch are distinct, so the deposits are plain read-add-write LDS
 // accesses; no other wavefront touches the region.  The region's non-zero
 // cells are then added to the grid with float atomics.
+//
+// Region columns start kPadT ticks before the tile and rows are a multiple of
+// four floats, so that a tick quad (four ticks 4k .. 4k + 3, the unit one
+// Philox block covers) is one aligned 16-byte LDS access.  A quad's ticks
+// outside the window carry weight zero, hence deposit zero; cells outside the
+// grid are never flushed.
+constexpr int kPadT = 4;
+
+template <int TT>
+constexpr int region_cols()
+{
+    return TT + kHaloT + 2 * kPadT;
+}
+
 template <int TP, int TT, bool B>
 __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
                                                      const int2 *__restrict__ items,
@@ -712,11 +741,11 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
                                                      const int32_t *__restrict__ counters,
                                                      EventCtx e0, BatchTables bt)
 {
-    // Odd LDS row stride: the deposits of one wavefront step through rows and
-    // tick quads, and an even stride would fold them onto a few banks.
-    constexpr int RP = TP + kHaloP, RT = TT + kHaloT + 1;
-    __shared__ float acc[RP * RT];
+    constexpr int RP = TP + kHaloP, RT = region_cols<TT>();
+    static_assert(RT % 4 == 0, "region rows must hold whole quads");
+    __shared__ float4 acc4[RP * RT / 4];
     __shared__ float rec[kRecWords];
+    float *acc = (float *)acc4;
     if ((int)blockIdx.x >= counters[2])
         return;
     const int2 it2 = items[blockIdx.x];
@@ -725,14 +754,15 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     const int end = min(beg + kChunk, tile_off[tile + 1]);
     const int lane = threadIdx.x;
     float next = records[(int64_t)beg * kRecWords + lane];
-    for (int c = lane; c < RP * RT; c += 64)
-        acc[c] = 0.0f;
+    for (int c = lane; c < RP * RT / 4; c += 64)
+        acc4[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const EventCtx &E = B ? bt.ev[find_event(bt.tile_base, bt.nev, tile)] : e0;
     const PlaneParams P = E.kp;
     const uint32_t event = E.event;
     float *grid = E.grid;
     const int local = tile - E.tile_base;
     const int p0 = (local / E.ntt) * TP, t0 = (local % E.ntt) * TT;
+    const int c0 = t0 - kPadT;  // grid tick of region column 0
     const int *reci = (const int *)rec;
 
     for (int k = beg; k < end; ++k) {
@@ -741,77 +771,105 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
         // the next record is loaded while this patch is rasterized
         if (k + 1 < end)
             next = records[(int64_t)(k + 1) * kRecWords + lane];
-        const int lo_p = reci[kHLoP], lo_t = reci[kHLoT], n_t = reci[kHNt];
-        const int d = reci[kHDepo];
-        const float qf = rec[kHQ];
+        // header words are the same for every lane
+        const int lo_p = __builtin_amdgcn_readfirstlane(reci[kHLoP]);
+        const int lo_t = __builtin_amdgcn_readfirstlane(reci[kHLoT]);
+        const int n_t = __builtin_amdgcn_readfirstlane(reci[kHNt]);
+        const int d = __builtin_amdgcn_readfirstlane(reci[kHDepo]);
+        const float qf = __int_as_float(__builtin_amdgcn_readfirstlane(reci[kHQ]));
         const float *Wp = rec + kRecWp, *Wt = rec + kRecWt;
         if (!P.fluct) {
-            const int cnt = reci[kHItemsP], m = reci[kHMt];
+            const int cnt = __builtin_amdgcn_readfirstlane(reci[kHItemsP]);
+            const int m = __builtin_amdgcn_readfirstlane(reci[kHMt]);
             for (int it = lane; it < cnt; it += 64) {
                 const int i = div_small(it, m), j = it - i * n_t;
-                const int I = lo_p + i, J = lo_t + j;
-                if ((unsigned)I < (unsigned)P.Np && (unsigned)J < (unsigned)P.Nt)
-                    acc[(I - p0) * RT + (J - t0)] += qf * Wp[i] * Wt[j];
+                const int r = lo_p + i - p0, c = lo_t + j - c0;
+                if ((unsigned)r < (unsigned)RP && (unsigned)c < (unsigned)RT)
+                    acc[r * RT + c] += qf * Wp[i] * Wt[j];
             }
         } else {
-            const int qlo = reci[kHQlo], nq = reci[kHNq];
-            const int items_n = reci[kHItemsF], m = reci[kHMq];
+            const int qlo = __builtin_amdgcn_readfirstlane(reci[kHQlo]);
+            const int nq = __builtin_amdgcn_readfirstlane(reci[kHNq]);
+            const int items_n = __builtin_amdgcn_readfirstlane(reci[kHItemsF]);
+            const int m = __builtin_amdgcn_readfirstlane(reci[kHMq]);
             float F[kFluctItems][4];
             float S = 0.0f;
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b) {
-                const int it = lane + 64 * b;
 #pragma unroll
                 for (int mm = 0; mm < 4; ++mm)
                     F[b][mm] = 0.0f;
-                if (it < items_n) {
-                    const int i = div_small(it, m), qd = qlo + (it - i * nq);
+                if (64 * b < items_n) {  // uniform
+                    const int it = lane + 64 * b;
+                    const bool valid = it < items_n;
+                    const int i = valid ? div_small(it, m) : 0;
+                    const int qd = qlo + (it - i * nq);
                     const uint4 r = philox4x32_10(
                         make_uint4((uint32_t)qd, (uint32_t)(lo_p + i), (uint32_t)d, event),
                         P.key0, P.key1);
                     float z[4];
                     box_muller(r.x, r.y, z[0], z[1]);
                     box_muller(r.z, r.w, z[2], z[3]);
-                    const float wp = Wp[i];
+                    // loads at clamped indexes, then selects: no branches
+                    const float wp_raw = Wp[i];
+                    const float wp = valid ? wp_raw : 0.0f;
 #pragma unroll
                     for (int mm = 0; mm < 4; ++mm) {
                         const int j = 4 * qd + mm - lo_t;
-                        if (j >= 0 && j < n_t) {
-                            F[b][mm] = fluct_value(qf, wp * Wt[j], z[mm]);
-                            S += F[b][mm];
-                        }
+                        const bool in = (unsigned)j < (unsigned)n_t;
+                        const float wt_raw = Wt[min(max(j, 0), n_t - 1)];
+                        const float pw = in ? wp * wt_raw : 0.0f;
+                        F[b][mm] = fluct_value(qf, pw, z[mm]);
+                        S += F[b][mm];
                     }
                 }
             }
-            S = wave_sum(S);
-            const float scale = (S > 0.0f) ? qf / S : 0.0f;
+            S = wave_sum_uniform(S);
+            const bool pos = S > 0.0f;
+            const float scale = pos ? qf / S : 0.0f;
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b) {
-                const int it = lane + 64 * b;
-                if (it < items_n) {
+                if (64 * b < items_n) {  // uniform
+                    const int it = lane + 64 * b;
                     const int i = div_small(it, m), qd = qlo + (it - i * nq);
-                    const int I = lo_p + i;
-                    if ((unsigned)I < (unsigned)P.Np) {
+                    const int r = lo_p + i - p0, c = 4 * qd - c0;
+                    if (it < items_n && (unsigned)r < (unsigned)RP && (unsigned)c <= (unsigned)(RT - 4)) {
+                        float v[4];
+                        if (pos) {
 #pragma unroll
-                        for (int mm = 0; mm < 4; ++mm) {
-                            const int J = 4 * qd + mm, j = J - lo_t;
-                            if (j >= 0 && j < n_t && (unsigned)J < (unsigned)P.Nt) {
-                                const float v = (S > 0.0f) ? F[b][mm] * scale : qf * Wp[i] * Wt[j];
-                                acc[(I - p0) * RT + (J - t0)] += v;
+                            for (int mm = 0; mm < 4; ++mm)
+                                v[mm] = F[b][mm] * scale;
+                        } else {
+                            // every fluctuated bin is zero: deposit the mean
+#pragma unroll
+                            for (int mm = 0; mm < 4; ++mm) {
+                                const int j = 4 * qd + mm - lo_t;
+                                const float w = qf * Wp[i] * Wt[min(max(j, 0), n_t - 1)];
+                                v[mm] = ((unsigned)j < (unsigned)n_t) ? w : 0.0f;
                             }
                         }
+                        float4 &cell = acc4[(r * RT + c) >> 2];
+                        float4 a4 = cell;
+                        a4.x += v[0];
+                        a4.y += v[1];
+                        a4.z += v[2];
+                        a4.w += v[3];
+                        cell = a4;
                     }
                 }
             }
         }
         wave_lds_sync();  // the record buffer is rewritten by the next patch
     }
-    for (int c = lane; c < RP * RT; c += 64) {
-        const float v = acc[c];
-        if (v != 0.0f) {
-            const int I = p0 + c / RT, J = t0 + c % RT;
-            if (I < P.Np && J < P.Nt)
-                unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v);
+    for (int c4 = lane; c4 < RP * RT / 4; c4 += 64) {
+        const float4 a4 = acc4[c4];
+        const float v[4] = {a4.x, a4.y, a4.z, a4.w};
+        const int I = p0 + (4 * c4) / RT, J0 = c0 + (4 * c4) % RT;
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+            const int J = J0 + mm;
+            if (v[mm] != 0.0f && I < P.Np && (unsigned)J < (unsigned)P.Nt)
+                unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v[mm]);
         }
     }
 }
