@@ -193,7 +193,8 @@ __device__ __forceinline__ void wave_weights(const Win &w, float *Wp, float *Wt,
 __device__ __forceinline__ float fluct_value(float q, float p, float z)
 {
     const float qp = q * p;
-    return fmaxf(0.0f, qp + z * __builtin_amdgcn_sqrtf(qp * (1.0f - p)));
+    const float var = fmaf(-qp, p, qp);  // q p (1 - p)
+    return fmaxf(0.0f, fmaf(z, __builtin_amdgcn_sqrtf(var), qp));
 }
 
 __device__ __forceinline__ int quad_of(int J) { return J >> 2; }  // floor(J / 4)
@@ -497,16 +498,18 @@ __global__ __launch_bounds__(256) void k_scatter_flat(int64_t n, const int32_t *
 // Fused path: tile binning and LDS-staged rasterization
 // ---------------------------------------------------------------------------
 constexpr int kHaloP = 32, kHaloT = 16;   // LDS region = tile + halo
-constexpr int kRecP = kHaloP + 1;         // longest pitch window of the tile path
+constexpr int kRecP = kHaloP;             // longest pitch window of the tile path
 constexpr int kRecT = kHaloT + 1;         // longest tick window of the tile path
+constexpr int kRecQuads = (kRecT + 2) / 4 + 1;  // most tick quads such a window touches
 constexpr int kRecWords = 64;             // floats per depo record (256 bytes)
-constexpr int kRecWp = 12;                // record offset of the pitch weights
-constexpr int kRecWt = kRecWp + kRecP;    // record offset of the tick weights
-static_assert(kRecWt + kRecT <= kRecWords, "depo record overflow");
+constexpr int kRecWp = 8;                 // record offset of the pitch weights
+constexpr int kRecWt = kRecWp + kRecP;    // record offset of the quad-aligned tick weights
+static_assert(kRecWt % 4 == 0, "tick quads must be 16-byte aligned");
+static_assert(kRecWt + 4 * kRecQuads <= kRecWords, "depo record overflow");
 constexpr int kChunk = 16;                // depos per tile work item (one wavefront)
-constexpr int kFluctItems = 4;            // work items per lane held in registers
-// A tile-path patch has at most kRecP * (kRecT / 4 + 2) = 231 Philox calls.
-static_assert(kRecP * (kRecT / 4 + 2) <= 64 * kFluctItems, "fluctuation items overflow");
+constexpr int kFluctItems = 3;            // work items per lane held in registers
+// A tile-path patch has at most kRecP * kRecQuads = 160 (row, quad) items.
+static_assert(kRecP * kRecQuads <= 64 * kFluctItems, "patch items overflow");
 
 struct TileGeom {
     int tp, tt, rp, rt, ntt;
@@ -589,8 +592,8 @@ __global__ __launch_bounds__(256) void k_prep_bin(EventCtx e0, BatchTables bt, i
 
 // Tile schedule, two kernels over blocks of kSchedTiles tiles: per-tile depo
 // counts -> exclusive list offsets (in place, ntiles + 1 entries, the scan of
-// Sec. 4.3), and the list of (tile, chunk) work items of at most kChunk depos.
-// counters[2] = number of work items.
+// Sec. 4.3), and the list of work items {tile, first record, end record, 0}
+// of at most kChunk depos each.  counters[2] = number of work items.
 constexpr int kSchedThreads = 256, kSchedPer = 16, kSchedTiles = kSchedThreads * kSchedPer;
 
 __device__ __forceinline__ int chunks_of(int count) { return (count + kChunk - 1) / kChunk; }
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(kSchedThreads) void k_tile_sums(const int32_t *tile
 
 __global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_count, int ntiles,
                                                                 const int2 *block_tot,
-                                                                int2 *items, int32_t *counters)
+                                                                int4 *items, int32_t *counters)
 {
     __shared__ int sh[kSchedThreads / 64];
     int base_t = 0, base_c = 0;
@@ -645,8 +648,10 @@ __global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_c
         if (idx <= ntiles)
             tile_count[idx] = off_t;
         const int nch = chunks_of(cnt[k]);
-        for (int j = 0; j < nch; ++j)
-            items[off_c + j] = make_int2(idx, j);
+        for (int j = 0; j < nch; ++j) {
+            const int b = off_t + j * kChunk;
+            items[off_c + j] = make_int4(idx, b, min(b + kChunk, off_t + cnt[k]), 0);
+        }
         off_t += cnt[k];
         off_c += nch;
     }
@@ -677,50 +682,59 @@ __device__ __forceinline__ int div_small(int a, int m) { return (int)(__umul24(a
 __device__ __forceinline__ int magic_small(int b) { return ((1 << 20) + b - 1) / b; }
 
 // Depo records in tile-list order.  Header words: lo_p, lo_t, n_p, n_t, depo
-// index, charge (float), first tick quad, tick quads, the division magics of
-// the quad count and of n_t, the Philox work items n_p * quads and the bins
-// n_p * n_t; then the pitch and tick weight vectors.
-enum { kHLoP, kHLoT, kHNp, kHNt, kHDepo, kHQ, kHQlo, kHNq, kHMq, kHMt, kHItemsF, kHItemsP };
-static_assert(kHItemsP < kRecWp, "record header overflow");
+// index, charge (float) and the division magic of the tick quad count; then
+// the pitch weights, and the tick weights placed by tick quad: entry
+// 4 (floor(J / 4) - floor(lo_t / 4)) + J mod 4 holds the weight of tick J, and
+// the entries of the first and last quad outside the window hold zero.
+enum { kHLoP, kHLoT, kHNp, kHNt, kHDepo, kHQ, kHMq, kHeaderWords };
+static_assert(kHeaderWords <= kRecWp, "record header overflow");
+constexpr int kStageStride = kRecWords + 1;  // odd: one LDS bank per lane
 
+// One wavefront per block: each lane computes one record into LDS, then the
+// wavefront writes the records out one 256-byte row at a time.
 template <bool B>
-__global__ __launch_bounds__(256) void k_fill_records(EventCtx e0, BatchTables bt, int64_t ntotal,
-                                                      const int32_t *depo_tile,
-                                                      const int32_t *depo_slot,
-                                                      const int32_t *tile_off, float *records)
+__global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt, int64_t ntotal,
+                                                     const int32_t *depo_tile,
+                                                     const int32_t *depo_slot,
+                                                     const int32_t *tile_off, float *records)
 {
-    const int64_t gd = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gd >= ntotal)
-        return;
-    const int t = depo_tile[gd];
-    if (t < 0)
-        return;
-    const EventCtx &E = B ? bt.ev[find_event(bt.depo_base, bt.nev, (int)gd)] : e0;
-    const int64_t d = gd - E.depo_base;  // index in the event's own depo array
-    const int64_t pos = (int64_t)tile_off[t] + depo_slot[gd];
-    const Win w = depo_window(E.depos[d], E.kp);
-    float *rec = records + pos * kRecWords;
-    int *h = (int *)rec;
-    const int qlo = quad_of(w.lo_t), nq = quad_of(w.lo_t + w.n_t - 1) - qlo + 1;
-    *(int4 *)h = make_int4(w.lo_p, w.lo_t, w.n_p, w.n_t);
-    h[kHDepo] = (int)d;
-    rec[kHQ] = (float)w.q;
-    h[kHQlo] = qlo;
-    h[kHNq] = nq;
-    h[kHMq] = magic_small(nq);
-    h[kHMt] = magic_small(w.n_t);
-    h[kHItemsF] = w.n_p * nq;
-    h[kHItemsP] = w.n_p * w.n_t;
-    thread_axis_weights(w.lo_p, w.n_p, w.mu_p, w.s_p, rec + kRecWp);
-    thread_axis_weights(w.lo_t, w.n_t, w.mu_t, w.s_t, rec + kRecWt);
+    __shared__ float stage[64 * kStageStride];
+    const int lane = threadIdx.x;
+    const int64_t gd = blockIdx.x * (int64_t)64 + lane;
+    int pos = -1;
+    const int t = (gd < ntotal) ? depo_tile[gd] : -1;
+    if (t >= 0) {
+        const EventCtx &E = B ? bt.ev[find_event(bt.depo_base, bt.nev, (int)gd)] : e0;
+        const int64_t d = gd - E.depo_base;  // index in the event's own depo array
+        pos = tile_off[t] + depo_slot[gd];
+        const Win w = depo_window(E.depos[d], E.kp);
+        float *rec = stage + lane * kStageStride;
+        int *h = (int *)rec;
+        const int off = w.lo_t & 3;
+        const int nq = quad_of(w.lo_t + w.n_t - 1) - quad_of(w.lo_t) + 1;
+        h[kHLoP] = w.lo_p;
+        h[kHLoT] = w.lo_t;
+        h[kHNp] = w.n_p;
+        h[kHNt] = w.n_t;
+        h[kHDepo] = (int)d;
+        rec[kHQ] = (float)w.q;
+        h[kHMq] = magic_small(nq);
+        float *Wt = rec + kRecWt;
+        for (int k = 0; k < off; ++k)
+            Wt[k] = 0.0f;
+        for (int k = off + w.n_t; k < 4 * nq; ++k)
+            Wt[k] = 0.0f;
+        thread_axis_weights(w.lo_p, w.n_p, w.mu_p, w.s_p, rec + kRecWp);
+        thread_axis_weights(w.lo_t, w.n_t, w.mu_t, w.s_t, Wt + off);
+    }
+    wave_lds_sync();
+    for (int r = 0; r < 64; ++r) {
+        const int pr = __builtin_amdgcn_readlane(pos, r);
+        if (pr >= 0)
+            records[(int64_t)pr * kRecWords + lane] = stage[r * kStageStride + lane];
+    }
 }
 
-// One wavefront per (tile, chunk of <= kChunk depos), rasterizing one patch
-// at a time into its own LDS copy of the tile region (tile + halo).  The bins
-// of one patch are distinct, so the deposits are plain read-add-write LDS
-// accesses; no other wavefront touches the region.  The region's non-zero
-// cells are then added to the grid with float atomics.
-//
 // Region columns start kPadT ticks before the tile and rows are a multiple of
 // four floats, so that a tick quad (four ticks 4k .. 4k + 3, the unit one
 // Philox block covers) is one aligned 16-byte LDS access.  A quad's ticks
@@ -734,133 +748,168 @@ constexpr int region_cols()
     return TT + kHaloT + 2 * kPadT;
 }
 
+// Header of one record, read from the lanes that hold its words (lane w holds
+// word w): window, depo, charge and the (row, tick quad) work items.
+struct PatchHdr {
+    int lo_p, lo_t, d, m, qlo, nq, items;
+    float q;
+};
+
+__device__ __forceinline__ PatchHdr patch_header(float cur)
+{
+    const int w = __float_as_int(cur);
+    PatchHdr h;
+    h.lo_p = __builtin_amdgcn_readlane(w, kHLoP);
+    h.lo_t = __builtin_amdgcn_readlane(w, kHLoT);
+    const int n_p = __builtin_amdgcn_readlane(w, kHNp);
+    const int n_t = __builtin_amdgcn_readlane(w, kHNt);
+    h.d = __builtin_amdgcn_readlane(w, kHDepo);
+    h.q = __int_as_float(__builtin_amdgcn_readlane(w, kHQ));
+    h.m = __builtin_amdgcn_readlane(w, kHMq);
+    h.qlo = quad_of(h.lo_t);
+    h.nq = quad_of(h.lo_t + n_t - 1) - h.qlo + 1;
+    h.items = n_p * h.nq;
+    return h;
+}
+
+// Work item it = (window row i, tick quad qlo + qq) of one patch: the four
+// bins' values (charge times weights, fluctuated if asked) and the float4
+// cell of the region they go to (-1: not deposited).
+template <int RP, int RT, bool FLUCT>
+__device__ __forceinline__ void patch_item(const PatchHdr &h, int it, const float *Wp,
+                                           const float4 *Wq, int p0, int c0, uint32_t key0,
+                                           uint32_t key1, uint32_t event, float F[4], int &cell)
+{
+    const bool valid = it < h.items;
+    const int i = div_small(it, h.m);
+    const int qq = valid ? it - i * h.nq : 0;
+    const int qd = h.qlo + qq;
+    const int r = h.lo_p + i - p0, c = 4 * qd - c0;
+    cell = (valid && (unsigned)r < (unsigned)RP && (unsigned)c <= (unsigned)(RT - 4))
+               ? (r * RT + c) >> 2
+               : -1;
+    // loads at in-range indexes, then a select: no branches
+    const float wp_raw = Wp[valid ? i : 0];
+    const float wp = valid ? wp_raw : 0.0f;
+    const float4 wq = Wq[qq];
+    const float wt[4] = {wq.x, wq.y, wq.z, wq.w};
+    if (FLUCT) {
+        const uint4 rr = philox4x32_10(
+            make_uint4((uint32_t)qd, (uint32_t)(h.lo_p + i), (uint32_t)h.d, event), key0, key1);
+        float z[4];
+        box_muller(rr.x, rr.y, z[0], z[1]);
+        box_muller(rr.z, rr.w, z[2], z[3]);
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm)
+            F[mm] = fluct_value(h.q, wp * wt[mm], z[mm]);
+    } else {
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm)
+            F[mm] = h.q * (wp * wt[mm]);
+    }
+}
+
+// One wavefront per work item (tile, chunk of <= kChunk depos), rasterizing
+// one patch at a time into its own LDS copy of the tile region (tile + halo).
+// The bins of one patch are distinct, so the deposits are plain
+// read-add-write LDS accesses; no other wavefront touches the region.  The
+// region's non-zero cells are then added to the grid with float atomics.
+// (A wavefront that went on to further items would, before using their
+// loads, wait for its atomics: global loads and stores share one counter.)
 template <int TP, int TT, bool B>
 __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
-                                                     const int2 *__restrict__ items,
-                                                     const int32_t *__restrict__ tile_off,
+                                                     const int4 *__restrict__ items,
                                                      const int32_t *__restrict__ counters,
                                                      EventCtx e0, BatchTables bt)
 {
     constexpr int RP = TP + kHaloP, RT = region_cols<TT>();
     static_assert(RT % 4 == 0, "region rows must hold whole quads");
     __shared__ float4 acc4[RP * RT / 4];
-    __shared__ float rec[kRecWords];
-    float *acc = (float *)acc4;
+    __shared__ float4 rec4[kRecWords / 4];
     if ((int)blockIdx.x >= counters[2])
         return;
-    const int2 it2 = items[blockIdx.x];
-    const int tile = it2.x;
-    const int beg = tile_off[tile] + it2.y * kChunk;
-    const int end = min(beg + kChunk, tile_off[tile + 1]);
+    const int4 item = items[blockIdx.x];
+    const int tile = item.x, beg = item.y, end = item.z;
     const int lane = threadIdx.x;
     float next = records[(int64_t)beg * kRecWords + lane];
     for (int c = lane; c < RP * RT / 4; c += 64)
         acc4[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const EventCtx &E = B ? bt.ev[find_event(bt.tile_base, bt.nev, tile)] : e0;
     const PlaneParams P = E.kp;
-    const uint32_t event = E.event;
-    float *grid = E.grid;
     const int local = tile - E.tile_base;
     const int p0 = (local / E.ntt) * TP, t0 = (local % E.ntt) * TT;
     const int c0 = t0 - kPadT;  // grid tick of region column 0
-    const int *reci = (const int *)rec;
+    const float *Wp = (const float *)rec4 + kRecWp;
+    const float4 *Wq = rec4 + kRecWt / 4;
 
     for (int k = beg; k < end; ++k) {
-        rec[lane] = next;
-        wave_lds_sync();
+        const float cur = next;
+        ((float *)rec4)[lane] = cur;
         // the next record is loaded while this patch is rasterized
         if (k + 1 < end)
             next = records[(int64_t)(k + 1) * kRecWords + lane];
-        // header words are the same for every lane
-        const int lo_p = __builtin_amdgcn_readfirstlane(reci[kHLoP]);
-        const int lo_t = __builtin_amdgcn_readfirstlane(reci[kHLoT]);
-        const int n_t = __builtin_amdgcn_readfirstlane(reci[kHNt]);
-        const int d = __builtin_amdgcn_readfirstlane(reci[kHDepo]);
-        const float qf = __int_as_float(__builtin_amdgcn_readfirstlane(reci[kHQ]));
-        const float *Wp = rec + kRecWp, *Wt = rec + kRecWt;
-        if (!P.fluct) {
-            const int cnt = __builtin_amdgcn_readfirstlane(reci[kHItemsP]);
-            const int m = __builtin_amdgcn_readfirstlane(reci[kHMt]);
-            for (int it = lane; it < cnt; it += 64) {
-                const int i = div_small(it, m), j = it - i * n_t;
-                const int r = lo_p + i - p0, c = lo_t + j - c0;
-                if ((unsigned)r < (unsigned)RP && (unsigned)c < (unsigned)RT)
-                    acc[r * RT + c] += qf * Wp[i] * Wt[j];
-            }
-        } else {
-            const int qlo = __builtin_amdgcn_readfirstlane(reci[kHQlo]);
-            const int nq = __builtin_amdgcn_readfirstlane(reci[kHNq]);
-            const int items_n = __builtin_amdgcn_readfirstlane(reci[kHItemsF]);
-            const int m = __builtin_amdgcn_readfirstlane(reci[kHMq]);
-            float F[kFluctItems][4];
-            float S = 0.0f;
+        const PatchHdr h = patch_header(cur);
+        wave_lds_sync();
+
+        float F[kFluctItems][4];
+        int cell[kFluctItems];
 #pragma unroll
-            for (int b = 0; b < kFluctItems; ++b) {
+        for (int b = 0; b < kFluctItems; ++b) {
+            cell[b] = -1;
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm)
+                F[b][mm] = 0.0f;
+        }
+        if (P.fluct) {
+#pragma unroll
+            for (int b = 0; b < kFluctItems; ++b)
+                if (64 * b < h.items)  // uniform
+                    patch_item<RP, RT, true>(h, lane + 64 * b, Wp, Wq, p0, c0, P.key0, P.key1,
+                                             E.event, F[b], cell[b]);
+            // renormalise the patch to its charge
+            float acc = 0.0f;
+#pragma unroll
+            for (int b = 0; b < kFluctItems; ++b)
 #pragma unroll
                 for (int mm = 0; mm < 4; ++mm)
-                    F[b][mm] = 0.0f;
-                if (64 * b < items_n) {  // uniform
-                    const int it = lane + 64 * b;
-                    const bool valid = it < items_n;
-                    const int i = valid ? div_small(it, m) : 0;
-                    const int qd = qlo + (it - i * nq);
-                    const uint4 r = philox4x32_10(
-                        make_uint4((uint32_t)qd, (uint32_t)(lo_p + i), (uint32_t)d, event),
-                        P.key0, P.key1);
-                    float z[4];
-                    box_muller(r.x, r.y, z[0], z[1]);
-                    box_muller(r.z, r.w, z[2], z[3]);
-                    // loads at clamped indexes, then selects: no branches
-                    const float wp_raw = Wp[i];
-                    const float wp = valid ? wp_raw : 0.0f;
+                    acc += F[b][mm];
+            const float S = wave_sum_uniform(acc);
+            if (S > 0.0f) {
+                const float scale = h.q / S;
 #pragma unroll
-                    for (int mm = 0; mm < 4; ++mm) {
-                        const int j = 4 * qd + mm - lo_t;
-                        const bool in = (unsigned)j < (unsigned)n_t;
-                        const float wt_raw = Wt[min(max(j, 0), n_t - 1)];
-                        const float pw = in ? wp * wt_raw : 0.0f;
-                        F[b][mm] = fluct_value(qf, pw, z[mm]);
-                        S += F[b][mm];
-                    }
-                }
+                for (int b = 0; b < kFluctItems; ++b)
+#pragma unroll
+                    for (int mm = 0; mm < 4; ++mm)
+                        F[b][mm] *= scale;
+            } else {
+                // every fluctuated bin is zero: deposit the mean
+#pragma unroll
+                for (int b = 0; b < kFluctItems; ++b)
+                    if (64 * b < h.items)
+                        patch_item<RP, RT, false>(h, lane + 64 * b, Wp, Wq, p0, c0, 0, 0, 0,
+                                                  F[b], cell[b]);
             }
-            S = wave_sum_uniform(S);
-            const bool pos = S > 0.0f;
-            const float scale = pos ? qf / S : 0.0f;
+        } else {
 #pragma unroll
-            for (int b = 0; b < kFluctItems; ++b) {
-                if (64 * b < items_n) {  // uniform
-                    const int it = lane + 64 * b;
-                    const int i = div_small(it, m), qd = qlo + (it - i * nq);
-                    const int r = lo_p + i - p0, c = 4 * qd - c0;
-                    if (it < items_n && (unsigned)r < (unsigned)RP && (unsigned)c <= (unsigned)(RT - 4)) {
-                        float v[4];
-                        if (pos) {
+            for (int b = 0; b < kFluctItems; ++b)
+                if (64 * b < h.items)
+                    patch_item<RP, RT, false>(h, lane + 64 * b, Wp, Wq, p0, c0, 0, 0, 0, F[b],
+                                              cell[b]);
+        }
 #pragma unroll
-                            for (int mm = 0; mm < 4; ++mm)
-                                v[mm] = F[b][mm] * scale;
-                        } else {
-                            // every fluctuated bin is zero: deposit the mean
-#pragma unroll
-                            for (int mm = 0; mm < 4; ++mm) {
-                                const int j = 4 * qd + mm - lo_t;
-                                const float w = qf * Wp[i] * Wt[min(max(j, 0), n_t - 1)];
-                                v[mm] = ((unsigned)j < (unsigned)n_t) ? w : 0.0f;
-                            }
-                        }
-                        float4 &cell = acc4[(r * RT + c) >> 2];
-                        float4 a4 = cell;
-                        a4.x += v[0];
-                        a4.y += v[1];
-                        a4.z += v[2];
-                        a4.w += v[3];
-                        cell = a4;
-                    }
-                }
+        for (int b = 0; b < kFluctItems; ++b) {
+            if (64 * b < h.items && cell[b] >= 0) {
+                float4 a4 = acc4[cell[b]];
+                a4.x += F[b][0];
+                a4.y += F[b][1];
+                a4.z += F[b][2];
+                a4.w += F[b][3];
+                acc4[cell[b]] = a4;
             }
         }
         wave_lds_sync();  // the record buffer is rewritten by the next patch
     }
+    float *grid = E.grid;
     for (int c4 = lane; c4 < RP * RT / 4; c4 += 64) {
         const float4 a4 = acc4[c4];
         const float v[4] = {a4.x, a4.y, a4.z, a4.w};
@@ -1002,7 +1051,7 @@ size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles)
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     return align_up(256) + align_up(sizeof(int32_t) * (size_t)(ntiles + 1)) +
            align_up(sizeof(int2) * sched_blocks_of(ntiles)) +
-           align_up(sizeof(int2) * items_cap(ntiles, n)) + 3 * align_up(sizeof(int32_t) * nn) +
+           align_up(sizeof(int4) * items_cap(ntiles, n)) + 3 * align_up(sizeof(int32_t) * nn) +
            align_up(sizeof(float) * kRecWords * nn);
 }
 
@@ -1018,8 +1067,8 @@ RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t nti
     p += align_up(sizeof(int32_t) * (size_t)(ntiles + 1));
     w.block_tot = (int2 *)p;
     p += align_up(sizeof(int2) * sched_blocks_of(ntiles));
-    w.items = (int2 *)p;
-    p += align_up(sizeof(int2) * items_cap(ntiles, n));
+    w.items = (int4 *)p;
+    p += align_up(sizeof(int4) * items_cap(ntiles, n));
     w.depo_tile = (int32_t *)p;
     p += align_up(sizeof(int32_t) * nn);
     w.depo_slot = (int32_t *)p;
@@ -1074,7 +1123,7 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
                        (int)ntiles, w.block_tot);
     hipLaunchKernelGGL(k_tile_schedule, dim3(sched_blocks), dim3(kSchedThreads), 0, s,
                        w.tile_count, (int)ntiles, w.block_tot, w.items, w.counters);
-    hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 256)), dim3(256), 0, s, e0, bt, n,
+    hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64)), dim3(64), 0, s, e0, bt, n,
                        w.depo_tile, w.depo_slot, w.tile_count, w.records);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
@@ -1082,15 +1131,15 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     switch (pl->tile) {
     case 1:
         hipLaunchKernelGGL((k_raster_tiles<64, 64, B>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.tile_count, w.counters, e0, bt);
+                           w.records, w.items, w.counters, e0, bt);
         break;
     case 2:
         hipLaunchKernelGGL((k_raster_tiles<32, 64, B>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.tile_count, w.counters, e0, bt);
+                           w.records, w.items, w.counters, e0, bt);
         break;
     default:
         hipLaunchKernelGGL((k_raster_tiles<32, 32, B>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.tile_count, w.counters, e0, bt);
+                           w.records, w.items, w.counters, e0, bt);
         break;
     }
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess)

@@ -177,7 +177,7 @@ struct RasterWork {
     int32_t *counters;    // [0] invalid depos, [1] large-patch depos, [2] tile work items
     int32_t *tile_count;  // [ntiles + 1] counts -> exclusive list offsets
     int2 *block_tot;      // per schedule block: depos and work items
-    int2 *items;          // (tile, chunk) work items
+    int4 *items;          // work items {tile, first record, end record, 0}
     int32_t *depo_tile;   // [n] tile of each depo (-1: none)
     int32_t *depo_slot;   // [n] position in its tile's list
     int32_t *large;       // [n] depos of the large-patch path
