@@ -23,6 +23,7 @@
 // memory, and every global<->LDS copy issues its loads in batches.
 #include <math.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "wcsim_internal.h"
@@ -220,6 +221,10 @@ __device__ void fft_lds(float2 *buf, const FftPlan &plan, int nseq_shift, int ss
     }
 }
 
+// Marker for the default operand of a transform's first pass (input) or last
+// pass (output): the LDS buffer itself.
+struct InLds {};
+
 // Runtime-plan transform as a policy object (any supported size).
 struct FftRt {
     static constexpr int kMaxThreads = 1024;
@@ -229,18 +234,44 @@ struct FftRt {
     {
         fft_lds(buf, plan, nseq_shift, sstride, estride, tab);
     }
+    // Same contract as FftCt::run_io, by plain copies around run().
+    template <class Load, class Store>
+    __device__ __forceinline__ void run_io(float2 *buf, const float2 *tab, Load load,
+                                           Store store) const
+    {
+        const int total = plan.n << nseq_shift, mask = (1 << nseq_shift) - 1;
+        if constexpr (!std::is_same<Load, InLds>::value) {
+            for (int g = threadIdx.x; g < total; g += blockDim.x)
+                buf[(g & mask) * sstride + (g >> nseq_shift) * estride] =
+                    load(g & mask, g >> nseq_shift);
+            __syncthreads();
+        }
+        run(buf, tab);
+        if constexpr (!std::is_same<Store, InLds>::value) {
+            for (int g = threadIdx.x; g < total; g += blockDim.x)
+                store(g & mask, g >> nseq_shift,
+                      buf[(g & mask) * sstride + (g >> nseq_shift) * estride]);
+        }
+    }
 };
 
 // Compile-time Stockham pass: sizes, strides and the radix are constants, so
-// the index arithmetic folds and the butterflies unroll.
-template <int N, int R, int P, int NSS, int SS, int ES, int NT>
-__device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab)
+// the index arithmetic folds and the butterflies unroll.  With GLOAD the pass
+// takes its inputs from load(s, n) (element n of sequence s) instead of LDS:
+// the first pass of a transform reads global memory directly, all of its loads
+// in flight together, with no separate copy into LDS.  With GSTORE it hands its
+// outputs to store(s, n, value) instead of writing LDS; the caller then
+// synchronises before LDS is used again.
+template <int N, int R, int P, int NSS, int SS, int ES, int NT, bool GLOAD, bool GSTORE,
+          class Load, class Store>
+__device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab, Load &load, Store &store)
 {
     constexpr int NB = N / R;
     constexpr int TOTAL = NB << NSS;
     constexpr int MAXB = (TOTAL + NT - 1) / NT;
     constexpr int TWSTEP = N / (P * R);
     constexpr int MASK = (1 << NSS) - 1;
+    static_assert(!GLOAD || P == 1, "only the first pass reads its inputs from a loader");
     const int tid = threadIdx.x;
     float2 v[MAXB][R];
 #pragma unroll
@@ -248,13 +279,20 @@ __device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab)
         const int g = tid + b * NT;
         if ((TOTAL % NT) == 0 || g < TOTAL) {
             const int s = g & MASK, i = g >> NSS;
-            const float2 *src = buf + s * SS + i * ES;
+            if constexpr (GLOAD) {
 #pragma unroll
-            for (int t = 0; t < R; ++t)
-                v[b][t] = src[t * NB * ES];
+                for (int t = 0; t < R; ++t)
+                    v[b][t] = load(s, i + t * NB);
+            } else {
+                const float2 *src = buf + s * SS + i * ES;
+#pragma unroll
+                for (int t = 0; t < R; ++t)
+                    v[b][t] = src[t * NB * ES];
+            }
         }
     }
-    __syncthreads();
+    if constexpr (!GLOAD)
+        __syncthreads();  // every input is read before any output lands in LDS
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
         const int g = tid + b * NT;
@@ -264,31 +302,48 @@ __device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab)
             if (P > 1)
                 twiddle_powers<R>(v[b], tw_at(tab, k * TWSTEP));
             dft<R>(v[b]);
-            float2 *dst = buf + s * SS + ((i - k) * R + k) * ES;
+            const int n0 = (i - k) * R + k;
 #pragma unroll
-            for (int t = 0; t < R; ++t)
-                dst[t * P * ES] = v[b][t];
+            for (int t = 0; t < R; ++t) {
+                if constexpr (GSTORE)
+                    store(s, n0 + t * P, v[b][t]);
+                else
+                    buf[s * SS + (n0 + t * P) * ES] = v[b][t];
+            }
         }
     }
-    __syncthreads();
+    if constexpr (!GSTORE)
+        __syncthreads();
 }
 
-template <int N, int NSS, int SS, int ES, int NT, int P, int R, int... Rest>
-__device__ __forceinline__ void ct_fft(float2 *buf, const float2 *tab)
+template <int N, int NSS, int SS, int ES, int NT, int P, class Load, class Store, int R,
+          int... Rest>
+__device__ __forceinline__ void ct_fft(float2 *buf, const float2 *tab, Load &load, Store &store)
 {
-    ct_pass<N, R, P, NSS, SS, ES, NT>(buf, tab);
-    if constexpr (sizeof...(Rest) > 0)
-        ct_fft<N, NSS, SS, ES, NT, P * R, Rest...>(buf, tab);
+    constexpr bool kLast = sizeof...(Rest) == 0;
+    constexpr bool kLoad = P == 1 && !std::is_same<Load, InLds>::value;
+    constexpr bool kStore = kLast && !std::is_same<Store, InLds>::value;
+    ct_pass<N, R, P, NSS, SS, ES, NT, kLoad, kStore>(buf, tab, load, store);
+    if constexpr (!kLast)
+        ct_fft<N, NSS, SS, ES, NT, P * R, Load, Store, Rest...>(buf, tab, load, store);
 }
 
-// Compile-time transform as a policy object.
+// Compile-time transform as a policy object.  run(): LDS in, LDS out.
+// run_io(load, store): either end may be a functor or InLds.
 template <int N, int NSS, int SS, int ES, int NT, int... Rs>
 struct FftCt {
     static constexpr int kThreads = NT;
     static constexpr int kMaxThreads = NT;
     __device__ __forceinline__ void run(float2 *buf, const float2 *tab) const
     {
-        ct_fft<N, NSS, SS, ES, NT, 1, Rs...>(buf, tab);
+        InLds in, out;
+        ct_fft<N, NSS, SS, ES, NT, 1, InLds, InLds, Rs...>(buf, tab, in, out);
+    }
+    template <class Load, class Store>
+    __device__ __forceinline__ void run_io(float2 *buf, const float2 *tab, Load load,
+                                           Store store) const
+    {
+        ct_fft<N, NSS, SS, ES, NT, 1, Load, Store, Rs...>(buf, tab, load, store);
     }
 };
 
@@ -383,32 +438,25 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
     load_tables(tw, tabN2, tabH);
     const int row0 = blk * RPW;
     const bool vec2 = ((ncols & 1) == 0) && ((in_stride & 1) == 0);
-    for (int s = 0; s < RPW; ++s) {
-        const int row = row0 + s;
-        const float *src = in + (int64_t)row * in_stride;
-        const bool live = row < nrows;
-        batched_copy(
-            N2,
-            [&](int n) {
-                const int t = 2 * n;
-                float2 v = make_float2(0.0f, 0.0f);
-                if (live) {
-                    if (vec2) {
-                        if (t < ncols)
-                            v = *(const float2 *)(src + t);
-                    } else {
-                        if (t < ncols)
-                            v.x = src[t];
-                        if (t + 1 < ncols)
-                            v.y = src[t + 1];
-                    }
-                }
-                return v;
-            },
-            [&](int n, float2 v) { lds[s * S + n] = v; });
-    }
-    __syncthreads();
-    fft.run(lds, tabN2);
+    // z_n of row s straight from global memory into the first pass
+    auto load = [&](int s, int n) {
+        const int row = row0 + s, t = 2 * n;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (row < nrows) {
+            const float *src = in + (int64_t)row * in_stride;
+            if (vec2) {
+                if (t < ncols)
+                    v = *(const float2 *)(src + t);
+            } else {
+                if (t < ncols)
+                    v.x = src[t];
+                if (t + 1 < ncols)
+                    v.y = src[t + 1];
+            }
+        }
+        return v;
+    };
+    fft.run_io(lds, tabN2, load, InLds{});
     const int half = N2 / 2;
     for (int s = 0; s < RPW; ++s) {
         float2 *b = lds + s * S;
@@ -520,28 +568,22 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(C2RIo io, BatchTa
         }
     }
     __syncthreads();
-    fft.run(lds, tabN2);
     const bool vec2 = ((ncols & 1) == 0) && ((out_stride & 1) == 0);
-    for (int s = 0; s < RPW; ++s) {
-        const int row = row0 + s;
-        if (row >= nrows)
-            break;
+    // the last pass writes x_{2n}, x_{2n+1} of row s straight to global memory
+    auto store = [&](int s, int n, float2 z) {
+        const int row = row0 + s, t = 2 * n;
+        if (row >= nrows || t >= ncols)
+            return;
         float *dst = out + (int64_t)row * out_stride;
-        const float2 *b = lds + s * S;
-        for (int n = threadIdx.x; n < N2; n += blockDim.x) {
-            const int t = 2 * n;
-            if (t >= ncols)
-                continue;
-            const float2 z = b[n];
-            if (vec2) {
-                *(float2 *)(dst + t) = make_float2(z.x, -z.y);
-            } else {
-                dst[t] = z.x;
-                if (t + 1 < ncols)
-                    dst[t + 1] = -z.y;
-            }
+        if (vec2) {
+            *(float2 *)(dst + t) = make_float2(z.x, -z.y);
+        } else {
+            dst[t] = z.x;
+            if (t + 1 < ncols)
+                dst[t + 1] = -z.y;
         }
-    }
+    };
+    fft.run_io(lds, tabN2, InLds{}, store);
 }
 
 // ---------------------------------------------------------------------------
@@ -602,42 +644,40 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
     const int P0 = blk * V;
     const int in0 = (mode == 2) ? 0 : P0 + r0 - (Rp - 1);
     const float2 *src = X + ((int64_t)c * nrows_in << F_shift);
-    batched_copy(
-        LF,
-        [&](int g) {
-            const int row = in0 + (g >> F_shift);
-            return (row >= 0 && row < nrows_in) ? src[((int64_t)row << F_shift) + (g & (F - 1))]
-                                                : make_float2(0.0f, 0.0f);
-        },
-        [&](int g, float2 v) { lds[g] = v; });
-    __syncthreads();
-    fft.run(lds, tabL);
+    // block row n, column s straight from global memory into the first pass
+    auto load = [&](int s, int n) {
+        const int row = in0 + n;
+        return (row >= 0 && row < nrows_in) ? src[((int64_t)row << F_shift) + s]
+                                            : make_float2(0.0f, 0.0f);
+    };
     if (mode == 2) {
         float2 *dst = Y + (int64_t)c * LF;
-        for (int g = threadIdx.x; g < LF; g += blockDim.x)
-            dst[g] = cscale(lds[g], scale);
+        fft.run_io(lds, tabL, load,
+                   [&](int s, int n, float2 v) { dst[(n << F_shift) + s] = cscale(v, scale); });
         return;
     }
+    // forward transform; its last pass multiplies by the response spectrum and
+    // conjugates (the inverse runs as a forward transform of the conjugate)
     const float2 *Kc = K + (int64_t)c * LF;
-    batched_copy(
-        LF, [&](int g) { return Kc[g]; },
-        [&](int g, float2 k) { lds[g] = conjf2(cmul(lds[g], k)); });
+    fft.run_io(lds, tabL, load, [&](int s, int n, float2 v) {
+        const int g = (n << F_shift) + s;
+        lds[g] = conjf2(cmul(v, Kc[g]));
+    });
     __syncthreads();
-    fft.run(lds, tabL);
+    // inverse; its last pass writes the block's valid rows
     float2 *dst = Y + ((int64_t)c * nrows_out << F_shift);
-    const int first = (Rp - 1) << F_shift;
-    for (int g = first + threadIdx.x; g < LF; g += blockDim.x) {
-        const int p = P0 + (g >> F_shift) - (Rp - 1);
-        if (p >= nrows_in)
-            break;
+    fft.run_io(lds, tabL, InLds{}, [&](int s, int n, float2 v) {
+        const int p = P0 + n - (Rp - 1);
+        if (n < Rp - 1 || p >= nrows_in)
+            return;
         int o = p;
         if (mode == 1) {
             if (p % nimpact != nimpact / 2)
-                continue;
+                return;
             o = p / nimpact;
         }
-        dst[((int64_t)o << F_shift) + (g & (F - 1))] = conjf2(lds[g]);
-    }
+        dst[((int64_t)o << F_shift) + s] = conjf2(v);
+    });
 }
 
 int ilog2(int v)
