@@ -706,16 +706,24 @@ int threads_for(const FftPlan &plan, int nseq)
     return threads;
 }
 
-constexpr int kRowsPerBlock = 2;  // rows per workgroup in passes A and C (power of two)
+// Rows per workgroup in passes A and C.  One row keeps a workgroup's LDS at
+// one row (25 KB for N2 = 3125), so six workgroups share a CU and the global
+// loads of some overlap the transforms of others; two rows per workgroup
+// halve that overlap and measured slower.
+constexpr int kRowsShift = 0;
+constexpr int kRowsPerBlock = 1 << kRowsShift;
 
-// Compile-time transforms for the sizes the default schedules use:
+// Compile-time transforms for the sizes the schedules use:
 //   tick axis N2 = 3125 (N' = 6250, 6000-tick planes) and N2 = 600 (N' = 1200,
-//   1000-tick planes), two rows per workgroup;
-//   pitch axis L = 1024 with 8-column chunks and L = 512 with 16-column chunks.
-using TickCt3125 = FftCt<3125, 1, 3126, 1, 256, 5, 5, 5, 5, 5>;
-using TickCt600 = FftCt<600, 1, 601, 1, 256, 8, 5, 5, 3>;
-using PitchCt1024x8 = FftCt<1024, 3, 1, 8, 256, 8, 8, 4, 4>;
-using PitchCt512x16 = FftCt<512, 4, 1, 16, 256, 8, 8, 8>;
+//   1000-tick planes);
+//   pitch axis L = 1024 with 8- or 16-column chunks and L = 512 with
+//   16-column chunks.  A pitch block fills most of the LDS, so a CU holds one
+//   or two workgroups; they get 512 or 1024 threads to keep enough waves.
+using TickCt3125 = FftCt<3125, kRowsShift, 3126, 1, 256, 5, 5, 5, 5, 5>;
+using TickCt600 = FftCt<600, kRowsShift, 601, 1, 128, 8, 5, 5, 3>;
+using PitchCt1024x8 = FftCt<1024, 3, 1, 8, 512, 8, 8, 4, 4>;
+using PitchCt1024x16 = FftCt<1024, 4, 1, 16, 1024, 8, 8, 4, 4>;
+using PitchCt512x16 = FftCt<512, 4, 1, 16, 512, 8, 8, 8>;
 
 int table_len(int m) { return kTwLo + (m + kTwLo - 1) / kTwLo; }
 
@@ -732,7 +740,7 @@ void launch_r2c(const wcsim_plane *pl, FFT fft, int threads, const R2CIo &io,
     const TwTables tw = tick_tables(pl);
     const size_t lds = sizeof(float2) * ((size_t)(pl->N2 + 1) * kRowsPerBlock + tw.na + tw.nb);
     hipLaunchKernelGGL((k_rows_r2c<FFT, B>), dim3(blocks), dim3(threads), lds, s, io, bt, pl->N2,
-                       fft, tw, ilog2(pl->F), pl->C, ilog2(kRowsPerBlock));
+                       fft, tw, ilog2(pl->F), pl->C, kRowsShift);
 }
 
 template <class FFT, bool B>
@@ -742,7 +750,7 @@ void launch_c2r(const wcsim_plane *pl, FFT fft, int threads, const C2RIo &io,
     const TwTables tw = tick_tables(pl);
     const size_t lds = sizeof(float2) * ((size_t)(pl->N2 + 1) * kRowsPerBlock + tw.na + tw.nb);
     hipLaunchKernelGGL((k_rows_c2r<FFT, B>), dim3(blocks), dim3(threads), lds, s, io, bt, pl->N2,
-                       fft, tw, ilog2(pl->F), pl->C, ilog2(kRowsPerBlock));
+                       fft, tw, ilog2(pl->F), pl->C, kRowsShift);
 }
 
 bool plan_is(const FftPlan &p, std::initializer_list<int> radices)
@@ -780,12 +788,12 @@ template <bool B>
 hipError_t rows_r2c_any(const wcsim_plane *pl, const R2CIo &io, const BatchTables &bt,
                         unsigned blocks, hipStream_t s)
 {
-    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
+    if (pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
         launch_r2c<TickCt3125, B>(pl, TickCt3125(), TickCt3125::kThreads, io, bt, blocks, s);
-    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
+    else if (pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
         launch_r2c<TickCt600, B>(pl, TickCt600(), TickCt600::kThreads, io, bt, blocks, s);
     else
-        launch_r2c<FftRt, B>(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
+        launch_r2c<FftRt, B>(pl, runtime_fft(pl->planT, kRowsShift, pl->N2 + 1, 1),
                              tick_threads(pl), io, bt, blocks, s);
     return hipGetLastError();
 }
@@ -794,12 +802,12 @@ template <bool B>
 hipError_t rows_c2r_any(const wcsim_plane *pl, const C2RIo &io, const BatchTables &bt,
                         unsigned blocks, hipStream_t s)
 {
-    if (kRowsPerBlock == 2 && pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
+    if (pl->N2 == 3125 && plan_is(pl->planT, {5, 5, 5, 5, 5}))
         launch_c2r<TickCt3125, B>(pl, TickCt3125(), TickCt3125::kThreads, io, bt, blocks, s);
-    else if (kRowsPerBlock == 2 && pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
+    else if (pl->N2 == 600 && plan_is(pl->planT, {8, 5, 5, 3}))
         launch_c2r<TickCt600, B>(pl, TickCt600(), TickCt600::kThreads, io, bt, blocks, s);
     else
-        launch_c2r<FftRt, B>(pl, runtime_fft(pl->planT, ilog2(kRowsPerBlock), pl->N2 + 1, 1),
+        launch_c2r<FftRt, B>(pl, runtime_fft(pl->planT, kRowsShift, pl->N2 + 1, 1),
                              tick_threads(pl), io, bt, blocks, s);
     return hipGetLastError();
 }
@@ -836,6 +844,9 @@ hipError_t pitch_any(const wcsim_plane *pl, const PitchIo &io, const BatchTables
     if (pl->L == 1024 && pl->F == 8 && plan_is(pl->planL, {8, 8, 4, 4}))
         launch_pitch<PitchCt1024x8, B>(pl, PitchCt1024x8(), PitchCt1024x8::kThreads, io, bt,
                                        blocks, scale, s);
+    else if (pl->L == 1024 && pl->F == 16 && plan_is(pl->planL, {8, 8, 4, 4}))
+        launch_pitch<PitchCt1024x16, B>(pl, PitchCt1024x16(), PitchCt1024x16::kThreads, io, bt,
+                                        blocks, scale, s);
     else if (pl->L == 512 && pl->F == 16 && plan_is(pl->planL, {8, 8, 8}))
         launch_pitch<PitchCt512x16, B>(pl, PitchCt512x16(), PitchCt512x16::kThreads, io, bt,
                                        blocks, scale, s);

@@ -174,7 +174,8 @@ def test_convolve_schedules_agree(ws):
     g = torch.from_numpy(G).cuda()
     for sc in ({}, {"fft_ticks": 1024}, {"fft_ticks": 1000, "freq_chunk": 8},
                {"fft_pitch": 512, "freq_chunk": 16}, {"fft_ticks": 1250},
-               {"fft_pitch": 128}, {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 240}):
+               {"fft_pitch": 128}, {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 240},
+               {"fft_pitch": 1024, "freq_chunk": 16}, {"fft_ticks": 6250}, {"fft_ticks": 1200}):
         P = ws.Plane(pl, W.physics(False), R, r0=25, schedule=sc)
         out = ws.convolve(P, g, kind=ws.OUT_PITCH)
         assert normwise(out.cpu().numpy(), ref) <= CONV_TOL, sc
