@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served-form measurement")
     ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default schedules instead of autotuned ones")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy kernel "
                          "whose HBM counters scale the kernels' FETCH_SIZE / WRITE_SIZE)")
@@ -129,21 +131,31 @@ def cpu_baseline(w, kind_wire: bool) -> dict:
                       % (dep.shape[0], pl["nwires"] * pl["nimpact"], pl["nticks"], dt)}
 
 
-def batch_comparison(wcsim, W, dev, nevents: int, rounds: int = 3) -> dict:
+def batch_comparison(wcsim, W, dev, nevents: int, tuner=None, rounds: int = 3) -> dict:
     """The batch workload (uneven events: depo counts log-uniform in
     10^4..10^6, 100/480/800/960 wires x 6000 ticks): `nevents` plain
-    per-event launches against one captured batch, both timed over whole
-    rounds with inputs resident in HBM."""
+    per-event launches (library default schedules) against one captured batch
+    (schedules from the autotuner, one per wire count, tuned on that wire
+    count's median event), both timed over whole rounds with inputs resident
+    in HBM."""
     import torch
 
     evs = W.batch_events(nevents=nevents)
     phys = W.physics(True)
-    planes = {}
-    for e in evs:
-        nw = e["plane"]["nwires"]
-        if nw not in planes:
-            planes[nw] = wcsim.Plane(e["plane"], phys, e["response"])
+    planes, tuned, schedules = {}, {}, {}
+    for nw in sorted({e["plane"]["nwires"] for e in evs}):
+        mine = sorted((e for e in evs if e["plane"]["nwires"] == nw),
+                      key=lambda e: e["depos"].shape[0])
+        e = mine[len(mine) // 2]
+        planes[nw] = wcsim.Plane(e["plane"], phys, e["response"])
+        sched = None
+        if tuner is not None:
+            sched = tuner.tune(e["plane"], phys, e["response"],
+                               torch.from_numpy(e["depos"]).to(dev))
+        schedules[nw] = sched or {}
+        tuned[nw] = wcsim.Plane(e["plane"], phys, e["response"], schedule=sched)
     pl = [planes[e["plane"]["nwires"]] for e in evs]
+    plb = [tuned[e["plane"]["nwires"]] for e in evs]
     deps = [torch.from_numpy(e["depos"]).to(dev) for e in evs]
     ids = [e["event_id"] for e in evs]
     outs = [torch.empty((p.nwires, p.nticks), dtype=torch.float32, device=dev) for p in pl]
@@ -161,7 +173,7 @@ def batch_comparison(wcsim, W, dev, nevents: int, rounds: int = 3) -> dict:
         for p, d, i, o in zip(pl, deps, ids, outs):
             wcsim.simulate_event(p, d, i, out=o, workspace=wsp)
 
-    batch = wcsim.Batch(pl, [d.shape[0] for d in deps])
+    batch = wcsim.Batch(plb, [d.shape[0] for d in deps])
 
     def batched():
         batch.run(deps, ids, outs)
@@ -181,20 +193,39 @@ def batch_comparison(wcsim, W, dev, nevents: int, rounds: int = 3) -> dict:
     res["events"] = nevents
     res["depos"] = int(ntot)
     res["speedup"] = res["plain"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    res["batched_schedules"] = {str(k): v for k, v in schedules.items()}
     return res
 
 
-def serve_measurement(W, nreq: int) -> dict:
+def serve_measurement(W, nreq: int, tuner=None) -> dict:
     """The serving workload (requests of 1-3 planes of 100-960 wires x 6000
     ticks, depo counts log-uniform in 10^3..2x10^6): saturated throughput
-    (all requests at t = 0), then Poisson arrivals at fractions of it."""
+    (all requests at t = 0), then Poisson arrivals at fractions of it.  With
+    a tuner, one schedule tuned on a representative plane (480 wires, 200,000
+    track depos) serves every plane of the same tick count and response
+    shape, so that requests still group into one batch class."""
+    import torch
+
     from paper_2304_01841_amd import serve
 
     reqs = W.serve_requests(nreq=nreq)
-    srv = serve.Server(W.physics(True), hbm_budget=64 << 30, slots=4, max_batch=8)
+    phys = W.physics(True)
+    schedule_for, sched = None, None
+    if tuner is not None:
+        rng = np.random.default_rng(6000)
+        rep_plane = W.plane(480, 6000)
+        rep_resp = W.response("unipolar")
+        rep_dep = W.clipped_track_depos(rng, 200_000, (W.BOX_X, W.BOX_Y, 480 * W.PITCH))
+        sched = tuner.tune(rep_plane, phys, rep_resp, torch.from_numpy(rep_dep).cuda())
+        shape = (6000, rep_resp.shape)
+
+        def schedule_for(desc, response):
+            return sched if (desc["nticks"], np.shape(response)) == shape else None
+    srv = serve.Server(phys, hbm_budget=64 << 30, slots=4, max_batch=8,
+                       schedule_for=schedule_for)
     srv.serve(reqs[: min(8, nreq)])  # plane set-up and allocator warm-up
     sat = serve.latency_summary(srv.serve(reqs))
-    out = {"requests": nreq, "budget_gb": 64, "slots": 4, "max_group": 8,
+    out = {"requests": nreq, "budget_gb": 64, "slots": 4, "max_group": 8, "schedule": sched,
            "depos": int(sum(r["depos"].shape[0] for r in reqs)),
            "planes": int(sum(len(r["planes"]) for r in reqs)), "saturated": sat}
     rate = sat["throughput_rps"]
@@ -225,8 +256,16 @@ def main():
     w = W.collection()
     pl, R = w["planes"][0], w["responses"][0]
     kind = wcsim.OUT_WIRE if args.kind == "wire" else wcsim.OUT_PITCH
-    P = wcsim.Plane(pl, w["phys"], R)
     dep = torch.from_numpy(w["depos"]).to(dev)
+    tuner, tuning, sched = None, None, None
+    if not args.no_tune:
+        from paper_2304_01841_amd import autotune
+        tuner = autotune.Tuner()
+        sched = tuner.tune(pl, w["phys"], R, dep, kind=kind)
+        key = autotune.cache_key(pl, R, R.shape[0] // 2, w["phys"]["fluctuate"], dep.shape[0],
+                                 kind)
+        tuning = dict(tuner.entry(key))
+    P = wcsim.Plane(pl, w["phys"], R, schedule=sched)
     n = dep.shape[0]
     nout = P.out_rows(kind)
     out = torch.empty((nout, P.nticks), dtype=torch.float32, device=dev)
@@ -291,11 +330,11 @@ def main():
 
     batch = None
     if not args.no_batch:
-        batch = batch_comparison(wcsim, W, dev, args.batch_events)
+        batch = batch_comparison(wcsim, W, dev, args.batch_events, tuner)
 
     served = None
     if not args.no_serve:
-        served = serve_measurement(W, args.serve_requests)
+        served = serve_measurement(W, args.serve_requests, tuner)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -319,7 +358,9 @@ def main():
                                "per-event launch, %s output" % args.kind,
                    "global_batch": 1, "depos_per_event": n,
                    "fft_ticks": P.info["fft_ticks"], "fft_pitch": P.info["fft_pitch"],
-                   "freq_chunk": P.info["freq_chunk"], "tile": P.info["tile"]},
+                   "freq_chunk": P.info["freq_chunk"], "tile": P.info["tile"],
+                   "schedule": "autotuned" if tuning else "library default"},
+        "tuning": tuning,
         "planes_per_s": planes_per_s,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},

@@ -232,6 +232,22 @@ wcsim_status wcsim_simulate_event_profiled(const wcsim_plane *plane, const wcsim
                                            float *out, wcsim_out out_kind, wcsim_mem out_mem,
                                            void *workspace, void *stream, void *const *events);
 
+/* Schedule tuning (the paper treats launch geometry as a tuning parameter,
+ * Sec. 5.3): times wcsim_simulate_event of one plane under each of `ncand`
+ * candidate schedules on the caller's `n` device depos.  For each candidate
+ * a plane is created from desc/phys (its response spectrum included), two
+ * untimed events are run, then `reps` timed events (HIP events on `stream`);
+ * ms[i] receives the median time per event in milliseconds, or -1 when
+ * candidate i is not a valid schedule for this plane.  Allocates and frees
+ * its own device workspace and output; synchronises `stream`.  Errors:
+ * WCSIM_E_INVALID for bad arguments or when no candidate is valid,
+ * WCSIM_E_NOMEM, WCSIM_E_DEVICE.  Results do not depend on the schedule
+ * (within the stated tolerances); only the time does. */
+wcsim_status wcsim_tune_schedules(const wcsim_plane_desc *desc, const wcsim_physics *phys,
+                                  const wcsim_schedule *cands, int32_t ncand,
+                                  const wcsim_depo *depos, int64_t n, wcsim_out out_kind,
+                                  int32_t reps, void *stream, float *ms);
+
 /* Device pointer to the [npitch][nticks] grid inside a simulate workspace. */
 float *wcsim_workspace_grid(const wcsim_plane *plane, void *workspace, int64_t n);
 

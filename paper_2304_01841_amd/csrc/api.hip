@@ -673,6 +673,70 @@ wcsim_status wcsim_simulate_event_profiled(const wcsim_plane *pl, const wcsim_de
                           stream, (const hipEvent_t *)events);
 }
 
+wcsim_status wcsim_tune_schedules(const wcsim_plane_desc *desc, const wcsim_physics *phys,
+                                  const wcsim_schedule *cands, int32_t ncand,
+                                  const wcsim_depo *depos, int64_t n, wcsim_out out_kind,
+                                  int32_t reps, void *stream, float *ms)
+{
+    if (!desc || !phys || !cands || !ms || ncand < 1 || reps < 1 || n < 0 || (n > 0 && !depos))
+        return fail(WCSIM_E_INVALID, "bad tuning arguments");
+    if (out_kind != WCSIM_OUT_WIRE && out_kind != WCSIM_OUT_PITCH)
+        return fail(WCSIM_E_INVALID, "bad output kind");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    WCS_HIP(hipEventCreate(&t0));
+    if (hipEventCreate(&t1) != hipSuccess) {
+        (void)hipEventDestroy(t0);
+        return fail(WCSIM_E_DEVICE, "hipEventCreate failed");
+    }
+    wcsim_status result = WCSIM_OK;
+    int timed = 0;
+    for (int32_t i = 0; i < ncand && result == WCSIM_OK; ++i) {
+        ms[i] = -1.0f;
+        wcsim_plane *pl = nullptr;
+        if (plane_create(desc, phys, &cands[i], nullptr, stream, &pl) != WCSIM_OK)
+            continue;  // not a valid schedule for this plane
+        const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
+        void *ws = nullptr, *out = nullptr;
+        if (hipMalloc(&ws, wcsim_simulate_workspace_bytes(pl, n, out_kind)) != hipSuccess ||
+            hipMalloc(&out, sizeof(float) * (size_t)nout * pl->Nt) != hipSuccess) {
+            result = fail(WCSIM_E_NOMEM, "device allocation failed while tuning");
+        } else {
+            std::vector<float> t;
+            for (int r = -2; r < reps && result == WCSIM_OK; ++r) {  // r < 0 warm up
+                float e = 0.0f;
+                if (hipEventRecord(t0, s) != hipSuccess ||
+                    (result = simulate_event(pl, depos, n, WCSIM_MEM_DEVICE, 0, (float *)out,
+                                             out_kind, WCSIM_MEM_DEVICE, ws, stream,
+                                             nullptr)) != WCSIM_OK ||
+                    hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                    hipEventElapsedTime(&e, t0, t1) != hipSuccess) {
+                    if (result == WCSIM_OK)
+                        result = fail(WCSIM_E_DEVICE, "timing a candidate schedule failed");
+                    break;
+                }
+                if (r >= 0)
+                    t.push_back(e);
+            }
+            if (result == WCSIM_OK) {
+                std::sort(t.begin(), t.end());
+                ms[i] = t[t.size() / 2];
+                ++timed;
+            }
+        }
+        if (out)
+            (void)hipFree(out);
+        if (ws)
+            (void)hipFree(ws);
+        wcsim_plane_destroy(pl);
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (result == WCSIM_OK && timed == 0)
+        return fail(WCSIM_E_INVALID, "no candidate schedule is valid for this plane");
+    return result;
+}
+
 }  // extern "C"
 
 namespace wcs {

@@ -47,7 +47,7 @@ class Result:
 
 class Server:
     def __init__(self, phys: dict, device="cuda", hbm_budget: int = 64 << 30, slots: int = 4,
-                 max_batch: int = 8, kind: int = wcsim.OUT_WIRE):
+                 max_batch: int = 8, kind: int = wcsim.OUT_WIRE, schedule_for=None):
         self.phys = dict(phys)
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
@@ -55,6 +55,9 @@ class Server:
         self.kind = kind
         # default-priority streams, one per slot
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        # schedule_for(desc, response) -> schedule dict or None (library default),
+        # e.g. from the autotuner's cache
+        self.schedule_for = schedule_for
         self._planes: dict = {}
         self._donors: dict = {}
         self.stats = {"groups": 0, "max_group": 0, "max_inflight_groups": 0,
@@ -68,11 +71,16 @@ class Server:
                desc["dir_z"], desc["pitch_origin"])
         p = self._planes.get(key)
         if p is None:
-            donor = self._donors.get(rkey)
-            p = wcsim.Plane(desc, self.phys, response, share=donor)
+            sched = self.schedule_for(desc, response) if self.schedule_for else None
+            # planes share a response spectrum only under the same schedule
+            dkey = (rkey, tuple(sorted((sched or {}).items())))
+            donor = self._donors.get(dkey)
+            if donor is not None:
+                p = wcsim.Plane(desc, self.phys, response, share=donor)
+            else:
+                p = wcsim.Plane(desc, self.phys, response, schedule=sched)
+                self._donors[dkey] = p
             self._planes[key] = p
-            if donor is None:
-                self._donors[rkey] = p
         return p
 
     def request_bytes(self, planes, n: int) -> int:

@@ -97,6 +97,7 @@ _SIGS = {
     "wcsim_simulate_event": (_st, [_P, _P, _i64, _i32, _u64, _P, _i32, _i32, _P, _P]),
     "wcsim_simulate_event_profiled": (_st, [_P, _P, _i64, _i32, _u64, _P, _i32, _i32, _P, _P,
                                             _P]),
+    "wcsim_tune_schedules": (_st, [_P, _P, _P, _i32, _P, _i64, _i32, _i32, _P, _P]),
     "wcsim_workspace_grid": (_P, [_P, _P, _i64]),
     "wcsim_workspace_invalid_count": (_st, [_P, _P, _P]),
     "wcsim_batch_workspace_bytes": (_sz, [_P, _P, _i32, _i32]),
@@ -147,6 +148,23 @@ def physics_struct(phys: dict) -> Physics:
                    int(phys["seed"]) & (2**64 - 1))
 
 
+def plane_desc_struct(plane: dict, resp: np.ndarray, r0: int) -> PlaneDesc:
+    """wcsim_plane_desc of a plane dict and a contiguous float32 response (the
+    caller keeps `resp` alive while the struct is in use)."""
+    Rp, Rt = resp.shape
+    return PlaneDesc(int(plane["plane_id"]), int(plane["nwires"]), int(plane["nimpact"]),
+                     int(plane["nticks"]), float(plane["pitch"]), float(plane["tick"]),
+                     float(plane["t0"]), float(plane["plane_x"]), float(plane["dir_y"]),
+                     float(plane["dir_z"]), float(plane["pitch_origin"]), Rp, Rt, int(r0), 0,
+                     resp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+
+
+def schedule_struct(schedule: dict | None) -> Schedule:
+    schedule = schedule or {}
+    return Schedule(int(schedule.get("fft_ticks", 0)), int(schedule.get("fft_pitch", 0)),
+                    int(schedule.get("freq_chunk", 0)), int(schedule.get("tile", 0)))
+
+
 class Plane:
     """A plane with its resident response spectrum (wcsim_plane)."""
 
@@ -157,19 +175,14 @@ class Plane:
         if r0 is None:
             r0 = Rp // 2
         self._resp = resp
-        d = PlaneDesc(int(plane["plane_id"]), int(plane["nwires"]), int(plane["nimpact"]),
-                      int(plane["nticks"]), float(plane["pitch"]), float(plane["tick"]),
-                      float(plane["t0"]), float(plane["plane_x"]), float(plane["dir_y"]),
-                      float(plane["dir_z"]), float(plane["pitch_origin"]), Rp, Rt, int(r0), 0,
-                      resp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        d = plane_desc_struct(plane, resp, r0)
         ph = physics_struct(phys)
         h = ctypes.c_void_p()
         if share is not None:
             st = _lib.wcsim_plane_create_sharing(ctypes.byref(d), ctypes.byref(ph), share.handle,
                                                  _stream(stream), ctypes.byref(h))
         elif schedule:
-            sc = Schedule(int(schedule.get("fft_ticks", 0)), int(schedule.get("fft_pitch", 0)),
-                          int(schedule.get("freq_chunk", 0)), int(schedule.get("tile", 0)))
+            sc = schedule_struct(schedule)
             st = _lib.wcsim_plane_create_with_schedule(ctypes.byref(d), ctypes.byref(ph),
                                                        ctypes.byref(sc), _stream(stream),
                                                        ctypes.byref(h))
@@ -465,3 +478,25 @@ def philox4x32_10(ctr: torch.Tensor, key: torch.Tensor, stream=None) -> torch.Te
                                     _dev_ptr(key, torch.int32, "key"), n,
                                     _dev_ptr(out, torch.int32, "out"), _stream(stream)))
     return out
+
+
+def tune_schedules(plane: dict, phys: dict, response: np.ndarray, depos: torch.Tensor,
+                   candidates: list, r0: int | None = None, kind: int = OUT_WIRE, reps: int = 5,
+                   stream=None) -> list:
+    """Median ms per event of wcsim_simulate_event under each candidate
+    schedule (dicts with fft_ticks, fft_pitch, freq_chunk, tile; 0 or absent =
+    default), -1.0 for a candidate that is invalid for this plane."""
+    resp = np.ascontiguousarray(response, dtype=np.float32)
+    if r0 is None:
+        r0 = resp.shape[0] // 2
+    d = plane_desc_struct(plane, resp, r0)
+    ph = physics_struct(phys)
+    arr = (Schedule * len(candidates))(*[schedule_struct(c) for c in candidates])
+    ms = (ctypes.c_float * len(candidates))()
+    if depos.dtype != torch.float64 or depos.dim() != 2 or depos.shape[1] != 5:
+        raise ValueError("depos must be a [n, 5] float64 tensor")
+    n = int(depos.shape[0])
+    ptr = _dev_ptr(depos, torch.float64, "depos") if n else None
+    _check(_lib.wcsim_tune_schedules(ctypes.byref(d), ctypes.byref(ph), arr, len(candidates), ptr,
+                                     n, int(kind), int(reps), _stream(stream), ms))
+    return [float(v) for v in ms]
