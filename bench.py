@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true",
                     help="library default schedules instead of autotuned ones")
+    ap.add_argument("--schedule", type=str, default=None, metavar="JSON",
+                    help="fixed schedule of the benchmark plane, e.g. "
+                         "'{\"fft_pitch\": 512, \"freq_chunk\": 16}' (no tuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy kernel "
                          "whose HBM counters scale the kernels' FETCH_SIZE / WRITE_SIZE)")
@@ -94,10 +97,11 @@ def raster_work(wcsim, P, dep) -> dict:
             "ops": calls * OPS_PER_PHILOX_CALL + bins * OPS_PER_BIN}
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, schedule: dict):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel), or None when
-    the kernel's source changed since the counters were taken."""
+    the kernel's source changed since the counters were taken or they were
+    taken under another schedule."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic_collection.json")
@@ -106,7 +110,7 @@ def measured_traffic(kernel: str):
     with open(path) as f:
         rec = json.load(f)
     k = rec.get("kernels", {}).get(kernel)
-    if not k:
+    if not k or rec.get("schedule") != schedule:
         return None
     src = os.path.join(ROOT, k["source"])
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -258,7 +262,9 @@ def main():
     kind = wcsim.OUT_WIRE if args.kind == "wire" else wcsim.OUT_PITCH
     dep = torch.from_numpy(w["depos"]).to(dev)
     tuner, tuning, sched = None, None, None
-    if not args.no_tune:
+    if args.schedule:
+        sched = json.loads(args.schedule)
+    elif not args.no_tune:
         from paper_2304_01841_amd import autotune
         tuner = autotune.Tuner()
         sched = tuner.tune(pl, w["phys"], R, dep, kind=kind)
@@ -309,6 +315,7 @@ def main():
     # plain VALU arithmetic (no stage is a dense contraction); the FFT passes
     # are reported against HBM.
     alg = algorithmic_bytes(P, nout, n)
+    eff = {k: int(P.info[k]) for k in ("fft_ticks", "fft_pitch", "freq_chunk", "tile")}
     dom = max(("raster_tiles", "fft_ticks", "conv_pitch", "ifft_ticks"), key=lambda s: stages[s])
     kernel_of = {"raster_tiles": "k_raster_tiles", "fft_ticks": "k_rows_r2c",
                  "conv_pitch": "k_pitch_conv", "ifft_ticks": "k_rows_c2r"}
@@ -317,14 +324,14 @@ def main():
         achieved = work["ops"] / (stages[dom] * 1e-3) / 1e12
         roofline = {"kernel": kernel_of[dom], "bound": "alu", "achieved": achieved,
                     "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS,
-                    "traffic": measured_traffic(kernel_of[dom]), "algorithmic_ops": work["ops"],
+                    "traffic": measured_traffic(kernel_of[dom], eff), "algorithmic_ops": work["ops"],
                     "philox_calls": work["philox_calls"], "bins": work["bins"],
                     "avg_ms": stages[dom]}
     else:
         achieved = alg[dom] / (stages[dom] * 1e-3) / 1e9
         roofline = {"kernel": kernel_of[dom], "bound": "hbm", "achieved": achieved,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": measured_traffic(kernel_of[dom]), "algorithmic_bytes": alg[dom],
+                    "traffic": measured_traffic(kernel_of[dom], eff), "algorithmic_bytes": alg[dom],
                     "avg_ms": stages[dom]}
     per_stage_hbm = {s: alg[s] / (stages[s] * 1e-3) / 1e9 for s in alg if stages.get(s, 0) > 0}
 
@@ -359,7 +366,8 @@ def main():
                    "global_batch": 1, "depos_per_event": n,
                    "fft_ticks": P.info["fft_ticks"], "fft_pitch": P.info["fft_pitch"],
                    "freq_chunk": P.info["freq_chunk"], "tile": P.info["tile"],
-                   "schedule": "autotuned" if tuning else "library default"},
+                   "schedule": ("fixed" if args.schedule else
+                                "autotuned" if tuning else "library default")},
         "tuning": tuning,
         "planes_per_s": planes_per_s,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
