@@ -47,17 +47,23 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// Uniform ((r >> 9) + 1/2) 2^-23 in (0, 1), exact in binary32.
+// Uniform ((r >> 9) + 1/2) 2^-23 in (0, 1), exact in binary32: the float
+// 1 + m 2^-23 (m = r >> 9 as its mantissa) minus (1 - 2^-24) is
+// (2m + 1) 2^-24, an exact difference.
 __device__ __forceinline__ float word_to_uniform(uint32_t r)
 {
-    return ((float)(r >> 9) + 0.5f) * 0x1p-23f;
+    return __uint_as_float((r >> 9) | 0x3f800000u) - (1.0f - 0x1p-24f);
 }
 
 // Box-Muller pair: cosine branch (even tick) and sine branch (odd tick).
-// v_sin/v_cos take their argument in revolutions, so theta = 2 pi u is u.
+// v_sin/v_cos take their argument in revolutions, so theta = 2 pi u is u;
+// v_log gives log2, and -2 ln u = (-2 ln 2) log2 u.  u >= 2^-24 is never
+// denormal, so the hardware instructions need no range fix-ups.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &zc, float &zs)
 {
-    const float rho = __builtin_amdgcn_sqrtf(-2.0f * __logf(word_to_uniform(a)));
+    constexpr float kMinus2Ln2 = -1.38629436111989061883f;
+    const float rho =
+        __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(word_to_uniform(a)));
     const float u = word_to_uniform(b);
     zc = rho * __builtin_amdgcn_cosf(u);
     zs = rho * __builtin_amdgcn_sinf(u);
@@ -782,7 +788,7 @@ __device__ __forceinline__ void patch_item(const PatchHdr &h, int it, const floa
 {
     const bool valid = it < h.items;
     const int i = div_small(it, h.m);
-    const int qq = valid ? it - i * h.nq : 0;
+    const int qq = valid ? it - (int)__umul24(i, h.nq) : 0;
     const int qd = h.qlo + qq;
     const int r = h.lo_p + i - p0, c = 4 * qd - c0;
     cell = (valid && (unsigned)r < (unsigned)RP && (unsigned)c <= (unsigned)(RT - 4))
