@@ -20,6 +20,8 @@
 //    scanned offsets and a second kernel adds them to the grid atomically.
 #include <math.h>
 
+#include <limits.h>
+
 #include "wcsim_internal.h"
 
 namespace wcs {
@@ -838,8 +840,10 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     const int tile = item.x, beg = item.y, end = item.z;
     const int lane = threadIdx.x;
     float next = records[(int64_t)beg * kRecWords + lane];
-    for (int c = lane; c < RP * RT / 4; c += 64)
-        acc4[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // window of patch beg + lane (lanes past the chunk: empty)
+    int4 win = make_int4(INT_MAX, INT_MAX, 0, 0);
+    if (beg + lane < end)
+        win = *(const int4 *)(records + (int64_t)(beg + lane) * kRecWords);  // lo_p lo_t n_p n_t
     const EventCtx &E = B ? bt.ev[find_event(bt.tile_base, bt.nev, tile)] : e0;
     const PlaneParams P = E.kp;
     const int local = tile - E.tile_base;
@@ -847,6 +851,29 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     const int c0 = t0 - kPadT;  // grid tick of region column 0
     const float *Wp = (const float *)rec4 + kRecWp;
     const float4 *Wq = rec4 + kRecWt / 4;
+    // Only the bounding box of the chunk's patches (in region rows and tick
+    // quads, within the grid) is cleared and flushed; deposits outside the
+    // grid land outside it and are never read.
+    int rlo = win.x, rhi = (win.z > 0) ? win.x + win.z : INT_MIN;
+    int qlo = quad_of(win.y), qhi = (win.z > 0) ? quad_of(win.y + win.w - 1) + 1 : INT_MIN;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        rlo = min(rlo, __shfl_xor(rlo, m, 64));
+        rhi = max(rhi, __shfl_xor(rhi, m, 64));
+        qlo = min(qlo, __shfl_xor(qlo, m, 64));
+        qhi = max(qhi, __shfl_xor(qhi, m, 64));
+    }
+    const int br0 = max(rlo, p0) - p0;
+    const int br1 = min(min(rhi, (int)P.Np), p0 + RP) - p0;
+    const int bq0 = max(4 * max(qlo, 0) - c0, 0) >> 2;
+    const int bq1 = min(4 * min(qhi, quad_of((int)P.Nt - 1) + 1) - c0, RT) >> 2;
+    const int bnq = max(bq1 - bq0, 0), bcells = max(br1 - br0, 0) * bnq;
+    const int bmagic = magic_small(max(bnq, 1));
+    for (int x = lane; x < bcells; x += 64) {
+        const int r = div_small(x, bmagic);
+        acc4[r * (RT / 4) + bq0 + br0 * (RT / 4) + (x - r * bnq)] =
+            make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
 
     for (int k = beg; k < end; ++k) {
         const float cur = next;
@@ -916,14 +943,15 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
         wave_lds_sync();  // the record buffer is rewritten by the next patch
     }
     float *grid = E.grid;
-    for (int c4 = lane; c4 < RP * RT / 4; c4 += 64) {
-        const float4 a4 = acc4[c4];
+    for (int x = lane; x < bcells; x += 64) {
+        const int r = div_small(x, bmagic), cq = bq0 + (x - r * bnq);
+        const float4 a4 = acc4[(br0 + r) * (RT / 4) + cq];
         const float v[4] = {a4.x, a4.y, a4.z, a4.w};
-        const int I = p0 + (4 * c4) / RT, J0 = c0 + (4 * c4) % RT;
+        const int I = p0 + br0 + r, J0 = c0 + 4 * cq;
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
             const int J = J0 + mm;
-            if (v[mm] != 0.0f && I < P.Np && (unsigned)J < (unsigned)P.Nt)
+            if (v[mm] != 0.0f && (unsigned)J < (unsigned)P.Nt)
                 unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v[mm]);
         }
     }
