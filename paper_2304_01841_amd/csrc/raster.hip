@@ -780,13 +780,20 @@ __device__ __forceinline__ PatchHdr patch_header(float cur)
     return h;
 }
 
+// Word w of the record held by the wavefront (lane w holds word w).
+__device__ __forceinline__ float rec_word(int rec_bits, int w)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(w << 2, rec_bits));
+}
+
 // Work item it = (window row i, tick quad qlo + qq) of one patch: the four
 // bins' values (charge times weights, fluctuated if asked) and the float4
-// cell of the region they go to (-1: not deposited).
+// cell of the region they go to (-1: not deposited).  The weights are read
+// from the lanes that hold them (no LDS staging, no barrier per patch).
 template <int RP, int RT, bool FLUCT>
-__device__ __forceinline__ void patch_item(const PatchHdr &h, int it, const float *Wp,
-                                           const float4 *Wq, int p0, int c0, uint32_t key0,
-                                           uint32_t key1, uint32_t event, float F[4], int &cell)
+__device__ __forceinline__ void patch_item(const PatchHdr &h, int it, int rec_bits, int p0,
+                                           int c0, uint32_t key0, uint32_t key1, uint32_t event,
+                                           float F[4], int &cell)
 {
     const bool valid = it < h.items;
     const int i = div_small(it, h.m);
@@ -796,11 +803,13 @@ __device__ __forceinline__ void patch_item(const PatchHdr &h, int it, const floa
     cell = (valid && (unsigned)r < (unsigned)RP && (unsigned)c <= (unsigned)(RT - 4))
                ? (r * RT + c) >> 2
                : -1;
-    // loads at in-range indexes, then a select: no branches
-    const float wp_raw = Wp[valid ? i : 0];
+    // reads at in-range indexes, then a select: no branches
+    const float wp_raw = rec_word(rec_bits, kRecWp + (valid ? i : 0));
     const float wp = valid ? wp_raw : 0.0f;
-    const float4 wq = Wq[qq];
-    const float wt[4] = {wq.x, wq.y, wq.z, wq.w};
+    float wt[4];
+#pragma unroll
+    for (int mm = 0; mm < 4; ++mm)
+        wt[mm] = rec_word(rec_bits, kRecWt + 4 * qq + mm);
     if (FLUCT) {
         const uint4 rr = philox4x32_10(
             make_uint4((uint32_t)qd, (uint32_t)(h.lo_p + i), (uint32_t)h.d, event), key0, key1);
@@ -833,7 +842,6 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     constexpr int RP = TP + kHaloP, RT = region_cols<TT>();
     static_assert(RT % 4 == 0, "region rows must hold whole quads");
     __shared__ float4 acc4[RP * RT / 4];
-    __shared__ float4 rec4[kRecWords / 4];
     if ((int)blockIdx.x >= counters[2])
         return;
     const int4 item = items[blockIdx.x];
@@ -849,8 +857,6 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     const int local = tile - E.tile_base;
     const int p0 = (local / E.ntt) * TP, t0 = (local % E.ntt) * TT;
     const int c0 = t0 - kPadT;  // grid tick of region column 0
-    const float *Wp = (const float *)rec4 + kRecWp;
-    const float4 *Wq = rec4 + kRecWt / 4;
     // Only the bounding box of the chunk's patches (in region rows and tick
     // quads, within the grid) is cleared and flushed; deposits outside the
     // grid land outside it and are never read.
@@ -875,14 +881,15 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
             make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
 
+    wave_lds_sync();  // the cleared region is visible to every lane
+
     for (int k = beg; k < end; ++k) {
         const float cur = next;
-        ((float *)rec4)[lane] = cur;
+        const int cur_bits = __float_as_int(cur);
         // the next record is loaded while this patch is rasterized
         if (k + 1 < end)
             next = records[(int64_t)(k + 1) * kRecWords + lane];
         const PatchHdr h = patch_header(cur);
-        wave_lds_sync();
 
         float F[kFluctItems][4];
         int cell[kFluctItems];
@@ -897,8 +904,8 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b)
                 if (64 * b < h.items)  // uniform
-                    patch_item<RP, RT, true>(h, lane + 64 * b, Wp, Wq, p0, c0, P.key0, P.key1,
-                                             E.event, F[b], cell[b]);
+                    patch_item<RP, RT, true>(h, lane + 64 * b, cur_bits, p0, c0, P.key0,
+                                             P.key1, E.event, F[b], cell[b]);
             // renormalise the patch to its charge
             float acc = 0.0f;
 #pragma unroll
@@ -919,15 +926,15 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
 #pragma unroll
                 for (int b = 0; b < kFluctItems; ++b)
                     if (64 * b < h.items)
-                        patch_item<RP, RT, false>(h, lane + 64 * b, Wp, Wq, p0, c0, 0, 0, 0,
+                        patch_item<RP, RT, false>(h, lane + 64 * b, cur_bits, p0, c0, 0, 0, 0,
                                                   F[b], cell[b]);
             }
         } else {
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b)
                 if (64 * b < h.items)
-                    patch_item<RP, RT, false>(h, lane + 64 * b, Wp, Wq, p0, c0, 0, 0, 0, F[b],
-                                              cell[b]);
+                    patch_item<RP, RT, false>(h, lane + 64 * b, cur_bits, p0, c0, 0, 0, 0,
+                                              F[b], cell[b]);
         }
 #pragma unroll
         for (int b = 0; b < kFluctItems; ++b) {
@@ -940,8 +947,8 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
                 acc4[cell[b]] = a4;
             }
         }
-        wave_lds_sync();  // the record buffer is rewritten by the next patch
     }
+    wave_lds_sync();  // every deposit lands before the flush reads the region
     float *grid = E.grid;
     for (int x = lane; x < bcells; x += 64) {
         const int r = div_small(x, bmagic), cq = bq0 + (x - r * bnq);
