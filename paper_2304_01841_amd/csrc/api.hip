@@ -633,7 +633,8 @@ static wcsim_status simulate_event(const wcsim_plane *pl, const wcsim_depo *depo
     }
     if (ev)
         WCS_HIP(hipEventRecord(ev[0], s));
-    WCS_HIP(launch_fill_zero(grid, sizeof(float) * (size_t)pl->Np * pl->Nt, s));
+    // the grid is cleared inside the raster sequence (beside the record
+    // building), so stage [0, 1] is empty
     if (ev)
         WCS_HIP(hipEventRecord(ev[1], s));
     WCS_HIP(launch_raster_fused(pl, dd, n, event_id, rw, grid, s, ev ? ev + 2 : nullptr));
@@ -926,9 +927,8 @@ hipError_t launch_batch_group(const wcsim_plane *pl0, const BatchLayout &L, char
     const BatchTables bt = tables_of(L, ws);
     const RasterWork rw = raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, ws + L.off_raster);
     hipError_t e;
-    if ((e = launch_fill_zero(ws + L.off_grid, L.grid_bytes, s)) != hipSuccess)
-        return e;
-    if ((e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, s)) != hipSuccess)
+    if ((e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, ws + L.off_grid,
+                                 L.grid_bytes, s)) != hipSuccess)
         return e;
     return launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, s);
 }

@@ -699,16 +699,27 @@ static_assert(kHeaderWords <= kRecWp, "record header overflow");
 constexpr int kStageStride = kRecWords + 1;  // odd: one LDS bank per lane
 
 // One wavefront per block: each lane computes one record into LDS, then the
-// wavefront writes the records out one 256-byte row at a time.
+// wavefront writes the records out one 256-byte row at a time.  The first
+// `nclr` blocks instead clear the plane grid (n4 float4 words): the clear is
+// bound by HBM writes and the records by FP64 arithmetic, so one launch runs
+// both side by side.
 template <bool B>
 __global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt, int64_t ntotal,
                                                      const int32_t *depo_tile,
                                                      const int32_t *depo_slot,
-                                                     const int32_t *tile_off, float *records)
+                                                     const int32_t *tile_off, float *records,
+                                                     float4 *clr, int64_t n4, int nclr)
 {
     __shared__ float stage[64 * kStageStride];
     const int lane = threadIdx.x;
-    const int64_t gd = blockIdx.x * (int64_t)64 + lane;
+    if ((int)blockIdx.x < nclr) {
+        const int64_t per = (n4 + nclr - 1) / nclr;
+        const int64_t b0 = blockIdx.x * per, b1 = min(b0 + per, n4);
+        for (int64_t i = b0 + lane; i < b1; i += 64)
+            clr[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    const int64_t gd = (blockIdx.x - nclr) * (int64_t)64 + lane;
     int pos = -1;
     const int t = (gd < ntotal) ? depo_tile[gd] : -1;
     if (t >= 0) {
@@ -1076,6 +1087,10 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
     return hipGetLastError();
 }
 
+// Blocks of the record kernel that clear the grid: two per CU keep HBM
+// writes busy while the other blocks build records.
+constexpr int kClearBlocks = 512;
+
 static size_t sched_blocks_of(int64_t ntiles)
 {
     return (size_t)((ntiles + 1 + kSchedTiles - 1) / kSchedTiles);
@@ -1136,7 +1151,8 @@ RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
 template <bool B>
 static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
                                   const BatchTables &bt, int64_t n, int64_t ntiles,
-                                  const RasterWork &w, hipStream_t s, const hipEvent_t *ev)
+                                  const RasterWork &w, void *grid, size_t grid_bytes,
+                                  hipStream_t s, const hipEvent_t *ev)
 {
     hipError_t e;
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
@@ -1146,11 +1162,19 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     if ((e = launch_fill_zero(w.counters, align_up(clear, 16), s)) != hipSuccess)
         return e;
     if (n <= 0) {
+        if ((e = launch_fill_zero(grid, grid_bytes, s)) != hipSuccess)
+            return e;
         for (int i = 0; i < 3; ++i)
             if ((e = mark(i)) != hipSuccess)
                 return e;
         return hipSuccess;
     }
+    // the grid's float4 words are cleared by the record kernel's first blocks,
+    // any tail of fewer than four floats here
+    const int64_t n4 = (int64_t)(grid_bytes / 16);
+    if (grid_bytes % 16 &&
+        (e = launch_fill_zero((char *)grid + n4 * 16, grid_bytes % 16, s)) != hipSuccess)
+        return e;
     TileGeom g;
     g.tp = pl->ts.tp;
     g.tt = pl->ts.tt;
@@ -1164,8 +1188,10 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
                        (int)ntiles, w.block_tot);
     hipLaunchKernelGGL(k_tile_schedule, dim3(sched_blocks), dim3(kSchedThreads), 0, s,
                        w.tile_count, (int)ntiles, w.block_tot, w.items, w.counters);
-    hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64)), dim3(64), 0, s, e0, bt, n,
-                       w.depo_tile, w.depo_slot, w.tile_count, w.records);
+    const int nclr = (int)std::min<int64_t>(kClearBlocks, std::max<int64_t>(n4 / 4096, 1));
+    hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64) + nclr), dim3(64), 0, s, e0, bt,
+                       n, w.depo_tile, w.depo_slot, w.tile_count, w.records, (float4 *)grid, n4,
+                       nclr);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
     const unsigned grid_items = (unsigned)items_cap(ntiles, n);
@@ -1200,13 +1226,16 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
                                const hipEvent_t *ev)
 {
     const EventCtx e0 = single_event(pl, depos, n, event_id, grid);
-    return raster_sequence<false>(pl, e0, BatchTables{}, n, pl->ntiles, w, s, ev);
+    return raster_sequence<false>(pl, e0, BatchTables{}, n, pl->ntiles, w, grid,
+                                  sizeof(float) * (size_t)pl->Np * (size_t)pl->Nt, s, ev);
 }
 
 hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
-                               int64_t ntiles_total, const RasterWork &w, hipStream_t s)
+                               int64_t ntiles_total, const RasterWork &w, void *grids,
+                               size_t grid_bytes, hipStream_t s)
 {
-    return raster_sequence<true>(pl, EventCtx{}, bt, n_total, ntiles_total, w, s, nullptr);
+    return raster_sequence<true>(pl, EventCtx{}, bt, n_total, ntiles_total, w, grids, grid_bytes,
+                                 s, nullptr);
 }
 
 }  // namespace wcs

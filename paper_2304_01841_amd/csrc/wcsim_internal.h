@@ -187,6 +187,7 @@ size_t raster_work_bytes(const wcsim_plane *pl, int64_t n);
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base);
 // `ev` (nullable): 3 events recorded after binning, after the LDS-tiled
 // raster kernel and after the large-patch kernel.
+// The grid (npitch x nticks floats) is cleared by the sequence itself.
 hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
                                uint64_t event_id, const RasterWork &w, float *grid,
                                hipStream_t s, const hipEvent_t *ev = nullptr);
@@ -195,8 +196,11 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
 size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n_total, int64_t ntiles_total);
 RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n_total, int64_t ntiles_total,
                                    void *base);
+// `grids` (grid_bytes, all events' grids, contiguous) are cleared by the
+// sequence itself.
 hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
-                               int64_t ntiles_total, const RasterWork &w, hipStream_t s);
+                               int64_t ntiles_total, const RasterWork &w, void *grids,
+                               size_t grid_bytes, hipStream_t s);
 
 // FFT convolution passes
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind);
