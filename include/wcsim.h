@@ -109,6 +109,8 @@ typedef struct {
     int32_t tile_pitch, tile_ticks;
     int64_t ntiles;
     int64_t spectrum_bytes; /* resident response spectrum */
+    int32_t pitch_cols;     /* spectrum columns per pitch-pass workgroup (divides freq_chunk) */
+    int32_t wire_fold;      /* 1: wire output folds the pitch inverse to fft_pitch / nimpact */
 } wcsim_plane_info;
 
 typedef struct wcsim_plane wcsim_plane;

@@ -23,9 +23,11 @@ import torch
 from . import wcsim
 
 # Candidate schedules: the library default first, then the compiled pitch-pass
-# variants (block length x chunk width) crossed with the raster tile shapes.
+# variants (block length x chunk width; 640 and 960 allow the folded
+# wire-output inverse) crossed with the raster tile shapes.
 PITCH_CHOICES = ({}, {"fft_pitch": 512, "freq_chunk": 16}, {"fft_pitch": 1024, "freq_chunk": 16},
-                 {"fft_pitch": 1024, "freq_chunk": 8})
+                 {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 640, "freq_chunk": 16},
+                 {"fft_pitch": 960, "freq_chunk": 16})
 TILE_CHOICES = (0, 2)
 
 

@@ -15,7 +15,7 @@
 // Device buffers of a response spectrum and its twiddle tables, with the
 // host response they were built from (to recognise a compatible donor).
 struct wcs_spectrum {
-    float2 *K = nullptr, *twT = nullptr, *twHalf = nullptr, *twL = nullptr;
+    float2 *K = nullptr, *twT = nullptr, *twHalf = nullptr, *twL = nullptr, *twF = nullptr;
     std::vector<float> response;
     int Rp = 0, Rt = 0, r0 = 0, Nfft = 0, L = 0, F = 0, device = -1;
     ~wcs_spectrum()
@@ -24,6 +24,7 @@ struct wcs_spectrum {
         (void)hipFree(twT);
         (void)hipFree(twHalf);
         (void)hipFree(twL);
+        (void)hipFree(twF);
     }
 };
 
@@ -150,14 +151,25 @@ wcsim_status choose_schedule(wcsim_plane *pl, const wcsim_schedule *sc)
         return fail(WCSIM_E_INVALID, "fft_pitch must be >= resp_npitch");
     if (!make_plan(L, &pl->planL))
         return fail(WCSIM_E_INVALID, "fft_pitch must factor into 2, 3 and 5");
-    if (sizeof(float2) * ((size_t)L * pl->F + twiddle_table_len(L)) > kLdsBytes ||
+    // columns per pitch workgroup: the whole chunk while an L x F block fits
+    // 64 KB (two workgroups per CU), else halves of it
+    pl->Fb = pl->F;
+    while (pl->Fb > 4 && sizeof(float2) * (size_t)L * pl->Fb > 64 * 1024)
+        pl->Fb /= 2;
+    // folded wire-output inverse when nimpact divides L
+    const int D = pl->desc.nimpact;
+    pl->fold = D > 1 && L % D == 0 && make_plan(L / D, &pl->planF) &&
+               twiddle_table_len(L / D) <= 256;
+    pl->L10 = pl->fold ? L / D : 0;
+    if (sizeof(float2) * ((size_t)L * pl->Fb + (size_t)pl->L10 * pl->Fb + twiddle_table_len(L) +
+                          (pl->fold ? twiddle_table_len(pl->L10) : 0)) > kLdsBytes ||
         twiddle_table_len(L) > 256)
         return fail(WCSIM_E_INVALID, "pitch block too large for LDS");
     {
         // every pass must stage at most 32 complex values per thread of 1024
         for (int q = 0; q < pl->planL.npass; ++q) {
             const int R = pl->planL.radix[q];
-            if ((int64_t)L / R * pl->F > 1024LL * (32 / R))
+            if ((int64_t)L / R * pl->Fb > 1024LL * (32 / R))
                 return fail(WCSIM_E_INVALID, "pitch block too large for one workgroup");
         }
         for (int q = 0; q < pl->planT.npass; ++q) {
@@ -241,13 +253,14 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     if (donor && donor->spectrum) {
         const wcs_spectrum &d = *donor->spectrum;
         if (d.Rp == pl->Rp && d.Rt == pl->Rt && d.r0 == pl->r0 && d.Nfft == pl->Nfft &&
-            d.L == pl->L && d.F == pl->F && d.device == pl->device &&
+            d.L == pl->L && d.F == pl->F && d.device == pl->device && (d.twF != nullptr) == pl->fold &&
             memcmp(d.response.data(), desc->response, sizeof(float) * nresp) == 0) {
             pl->spectrum = donor->spectrum;
             pl->K = d.K;
             pl->twT = d.twT;
             pl->twHalf = d.twHalf;
             pl->twL = d.twL;
+            pl->twF = d.twF;
             *out = pl;
             return WCSIM_OK;
         }
@@ -273,11 +286,13 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     spec->device = pl->device;
     if ((st = upload(&spec->twT, twiddles(pl->N2, pl->N2), s)) != WCSIM_OK ||
         (st = upload(&spec->twHalf, twiddles(pl->Nfft, pl->N2 + 1), s)) != WCSIM_OK ||
-        (st = upload(&spec->twL, twiddles(pl->L, pl->L), s)) != WCSIM_OK)
+        (st = upload(&spec->twL, twiddles(pl->L, pl->L), s)) != WCSIM_OK ||
+        (pl->fold && (st = upload(&spec->twF, twiddles(pl->L10, pl->L10), s)) != WCSIM_OK))
         return cleanup(st);
     pl->twT = spec->twT;
     pl->twHalf = spec->twHalf;
     pl->twL = spec->twL;
+    pl->twF = spec->twF;
     hipError_t e;
     const size_t kbytes = sizeof(float2) * (size_t)pl->C * pl->L * pl->F;
     if ((e = hipMalloc((void **)&spec->K, kbytes)) != hipSuccess)
@@ -390,6 +405,8 @@ wcsim_status wcsim_plane_get_info(const wcsim_plane *pl, wcsim_plane_info *info)
     info->tile_ticks = pl->ts.tt;
     info->ntiles = pl->ntiles;
     info->spectrum_bytes = (int64_t)sizeof(float2) * pl->C * pl->L * pl->F;
+    info->pitch_cols = pl->Fb;
+    info->wire_fold = pl->fold ? 1 : 0;
     return WCSIM_OK;
 }
 

@@ -591,11 +591,20 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(C2RIo io, BatchTa
 //   mode 0: output every pitch row; mode 1: only row w*nimpact + nimpact/2 of
 //   each wire (output row w); mode 2: response spectrum (forward transform of
 //   rows 0..nrows_in-1 zero-padded to L, scaled, written as [c][L][F]).
+// A workgroup takes Fb of the chunk's F columns (Fb < F when an L x F block
+// would not leave room for two workgroups per CU).
 // Workgroups are mapped XCD-major: workgroup b runs on XCD b mod 8, and the
-// workgroups of one XCD walk the pitch blocks of one chunk before the next, so
-// the chunk's response spectrum and the rows shared by neighbouring blocks are
-// re-read from that XCD's L2.
-// LDS: the block [L][F], then the L table.
+// workgroups of one XCD walk the pitch blocks of one column chunk before the
+// next, so the chunk's response spectrum and the rows shared by neighbouring
+// blocks are re-read from that XCD's L2.
+// Wire output with D = nimpact dividing L folds the inverse: the kept rows of
+// a block are n = n0 + D w (n0 fixed by the block's first row), and
+//   y[n0 + D w] = sum_{k'<L/D} Z[k'] exp(2 pi i k' w / (L/D)),
+//   Z[k'] = exp(2 pi i k' n0 / L) sum_{j<D} P[k' + j L/D] exp(2 pi i j n0 / D),
+// P the block spectrum times the response spectrum (which carries 1/(L N')).
+// So the inverse runs at length L/D on the folded spectrum instead of L.
+// LDS: the block [L][Fb], the folded block [L/D][Fb] (fold only), then the L
+// table and the L/D table.
 // ---------------------------------------------------------------------------
 struct PitchIo {
     const float2 *X;
@@ -605,11 +614,13 @@ struct PitchIo {
     int nrows_out, nblocks, mode;
 };
 
-template <class FFT, bool BATCH>
+template <class FFT, class FFT2, bool BATCH>
 __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, BatchTables bt, int L,
                                                                 int V, int Rp, int r0, int C,
-                                                                int F_shift, FFT fft, TwTables tw,
-                                                                int nimpact, float scale)
+                                                                int F_shift, int Fb_shift,
+                                                                FFT fft, FFT2 fft2, TwTables tw,
+                                                                int nimpact, int fold_ok,
+                                                                float scale)
 {
     extern __shared__ float2 lds[];
     int gblk = blockIdx.x;
@@ -633,17 +644,23 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
     const float2 *__restrict__ K = io.K;
     float2 *__restrict__ Y = io.Y;
     const int xcd = gblk & 7, slot = gblk >> 3;
-    const int lc = slot / nblocks, blk = slot - lc * nblocks;
-    const int c = lc * 8 + xcd;
+    const int lcc = slot / nblocks, blk = slot - lcc * nblocks;
+    const int cc = lcc * 8 + xcd;  // column chunk: (chunk c, part hf of Fb columns)
+    const int parts_shift = F_shift - Fb_shift;
+    const int c = cc >> parts_shift, hf = cc & ((1 << parts_shift) - 1);
     if (c >= C)
         return;
-    const int F = 1 << F_shift;
-    const int LF = L << F_shift;
-    float2 *tabL = lds + LF;
-    load_tables(tw, tabL, nullptr);
+    const int D = nimpact, L10 = L / D;
+    const bool fold = fold_ok && mode == 1;
+    const int LFb = L << Fb_shift;
+    float2 *Z = lds + LFb;
+    float2 *tabL = Z + (fold_ok ? (L10 << Fb_shift) : 0);
+    float2 *tab2 = tabL + tw.na;
+    load_tables(tw, tabL, tab2);
     const int P0 = blk * V;
     const int in0 = (mode == 2) ? 0 : P0 + r0 - (Rp - 1);
-    const float2 *src = X + ((int64_t)c * nrows_in << F_shift);
+    const int col0 = hf << Fb_shift;
+    const float2 *src = X + ((int64_t)c * nrows_in << F_shift) + col0;
     // block row n, column s straight from global memory into the first pass
     auto load = [&](int s, int n) {
         const int row = in0 + n;
@@ -651,21 +668,47 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
                                             : make_float2(0.0f, 0.0f);
     };
     if (mode == 2) {
-        float2 *dst = Y + (int64_t)c * LF;
+        float2 *dst = Y + ((int64_t)c * L << F_shift) + col0;
         fft.run_io(lds, tabL, load,
                    [&](int s, int n, float2 v) { dst[(n << F_shift) + s] = cscale(v, scale); });
         return;
     }
+    const float2 *Kc = K + ((int64_t)c * L << F_shift) + col0;
+    float2 *dst = Y + ((int64_t)c * nrows_out << F_shift) + col0;
+    if (fold) {
+        // forward transform times the response spectrum, then the fold
+        fft.run_io(lds, tabL, load, [&](int s, int n, float2 v) {
+            lds[(n << Fb_shift) + s] = cmul(v, Kc[(n << F_shift) + s]);
+        });
+        __syncthreads();
+        const int n0 = ((D / 2 - P0 + Rp - 1) % D + D) % D;
+        for (int t = threadIdx.x; t < (L10 << Fb_shift); t += blockDim.x) {
+            const int kp = t >> Fb_shift, s = t & ((1 << Fb_shift) - 1);
+            float2 acc = make_float2(0.0f, 0.0f);
+            for (int j = 0; j < D; ++j) {
+                const float2 w = conjf2(tw_at(tabL, ((j * n0) % D) * L10));
+                acc = cadd(acc, cmul(lds[((kp + j * L10) << Fb_shift) + s], w));
+            }
+            // conjugated: the inverse runs as a forward transform
+            Z[t] = conjf2(cmul(acc, conjf2(tw_at(tabL, (kp * n0) % L))));
+        }
+        __syncthreads();
+        fft2.run_io(Z, tab2, InLds{}, [&](int s, int w, float2 v) {
+            const int n = n0 + D * w;
+            const int p = P0 + n - (Rp - 1);
+            if (n < Rp - 1 || p >= nrows_in)
+                return;
+            dst[((int64_t)(p / D) << F_shift) + s] = conjf2(v);
+        });
+        return;
+    }
     // forward transform; its last pass multiplies by the response spectrum and
     // conjugates (the inverse runs as a forward transform of the conjugate)
-    const float2 *Kc = K + (int64_t)c * LF;
     fft.run_io(lds, tabL, load, [&](int s, int n, float2 v) {
-        const int g = (n << F_shift) + s;
-        lds[g] = conjf2(cmul(v, Kc[g]));
+        lds[(n << Fb_shift) + s] = conjf2(cmul(v, Kc[(n << F_shift) + s]));
     });
     __syncthreads();
     // inverse; its last pass writes the block's valid rows
-    float2 *dst = Y + ((int64_t)c * nrows_out << F_shift);
     fft.run_io(lds, tabL, InLds{}, [&](int s, int n, float2 v) {
         const int p = P0 + n - (Rp - 1);
         if (n < Rp - 1 || p >= nrows_in)
@@ -716,14 +759,19 @@ constexpr int kRowsPerBlock = 1 << kRowsShift;
 // Compile-time transforms for the sizes the schedules use:
 //   tick axis N2 = 3125 (N' = 6250, 6000-tick planes) and N2 = 600 (N' = 1200,
 //   1000-tick planes);
-//   pitch axis L = 1024 with 8- or 16-column chunks and L = 512 with
-//   16-column chunks.  A pitch block fills most of the LDS, so a CU holds one
-//   or two workgroups; they get 512 or 1024 threads to keep enough waves.
+//   pitch axis: L = 1024 or 640 or 960 over 8 columns, L = 512 over 16
+//   columns.  A pitch block fills much of the LDS, so a CU holds two or three
+//   workgroups; they get 512 threads to keep enough waves.
 using TickCt3125 = FftCt<3125, kRowsShift, 3126, 1, 256, 5, 5, 5, 5, 5>;
 using TickCt600 = FftCt<600, kRowsShift, 601, 1, 128, 8, 5, 5, 3>;
 using PitchCt1024x8 = FftCt<1024, 3, 1, 8, 512, 8, 8, 4, 4>;
-using PitchCt1024x16 = FftCt<1024, 4, 1, 16, 1024, 8, 8, 4, 4>;
 using PitchCt512x16 = FftCt<512, 4, 1, 16, 512, 8, 8, 8>;
+// Blocks a multiple of 10 rows long for the folded wire-output inverse, with
+// the folded transforms of length L / 10.
+using PitchCt640x8 = FftCt<640, 3, 1, 8, 512, 8, 4, 4, 5>;
+using PitchCt960x8 = FftCt<960, 3, 1, 8, 512, 8, 8, 5, 3>;
+using FoldCt64x8 = FftCt<64, 3, 1, 8, 512, 8, 8>;
+using FoldCt96x8 = FftCt<96, 3, 1, 8, 512, 8, 4, 3>;
 
 int table_len(int m) { return kTwLo + (m + kTwLo - 1) / kTwLo; }
 
@@ -781,7 +829,7 @@ int tick_threads(const wcsim_plane *pl)
 
 int pitch_threads(const wcsim_plane *pl)
 {
-    return std::min(1024, std::max(256, threads_for(pl->planL, pl->F)));
+    return std::min(1024, std::max(256, threads_for(pl->planL, pl->Fb)));
 }
 
 template <bool B>
@@ -826,33 +874,45 @@ hipError_t rows_c2r(const wcsim_plane *pl, const float2 *Y, int nrows, float *ou
     return rows_c2r_any<false>(pl, io, BatchTables{}, (unsigned)rows_blocks(nrows), s);
 }
 
-template <class FFT, bool B>
-void launch_pitch(const wcsim_plane *pl, FFT fft, int threads, const PitchIo &io,
+template <class FFT, class FFT2, bool B>
+void launch_pitch(const wcsim_plane *pl, FFT fft, FFT2 fft2, int threads, const PitchIo &io,
                   const BatchTables &bt, unsigned blocks, float scale, hipStream_t s)
 {
-    const TwTables tw = {pl->twL, table_len(pl->L), nullptr, 0};
-    const size_t lds = sizeof(float2) * ((size_t)pl->L * pl->F + tw.na);
-    hipLaunchKernelGGL((k_pitch_conv<FFT, B>), dim3(blocks), dim3(threads), lds, s, io, bt,
-                       pl->L, pl->V, pl->Rp, pl->r0, pl->C, ilog2(pl->F), fft, tw,
-                       (int)pl->kp.nimpact, scale);
+    const TwTables tw = {pl->twL, table_len(pl->L), pl->fold ? pl->twF : nullptr,
+                         pl->fold ? table_len(pl->L10) : 0};
+    const size_t lds = sizeof(float2) * ((size_t)pl->L * pl->Fb +
+                                         (pl->fold ? (size_t)pl->L10 * pl->Fb : 0) + tw.na + tw.nb);
+    hipLaunchKernelGGL((k_pitch_conv<FFT, FFT2, B>), dim3(blocks), dim3(threads), lds, s, io, bt,
+                       pl->L, pl->V, pl->Rp, pl->r0, pl->C, ilog2(pl->F), ilog2(pl->Fb), fft,
+                       fft2, tw, (int)pl->kp.nimpact, pl->fold ? 1 : 0, scale);
 }
 
 template <bool B>
 hipError_t pitch_any(const wcsim_plane *pl, const PitchIo &io, const BatchTables &bt,
                      unsigned blocks, float scale, hipStream_t s)
 {
-    if (pl->L == 1024 && pl->F == 8 && plan_is(pl->planL, {8, 8, 4, 4}))
-        launch_pitch<PitchCt1024x8, B>(pl, PitchCt1024x8(), PitchCt1024x8::kThreads, io, bt,
-                                       blocks, scale, s);
-    else if (pl->L == 1024 && pl->F == 16 && plan_is(pl->planL, {8, 8, 4, 4}))
-        launch_pitch<PitchCt1024x16, B>(pl, PitchCt1024x16(), PitchCt1024x16::kThreads, io, bt,
-                                        blocks, scale, s);
-    else if (pl->L == 512 && pl->F == 16 && plan_is(pl->planL, {8, 8, 8}))
-        launch_pitch<PitchCt512x16, B>(pl, PitchCt512x16(), PitchCt512x16::kThreads, io, bt,
-                                       blocks, scale, s);
+    const bool fold10 = pl->fold && pl->kp.nimpact == 10;
+    if (pl->L == 1024 && pl->Fb == 8 && !pl->fold && plan_is(pl->planL, {8, 8, 4, 4}))
+        launch_pitch<PitchCt1024x8, PitchCt1024x8, B>(pl, PitchCt1024x8(), PitchCt1024x8(),
+                                                      PitchCt1024x8::kThreads, io, bt, blocks,
+                                                      scale, s);
+    else if (pl->L == 512 && pl->Fb == 16 && !pl->fold && plan_is(pl->planL, {8, 8, 8}))
+        launch_pitch<PitchCt512x16, PitchCt512x16, B>(pl, PitchCt512x16(), PitchCt512x16(),
+                                                      PitchCt512x16::kThreads, io, bt, blocks,
+                                                      scale, s);
+    else if (pl->L == 640 && pl->Fb == 8 && fold10 && plan_is(pl->planL, {8, 4, 4, 5}) &&
+             plan_is(pl->planF, {8, 8}))
+        launch_pitch<PitchCt640x8, FoldCt64x8, B>(pl, PitchCt640x8(), FoldCt64x8(),
+                                                  PitchCt640x8::kThreads, io, bt, blocks, scale, s);
+    else if (pl->L == 960 && pl->Fb == 8 && fold10 && plan_is(pl->planL, {8, 8, 5, 3}) &&
+             plan_is(pl->planF, {8, 4, 3}))
+        launch_pitch<PitchCt960x8, FoldCt96x8, B>(pl, PitchCt960x8(), FoldCt96x8(),
+                                                  PitchCt960x8::kThreads, io, bt, blocks, scale, s);
     else
-        launch_pitch<FftRt, B>(pl, runtime_fft(pl->planL, ilog2(pl->F), 1, pl->F),
-                               pitch_threads(pl), io, bt, blocks, scale, s);
+        launch_pitch<FftRt, FftRt, B>(pl, runtime_fft(pl->planL, ilog2(pl->Fb), 1, pl->Fb),
+                                      runtime_fft(pl->fold ? pl->planF : pl->planL, ilog2(pl->Fb),
+                                                  1, pl->Fb),
+                                      pitch_threads(pl), io, bt, blocks, scale, s);
     return hipGetLastError();
 }
 
@@ -860,7 +920,8 @@ hipError_t pitch_pass(const wcsim_plane *pl, const float2 *X, int nrows_in, cons
                       float2 *Y, int nrows_out, int nblocks, int mode, float scale, hipStream_t s)
 {
     const PitchIo io = {X, nrows_in, K, Y, nrows_out, nblocks, mode};
-    const unsigned blocks = (unsigned)(8 * ((pl->C + 7) / 8) * nblocks);
+    const int chunks = pl->C * (pl->F / pl->Fb);
+    const unsigned blocks = (unsigned)(8 * ((chunks + 7) / 8) * nblocks);
     return pitch_any<false>(pl, io, BatchTables{}, blocks, scale, s);
 }
 
@@ -932,12 +993,14 @@ int rows_blocks(int nrows) { return (nrows + kRowsPerBlock - 1) / kRowsPerBlock;
 
 int pitch_blocks_total(const wcsim_plane *pl)
 {
-    return 8 * ((pl->C + 7) / 8) * pl->nblocks;
+    const int chunks = pl->C * (pl->F / pl->Fb);
+    return 8 * ((chunks + 7) / 8) * pl->nblocks;
 }
 
 bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b)
 {
-    return a->Nfft == b->Nfft && a->L == b->L && a->F == b->F && a->Rp == b->Rp &&
+    return a->Nfft == b->Nfft && a->L == b->L && a->F == b->F && a->Fb == b->Fb &&
+           a->fold == b->fold && a->Rp == b->Rp &&
            a->Rt == b->Rt && a->r0 == b->r0 && a->tile == b->tile && a->Nt == b->Nt &&
            a->kp.nimpact == b->kp.nimpact && a->device == b->device;
 }

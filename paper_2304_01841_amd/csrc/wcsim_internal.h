@@ -124,11 +124,16 @@ struct wcsim_plane {
     // FFT schedule: tick axis N' = 2 N2 (real), pitch axis overlap-save blocks
     // of length L with V = L - Rp + 1 valid rows each.
     int Nfft, N2, H, F, C, L, V, nblocks;
+    // Fb: columns per pitch-pass workgroup (divides F); fold: wire output
+    // folds the inverse to length L10 = L / nimpact (nimpact divides L)
+    int Fb, L10;
+    bool fold;
     int Rp, Rt, r0;
-    wcs::FftPlan planT, planL;
+    wcs::FftPlan planT, planL, planF;
     float2 *twT;     // two-level table of exp(-2 pi i j / N2), j < N2
     float2 *twHalf;  // two-level table of exp(-2 pi i k / N'), k <= N2
     float2 *twL;     // two-level table of exp(-2 pi i j / L), j < L
+    float2 *twF;     // two-level table of exp(-2 pi i j / L10), j < L10 (fold only)
     float2 *K;       // response spectrum [C][L][F], scaled by 1/(L N')
     // owner of K and the twiddle tables; planes with the same response and
     // transform sizes share one

@@ -69,7 +69,8 @@ class PlaneInfo(ctypes.Structure):
                 ("freq_chunk", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("nchunks", ctypes.c_int32), ("pitch_blocks", ctypes.c_int32),
                 ("tile_pitch", ctypes.c_int32), ("tile_ticks", ctypes.c_int32),
-                ("ntiles", ctypes.c_int64), ("spectrum_bytes", ctypes.c_int64)]
+                ("ntiles", ctypes.c_int64), ("spectrum_bytes", ctypes.c_int64),
+                ("pitch_cols", ctypes.c_int32), ("wire_fold", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

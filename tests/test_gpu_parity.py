@@ -164,21 +164,29 @@ def test_convolve_random_response(ws, nw, nimp, nt, Rp, Rt, r0):
 
 def test_convolve_schedules_agree(ws):
     """The result does not depend on the FFT schedule (padded sizes, chunk
-    width, pitch block length)."""
+    width, pitch block length, column split of the pitch pass, and the
+    folded wire-output inverse when the block length is a multiple of the
+    impact count): pitch and wire output against the oracle."""
     log("case: convolve schedules")
     rng = np.random.default_rng(5)
     pl = W.plane(40, 900)
+    nimp = pl["nimpact"]
     R = W.random_response(rng, 50, 60)
     G = rng.standard_normal((400, 900)).astype(np.float32)
     ref = O.convolve(G.astype(np.float64), R.astype(np.float64), 25)
+    refw = O.wire_rows(ref, nimp)
     g = torch.from_numpy(G).cuda()
     for sc in ({}, {"fft_ticks": 1024}, {"fft_ticks": 1000, "freq_chunk": 8},
                {"fft_pitch": 512, "freq_chunk": 16}, {"fft_ticks": 1250},
                {"fft_pitch": 128}, {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 240},
-               {"fft_pitch": 1024, "freq_chunk": 16}, {"fft_ticks": 6250}, {"fft_ticks": 1200}):
+               {"fft_pitch": 1024, "freq_chunk": 16}, {"fft_ticks": 6250}, {"fft_ticks": 1200},
+               {"fft_pitch": 640, "freq_chunk": 16}, {"fft_pitch": 960, "freq_chunk": 16},
+               {"fft_pitch": 640, "freq_chunk": 8}, {"fft_pitch": 100}, {"fft_pitch": 320}):
         P = ws.Plane(pl, W.physics(False), R, r0=25, schedule=sc)
         out = ws.convolve(P, g, kind=ws.OUT_PITCH)
         assert normwise(out.cpu().numpy(), ref) <= CONV_TOL, sc
+        outw = ws.convolve(P, g, kind=ws.OUT_WIRE)
+        assert normwise(outw.cpu().numpy(), refw) <= CONV_TOL, ("wire", sc)
 
 
 def test_convolve_delta_response_identity(ws):
