@@ -757,12 +757,13 @@ constexpr int kRowsShift = 0;
 constexpr int kRowsPerBlock = 1 << kRowsShift;
 
 // Compile-time transforms for the sizes the schedules use:
-//   tick axis N2 = 3125 (N' = 6250, 6000-tick planes) and N2 = 600 (N' = 1200,
+//   tick axis N2 = 3125 (N' = 6250, 6000-tick planes; 320 threads: two
+//   radix-5 butterflies per thread and pass) and N2 = 600 (N' = 1200,
 //   1000-tick planes);
 //   pitch axis: L = 1024 or 640 or 960 over 8 columns, L = 512 over 16
 //   columns.  A pitch block fills much of the LDS, so a CU holds two or three
 //   workgroups; they get 512 threads to keep enough waves.
-using TickCt3125 = FftCt<3125, kRowsShift, 3126, 1, 256, 5, 5, 5, 5, 5>;
+using TickCt3125 = FftCt<3125, kRowsShift, 3126, 1, 320, 5, 5, 5, 5, 5>;
 using TickCt600 = FftCt<600, kRowsShift, 601, 1, 128, 8, 5, 5, 3>;
 using PitchCt1024x8 = FftCt<1024, 3, 1, 8, 512, 8, 8, 4, 4>;
 using PitchCt512x16 = FftCt<512, 4, 1, 16, 512, 8, 8, 8>;
