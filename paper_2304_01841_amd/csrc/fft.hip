@@ -594,9 +594,10 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(C2RIo io, BatchTa
 // A workgroup takes Fb of the chunk's F columns (Fb < F when an L x F block
 // would not leave room for two workgroups per CU).
 // Workgroups are mapped XCD-major: workgroup b runs on XCD b mod 8, and the
-// workgroups of one XCD walk the pitch blocks of one column chunk before the
-// next, so the chunk's response spectrum and the rows shared by neighbouring
-// blocks are re-read from that XCD's L2.
+// workgroups of one XCD walk the pitch blocks of one chunk before the next,
+// the column parts of a block one after the other, so the chunk's response
+// spectrum, the rows shared by neighbouring blocks and the other part of each
+// row segment are re-read from that XCD's L2.
 // Wire output with D = nimpact dividing L folds the inverse: the kept rows of
 // a block are n = n0 + D w (n0 fixed by the block's first row), and
 //   y[n0 + D w] = sum_{k'<L/D} Z[k'] exp(2 pi i k' w / (L/D)),
@@ -643,11 +644,11 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
     const int mode = io.mode;
     const float2 *__restrict__ K = io.K;
     float2 *__restrict__ Y = io.Y;
+    const int parts_shift = F_shift - Fb_shift;  // parts of Fb columns per chunk
     const int xcd = gblk & 7, slot = gblk >> 3;
-    const int lcc = slot / nblocks, blk = slot - lcc * nblocks;
-    const int cc = lcc * 8 + xcd;  // column chunk: (chunk c, part hf of Fb columns)
-    const int parts_shift = F_shift - Fb_shift;
-    const int c = cc >> parts_shift, hf = cc & ((1 << parts_shift) - 1);
+    const int hf = slot & ((1 << parts_shift) - 1), rest = slot >> parts_shift;
+    const int lc = rest / nblocks, blk = rest - lc * nblocks;
+    const int c = lc * 8 + xcd;
     if (c >= C)
         return;
     const int D = nimpact, L10 = L / D;
@@ -921,8 +922,7 @@ hipError_t pitch_pass(const wcsim_plane *pl, const float2 *X, int nrows_in, cons
                       float2 *Y, int nrows_out, int nblocks, int mode, float scale, hipStream_t s)
 {
     const PitchIo io = {X, nrows_in, K, Y, nrows_out, nblocks, mode};
-    const int chunks = pl->C * (pl->F / pl->Fb);
-    const unsigned blocks = (unsigned)(8 * ((chunks + 7) / 8) * nblocks);
+    const unsigned blocks = (unsigned)(8 * ((pl->C + 7) / 8) * nblocks * (pl->F / pl->Fb));
     return pitch_any<false>(pl, io, BatchTables{}, blocks, scale, s);
 }
 
@@ -994,8 +994,7 @@ int rows_blocks(int nrows) { return (nrows + kRowsPerBlock - 1) / kRowsPerBlock;
 
 int pitch_blocks_total(const wcsim_plane *pl)
 {
-    const int chunks = pl->C * (pl->F / pl->Fb);
-    return 8 * ((chunks + 7) / 8) * pl->nblocks;
+    return 8 * ((pl->C + 7) / 8) * pl->nblocks * (pl->F / pl->Fb);
 }
 
 bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b)
