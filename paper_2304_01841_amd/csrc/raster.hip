@@ -514,7 +514,12 @@ constexpr int kRecWp = 8;                 // record offset of the pitch weights
 constexpr int kRecWt = kRecWp + kRecP;    // record offset of the quad-aligned tick weights
 static_assert(kRecWt % 4 == 0, "tick quads must be 16-byte aligned");
 static_assert(kRecWt + 4 * kRecQuads <= kRecWords, "depo record overflow");
-constexpr int kChunk = 16;                // depos per tile work item (one wavefront)
+// Depos per tile work item (one wavefront).  Each work item flushes its own
+// region cells with global atomics, and the regions of items sharing a track
+// overlap, so longer chunks mean fewer atomics; at most 64, one window per
+// lane for the bounding box.
+constexpr int kChunk = 32;
+static_assert(kChunk <= 64, "the chunk bounding box takes one patch window per lane");
 constexpr int kFluctItems = 3;            // work items per lane held in registers
 // A tile-path patch has at most kRecP * kRecQuads = 160 (row, quad) items.
 static_assert(kRecP * kRecQuads <= 64 * kFluctItems, "patch items overflow");
