@@ -55,9 +55,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-tune", action="store_true",
                     help="library default schedules instead of autotuned ones")
-    ap.add_argument("--schedule", type=str, default=None, metavar="JSON",
-                    help="fixed schedule of the benchmark plane, e.g. "
-                         "'{\"fft_pitch\": 512, \"freq_chunk\": 16}' (no tuning)")
+    ap.add_argument("--schedule", type=str, default=None, metavar="K=V[,K=V]",
+                    help="fixed schedule of the benchmark plane (no tuning), e.g. "
+                         "fft_pitch=640,freq_chunk=16 (or the same as a JSON object)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy kernel "
                          "whose HBM counters scale the kernels' FETCH_SIZE / WRITE_SIZE)")
@@ -227,7 +227,7 @@ def serve_measurement(W, nreq: int, tuner=None) -> dict:
             return sched if (desc["nticks"], np.shape(response)) == shape else None
     srv = serve.Server(phys, hbm_budget=64 << 30, slots=4, max_batch=8,
                        schedule_for=schedule_for)
-    srv.serve(reqs[: min(8, nreq)])  # plane set-up and allocator warm-up
+    srv.serve(reqs)  # plane set-up and (pinned) allocator warm-up for every request size
     sat = serve.latency_summary(srv.serve(reqs))
     out = {"requests": nreq, "budget_gb": 64, "slots": 4, "max_group": 8, "schedule": sched,
            "depos": int(sum(r["depos"].shape[0] for r in reqs)),
@@ -263,7 +263,10 @@ def main():
     dep = torch.from_numpy(w["depos"]).to(dev)
     tuner, tuning, sched = None, None, None
     if args.schedule:
-        sched = json.loads(args.schedule)
+        if args.schedule.lstrip().startswith("{"):
+            sched = json.loads(args.schedule)
+        else:
+            sched = {k: int(v) for k, v in (kv.split("=") for kv in args.schedule.split(","))}
     elif not args.no_tune:
         from paper_2304_01841_amd import autotune
         tuner = autotune.Tuner()

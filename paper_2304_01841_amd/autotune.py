@@ -29,6 +29,7 @@ PITCH_CHOICES = ({}, {"fft_pitch": 512, "freq_chunk": 16}, {"fft_pitch": 1024, "
                  {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 640, "freq_chunk": 16},
                  {"fft_pitch": 960, "freq_chunk": 16})
 TILE_CHOICES = (0, 2)
+TIE = 0.02  # relative timing difference treated as a tie
 
 
 def candidates() -> list:
@@ -84,8 +85,11 @@ class Tuner:
         cands = candidates()
         ms = wcsim.tune_schedules(plane, phys, response, depos, cands, r0=r0, kind=kind,
                                   reps=self.reps, stream=stream)
+        # the first candidate (in list order) within TIE of the fastest, so that
+        # timing noise does not flip between near-equal schedules
         timed = [(t, i) for i, t in enumerate(ms) if t >= 0.0]
-        best_t, best_i = min(timed)
+        fastest = min(t for t, _ in timed)
+        best_t, best_i = next((t, i) for t, i in timed if t <= fastest * (1.0 + TIE))
         entry = {"schedule": cands[best_i], "ms": best_t,
                  "default_ms": ms[0] if ms[0] >= 0.0 else None,
                  "candidates": [{"schedule": c, "ms": t} for c, t in zip(cands, ms)]}
