@@ -968,18 +968,28 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
         }
     }
     wave_lds_sync();  // every deposit lands before the flush reads the region
+    // Flush: consecutive lanes take consecutive ticks of a row, so that one
+    // atomic instruction covers 256 contiguous bytes (few L2 lines) rather
+    // than 16-byte pieces of many lines.
     float *grid = E.grid;
-    for (int x = lane; x < bcells; x += 64) {
-        const int r = div_small(x, bmagic), cq = bq0 + (x - r * bnq);
-        const float4 a4 = acc4[(br0 + r) * (RT / 4) + cq];
-        const float v[4] = {a4.x, a4.y, a4.z, a4.w};
-        const int I = p0 + br0 + r, J0 = c0 + 4 * cq;
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm) {
-            const int J = J0 + mm;
-            if (v[mm] != 0.0f && (unsigned)J < (unsigned)P.Nt)
-                unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v[mm]);
-        }
+    const float *acc = (const float *)acc4;
+    const int W = 4 * bnq;  // floats per bounding-box row
+    const int nrows = max(br1 - br0, 0);
+    auto flush_one = [&](int r, int col) {
+        const float v = acc[(br0 + r) * RT + 4 * bq0 + col];
+        const int J = c0 + 4 * bq0 + col;
+        if (v != 0.0f && (unsigned)J < (unsigned)P.Nt)
+            unsafeAtomicAdd(grid + (size_t)(p0 + br0 + r) * P.Nt + J, v);
+    };
+    if (W > 0 && W <= 64) {
+        const int per = 64 / W, r_l = lane / W, col = lane - r_l * W;
+        if (r_l < per)
+            for (int r = r_l; r < nrows; r += per)
+                flush_one(r, col);
+    } else if (W > 64) {
+        for (int r = 0; r < nrows; ++r)
+            for (int col = lane; col < W; col += 64)
+                flush_one(r, col);
     }
 }
 
@@ -1221,7 +1231,7 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
         return e;
     // Depos whose patch does not fit a tile region: one workgroup each, direct
     // atomics.  The grid is persistent over the device-side count.
-    const unsigned lg = (unsigned)std::min<int64_t>(n, 2048);
+    const unsigned lg = (unsigned)std::min<int64_t>(n, 512);
     hipLaunchKernelGGL((k_patch_generic<256, false, B>), dim3(lg), dim3(256), 0, s, e0, bt,
                        w.large, w.counters + 1, (int64_t)0, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess)
