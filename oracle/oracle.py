@@ -59,7 +59,7 @@ def _load():
         lib.oracle_depo_window.argtypes = [P, P, P, P, P, P]
         lib.oracle_depo_window.restype = ctypes.c_int
         lib.oracle_axis_weights.argtypes = [i64, i64, ctypes.c_double, ctypes.c_double, P]
-        lib.oracle_rasterize.argtypes = [P, i64, P, i32, u64, P, P, u64, P, P, i64, P]
+        lib.oracle_rasterize.argtypes = [P, i64, P, i32, u64, P, P, u64, P, P, P, i64, P]
         lib.oracle_rasterize.restype = i64
         lib.oracle_scatter.argtypes = [P, P, i64, i64, i64, P]
         lib.oracle_convolve_points.argtypes = [P, i64, i64, P, i64, i64, i64, P, i64, P]
@@ -130,15 +130,17 @@ def axis_weights(lo: int, n: int, mu: float, s: float) -> np.ndarray:
     return W
 
 
-def rasterize(depos: np.ndarray, phys: dict, plane: dict, event_id: int = 0):
+def rasterize(depos: np.ndarray, phys: dict, plane: dict, event_id: int = 0, ids=None):
     """Patches of all depos.
 
     Returns (meta, values, status): meta is (n, 5) int64 rows
     (lo_p, lo_t, n_p, n_t, offset); values the flat float64 patch values
     (row-major n_p x n_t per depo, at its offset); status per depo
-    (0 ok, 1 invalid, 2 window misses the grid)."""
+    (0 ok, 1 invalid, 2 window misses the grid).  `ids`: the depos' indices
+    in their event (default 0..n-1), which key the fluctuation."""
     depos = np.ascontiguousarray(depos, dtype=np.float64).reshape(-1, 5)
     n = depos.shape[0]
+    ids_arr = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64).reshape(n)
     meta = np.zeros((n, 5), np.int64)
     status = np.zeros(n, np.int32)
     lib = _load()
@@ -148,7 +150,8 @@ def rasterize(depos: np.ndarray, phys: dict, plane: dict, event_id: int = 0):
     while True:
         values = np.zeros(cap, np.float64)
         got = lib.oracle_rasterize(_ptr(depos), n, args[0], args[1], args[2], args[3], args[4],
-                                   args[5], _ptr(meta), _ptr(values), cap, _ptr(status))
+                                   args[5], None if ids_arr is None else _ptr(ids_arr), _ptr(meta),
+                                   _ptr(values), cap, _ptr(status))
         if got >= 0:
             return meta, values[:got], status
         cap = -got
@@ -163,8 +166,8 @@ def scatter(meta: np.ndarray, values: np.ndarray, plane: dict) -> np.ndarray:
     return G
 
 
-def grid(depos: np.ndarray, phys: dict, plane: dict, event_id: int = 0) -> np.ndarray:
-    meta, values, _ = rasterize(depos, phys, plane, event_id)
+def grid(depos: np.ndarray, phys: dict, plane: dict, event_id: int = 0, ids=None) -> np.ndarray:
+    meta, values, _ = rasterize(depos, phys, plane, event_id, ids)
     return scatter(meta, values, plane)
 
 

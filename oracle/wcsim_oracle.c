@@ -217,10 +217,13 @@ void oracle_axis_weights(int64_t lo, int64_t n, double mu, double s, double *W)
  * takes the normal approximation of a binomial draw of the q electrons with
  * probability p = W_p W_t, clamped at zero, and the patch is rescaled so that
  * its total (over the whole window, in the grid or not) equals q again.
+ * The normal deviates are keyed by each depo's index in its event (reading
+ * A7): d itself, or ids[d] when ids is given (a subset of an event's depos).
  * Returns the number of values, or -(needed) when cap is too small. */
 int64_t oracle_rasterize(const double *depos, int64_t n, const double *phys, int32_t fluctuate,
                          uint64_t seed, const double *geom, const int32_t *dims, uint64_t event_id,
-                         int64_t *meta, double *values, int64_t cap, int32_t *status)
+                         const int64_t *ids, int64_t *meta, double *values, int64_t cap,
+                         int32_t *status)
 {
     int64_t total = 0;
     for (int64_t d = 0; d < n; ++d) {
@@ -261,7 +264,8 @@ int64_t oracle_rasterize(const double *depos, int64_t n, const double *phys, int
             for (int64_t i = 0; i < n_p; ++i) {
                 for (int64_t j = 0; j < n_t; ++j) {
                     double p = Wp[i] * Wt[j];
-                    double z = oracle_normal(w.lo_p + i, w.lo_t + j, d, event_id, seed, plane_id);
+                    double z = oracle_normal(w.lo_p + i, w.lo_t + j, ids ? ids[d] : d, event_id,
+                                             seed, plane_id);
                     double F = q * p + z * sqrt(q * p * (1.0 - p));
                     if (F < 0.0)
                         F = 0.0;

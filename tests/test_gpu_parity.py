@@ -248,6 +248,57 @@ def test_simulate_collection_full_size(ws):
     _sim_and_compare(ws, w, kinds=(ws.OUT_WIRE,), schedules=autotune.candidates())
 
 
+def _pitch_bins(depos, pl):
+    """Mean pitch bin of each depo (projection of (y, z) on the pitch
+    direction); used only to pick a superset of the depos that can reach
+    given grid rows."""
+    dp = pl["pitch"] / pl["nimpact"]
+    return ((depos[:, 1] * pl["dir_y"] + depos[:, 2] * pl["dir_z"]) - pl["pitch_origin"]) / dp
+
+
+def test_simulate_three_plane_full_size_sampled(ws):
+    """The three-plane event (U/V/W 800/800/960 wires x 6000 ticks, bipolar
+    and unipolar responses, 2,400,000 depos, fluctuation on) at its full size,
+    under the library default and the tuned pitch schedule: sampled wire
+    waveforms against the oracle.  For each sampled wire the oracle takes
+    every depo whose window can reach the response's reach of that wire (a
+    superset chosen by mean pitch bin plus 40 bins), keyed by its index in
+    the event, and evaluates the defining convolution sum at the sampled
+    ticks."""
+    log("case: simulate three planes, full size, sampled")
+    w = W.three_plane()
+    dep_np, ph, ev = w["depos"], w["phys"], w["event_id"]
+    dep = torch.from_numpy(dep_np).cuda()
+    rng = np.random.default_rng(31)
+    for pl, R in zip(w["planes"], w["responses"]):
+        Rp = R.shape[0]
+        r0 = Rp // 2
+        nimp = pl["nimpact"]
+        mu = _pitch_bins(dep_np, pl)
+        for sched in (None, {"fft_pitch": 640, "freq_chunk": 16}):
+            log("  plane %d schedule %s" % (pl["plane_id"], sched))
+            P = ws.Plane(pl, ph, R, schedule=sched)
+            wsp = ws.simulate_workspace(P, dep.shape[0], ws.OUT_WIRE)
+            out = ws.simulate_event(P, dep, ev, kind=ws.OUT_WIRE, workspace=wsp).cpu().numpy()
+            assert ws.workspace_invalid_count(wsp) == 0
+            scale = np.abs(out).max()
+            assert scale > 0
+            # the two wires with the largest signal and two at random
+            wires = list(np.argsort(-np.abs(out).max(axis=1))[:2])
+            wires += list(rng.integers(0, pl["nwires"], 2))
+            ticks = np.arange(0, pl["nticks"], 7)
+            for wi in wires:
+                p = int(wi) * nimp + nimp // 2
+                lo, hi = p + r0 - (Rp - 1), p + r0
+                idx = np.nonzero((mu >= lo - 40) & (mu <= hi + 40))[0]
+                G = O.grid(dep_np[idx], ph, pl, ev, ids=idx)
+                pts = np.stack([np.full(ticks.shape, p), ticks], axis=1)
+                ref = O.convolve_points(G, R.astype(np.float64), r0, pts)
+                err = np.abs(out[int(wi), ticks] - ref).max() / scale
+                assert err <= CONV_TOL, (pl["plane_id"], sched, int(wi), err)
+            P.destroy()
+
+
 def test_simulate_empty_and_invalid(ws):
     log("case: simulate empty / invalid")
     pl = W.plane(10, 200)

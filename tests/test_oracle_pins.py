@@ -417,3 +417,22 @@ def test_fluctuation_variance_short_drift():
     assert big.sum() >= 3 and p.max() > 0.2
     ratio = V.var(0)[big] / expect[big]
     assert np.all(np.abs(ratio - 1.0) < 0.12)
+
+
+def test_grid_of_a_partition_with_event_indices():
+    """The grid is a sum over depos, and a depo's fluctuation is keyed by its
+    index in the event: the grids of the parts of a partition of an event's
+    depos, each keyed by the depos' event indices, add up to the event's grid
+    (up to summation order)."""
+    w = W.small()
+    pl, d = w["planes"][0], w["depos"]
+    ph = W.physics(True)
+    G = O.grid(d, ph, pl, 3)
+    parts = np.zeros_like(G)
+    for s in range(3):
+        idx = np.arange(s, d.shape[0], 3)
+        parts += O.grid(d[idx], ph, pl, 3, ids=idx)
+    assert np.abs(parts - G).max() <= 1e-12 * np.abs(G).max()
+    # keyed by positions in the part instead, the fluctuations differ
+    idx = np.arange(0, d.shape[0], 3)
+    assert np.abs(O.grid(d[idx], ph, pl, 3) - O.grid(d[idx], ph, pl, 3, ids=idx)).max() > 0
