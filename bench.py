@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served-form measurement")
     ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--no-three-plane", action="store_true",
+                    help="skip the three-plane (U/V/W, 2.4M depos) event measurement")
     ap.add_argument("--no-tune", action="store_true",
                     help="library default schedules instead of autotuned ones")
     ap.add_argument("--schedule", type=str, default=None, metavar="K=V[,K=V]",
@@ -201,6 +203,41 @@ def batch_comparison(wcsim, W, dev, nevents: int, tuner=None, rounds: int = 3) -
     return res
 
 
+def three_plane_measurement(wcsim, W, dev, tuner=None, steps: int = 10) -> dict:
+    """The three-plane event (U/V/W 800/800/960 wires x 6000 ticks, 2,000,000
+    track + 400,000 background depos, fluctuation on, wire output): the three
+    planes run one after the other on one stream per step, depos resident."""
+    import torch
+
+    w = W.three_plane()
+    dep = torch.from_numpy(w["depos"]).to(dev)
+    n = dep.shape[0]
+    planes, outs, wsps, scheds = [], [], [], []
+    for pl, R in zip(w["planes"], w["responses"]):
+        sched = tuner.tune(pl, w["phys"], R, dep) if tuner is not None else None
+        P = wcsim.Plane(pl, w["phys"], R, schedule=sched)
+        planes.append(P)
+        scheds.append(sched or {})
+        outs.append(torch.empty((P.nwires, P.nticks), dtype=torch.float32, device=dev))
+        wsps.append(wcsim.simulate_workspace(P, n, wcsim.OUT_WIRE, dev))
+
+    def step():
+        for P, o, ws in zip(planes, outs, wsps):
+            wcsim.simulate_event(P, dep, w["event_id"], out=o, workspace=ws)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    for P in planes:
+        P.destroy()
+    return {"ms_per_event": dt * 1e3, "depos_per_s": n / dt, "depo_planes_per_s": 3 * n / dt,
+            "planes_per_s": 3 / dt, "depos": int(n), "schedules": scheds}
+
+
 def serve_measurement(W, nreq: int, tuner=None) -> dict:
     """The serving workload (requests of 1-3 planes of 100-960 wires x 6000
     ticks, depo counts log-uniform in 10^3..2x10^6): saturated throughput
@@ -342,6 +379,10 @@ def main():
     if not args.no_batch:
         batch = batch_comparison(wcsim, W, dev, args.batch_events, tuner)
 
+    three = None
+    if not args.no_three_plane:
+        three = three_plane_measurement(wcsim, W, dev, tuner)
+
     served = None
     if not args.no_serve:
         served = serve_measurement(W, args.serve_requests, tuner)
@@ -378,6 +419,7 @@ def main():
         "stage_ms": stages,
         "stage_hbm_gbs": per_stage_hbm,
         "roofline": roofline,
+        "three_plane": three,
         "batch": batch,
         "serve": served,
         "cpu_baseline": cpu,
