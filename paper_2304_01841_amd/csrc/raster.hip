@@ -12,10 +12,11 @@
 // Scatter-Add (Sec. 2 step 2) runs two ways:
 //  * fused (simulate path): depos are binned by the grid tile holding their
 //    window origin (count -> exclusive scan -> fill, the scan of Sec. 4.3);
-//    one workgroup per tile rasterizes its depos, one wavefront per patch, into
-//    an LDS copy of the tile plus a halo, then flushes the non-zero LDS cells
-//    to HBM with float atomics, so the grid sees one atomic per touched cell
-//    per tile instead of one per patch bin;
+//    a tile's list is cut into work items of a few dozen depos, and one
+//    wavefront per work item rasterizes them, one patch at a time, into its
+//    own LDS copy of the tile plus a halo, then adds the non-zero LDS cells to
+//    the grid with float atomics, so the grid sees one atomic per touched cell
+//    per work item instead of one per patch bin;
 //  * unfused (patch-set API): patches are written to a flat buffer at the
 //    scanned offsets and a second kernel adds them to the grid atomically.
 #include <math.h>
@@ -165,35 +166,6 @@ __device__ __forceinline__ float wave_sum_uniform(float v)
     const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
     const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
     return (r0 + r1) + (r2 + r3);
-}
-
-// Weights of one axis from `WIDTH` lanes: lane k holds edge k (n <= WIDTH - 1).
-template <int WIDTH>
-__device__ __forceinline__ void lane_axis_weights(int lo, int n, double mu, double s, int k,
-                                                  float *W)
-{
-    const double E = (k <= n && s > 0.0) ? edge_erf(lo, k, mu, s) : 0.0;
-    const double En = __shfl_down(E, 1, WIDTH);
-    const double wk = (k < n) ? 0.5 * (En - E) : 0.0;
-    const double sum = seg_sum<WIDTH>(wk);
-    if (k < n)
-        W[k] = (s > 0.0) ? (float)(wk / sum) : (k == 0 ? 1.0f : 0.0f);
-}
-
-// Both axes' weights of a patch with windows shorter than 64 bins, into the
-// wave's LDS arrays.  Windows shorter than 32 bins share one erf per lane
-// (pitch edges on lanes 0-31, tick edges on lanes 32-63).
-__device__ __forceinline__ void wave_weights(const Win &w, float *Wp, float *Wt, int lane)
-{
-    if (w.n_p < 32 && w.n_t < 32) {
-        const bool tax = lane >= 32;
-        lane_axis_weights<32>(tax ? w.lo_t : w.lo_p, tax ? w.n_t : w.n_p, tax ? w.mu_t : w.mu_p,
-                              tax ? w.s_t : w.s_p, lane & 31, tax ? Wt : Wp);
-    } else {
-        lane_axis_weights<64>(w.lo_p, w.n_p, w.mu_p, w.s_p, lane, Wp);
-        lane_axis_weights<64>(w.lo_t, w.n_t, w.mu_t, w.s_t, lane, Wt);
-    }
-    wave_lds_sync();
 }
 
 // Fluctuated bin value before rescaling: normal approximation of the binomial
