@@ -97,7 +97,9 @@ typedef struct {
     int32_t fft_ticks;  /* even padded tick-axis transform length N' >= nticks + resp_nticks - 1 */
     int32_t fft_pitch;  /* pitch-axis overlap-save block transform length L > resp_npitch - 1 */
     int32_t freq_chunk; /* spectrum columns per chunk (8 or 16) */
-    int32_t tile;       /* raster tile shape id (see wcsim_plane_info.tile) */
+    int32_t tile;       /* raster tile shape id, pitch bins x ticks of a tile: 0 = 32 x 8
+                         * (default), 1 = 32 x 32, 2 = 64 x 8; each wavefront's LDS
+                         * region adds a 32-bin x 16-tick halo */
 } wcsim_schedule;
 
 /* Derived sizes of a plane (read-only). */

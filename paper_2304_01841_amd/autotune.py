@@ -28,7 +28,7 @@ from . import wcsim
 PITCH_CHOICES = ({}, {"fft_pitch": 512, "freq_chunk": 16}, {"fft_pitch": 1024, "freq_chunk": 16},
                  {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 640, "freq_chunk": 16},
                  {"fft_pitch": 960, "freq_chunk": 16})
-TILE_CHOICES = (0, 2)
+TILE_CHOICES = (0, 1, 2)
 TIE = 0.02  # relative timing difference treated as a tie
 
 

@@ -734,17 +734,18 @@ __global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt
     }
 }
 
-// Region columns start kPadT ticks before the tile and rows are a multiple of
-// four floats, so that a tick quad (four ticks 4k .. 4k + 3, the unit one
-// Philox block covers) is one aligned 16-byte LDS access.  A quad's ticks
-// outside the window carry weight zero, hence deposit zero; cells outside the
+// Region columns start at the tile's first tick (a multiple of four) and rows
+// are a multiple of four floats, so that a tick quad (four ticks 4k .. 4k + 3,
+// the unit one Philox block covers) is one aligned 16-byte LDS access.  A
+// window starts inside its tile and spans at most kHaloT + 1 ticks, so its
+// last quad ends before column TT + kHaloT.  A quad's ticks outside the window
+// carry weight zero, hence deposit zero; quads before tick 0 (windows of the
+// first tile that start before the grid) are dropped, and cells outside the
 // grid are never flushed.
-constexpr int kPadT = 4;
-
 template <int TT>
 constexpr int region_cols()
 {
-    return TT + kHaloT + 2 * kPadT;
+    return TT + kHaloT;
 }
 
 // Header of one record, read from the lanes that hold its words (lane w holds
@@ -847,7 +848,7 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     const PlaneParams P = E.kp;
     const int local = tile - E.tile_base;
     const int p0 = (local / E.ntt) * TP, t0 = (local % E.ntt) * TT;
-    const int c0 = t0 - kPadT;  // grid tick of region column 0
+    const int c0 = t0;  // grid tick of region column 0
     // Only the bounding box of the chunk's patches (in region rows and tick
     // quads, within the grid) is cleared and flushed; deposits outside the
     // grid land outside it and are never read.
@@ -995,11 +996,11 @@ TileShape tile_shape(int id)
 {
     switch (id) {
     case 1:
-        return {64, 64, kHaloP, kHaloT};
-    case 2:
-        return {32, 64, kHaloP, kHaloT};
-    default:
         return {32, 32, kHaloP, kHaloT};
+    case 2:
+        return {64, 8, kHaloP, kHaloT};
+    default:
+        return {32, 8, kHaloP, kHaloT};
     }
 }
 
@@ -1187,15 +1188,15 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     const unsigned grid_items = (unsigned)items_cap(ntiles, n);
     switch (pl->tile) {
     case 1:
-        hipLaunchKernelGGL((k_raster_tiles<64, 64, B>), dim3(grid_items), dim3(64), 0, s,
+        hipLaunchKernelGGL((k_raster_tiles<32, 32, B>), dim3(grid_items), dim3(64), 0, s,
                            w.records, w.items, w.counters, e0, bt);
         break;
     case 2:
-        hipLaunchKernelGGL((k_raster_tiles<32, 64, B>), dim3(grid_items), dim3(64), 0, s,
+        hipLaunchKernelGGL((k_raster_tiles<64, 8, B>), dim3(grid_items), dim3(64), 0, s,
                            w.records, w.items, w.counters, e0, bt);
         break;
     default:
-        hipLaunchKernelGGL((k_raster_tiles<32, 32, B>), dim3(grid_items), dim3(64), 0, s,
+        hipLaunchKernelGGL((k_raster_tiles<32, 8, B>), dim3(grid_items), dim3(64), 0, s,
                            w.records, w.items, w.counters, e0, bt);
         break;
     }

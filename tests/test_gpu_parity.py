@@ -237,6 +237,23 @@ def test_simulate_small(ws):
     _sim_and_compare(ws, w, fl=True, out_mem="host", event_id=12)
 
 
+def test_simulate_small_every_tile_shape(ws):
+    """Every raster tile shape (32 x 8, 32 x 32, 64 x 8 bins x ticks) gives the
+    oracle's grid and output, with and without fluctuation."""
+    log("case: simulate small workload, every tile shape")
+    shapes = [{"tile": t} for t in range(3)]
+    w = W.small()
+    for fl in (False, True):
+        _sim_and_compare(ws, w, fl=fl, kinds=(ws.OUT_PITCH,), schedules=shapes)
+    # depos straddling every grid edge (windows starting before pitch bin 0 and
+    # tick 0, or running past the last ones) on the fused tile path
+    rng = np.random.default_rng(19)
+    dep = W.uniform_depos(rng, 600, (-5.0, 105.0), (-10.0, 160.0))
+    edges = dict(planes=[W.plane(20, 300)], responses=[W.response("bipolar")], depos=dep,
+                 phys=W.physics(True), event_id=6)
+    _sim_and_compare(ws, edges, kinds=(ws.OUT_PITCH,), schedules=shapes)
+
+
 def test_simulate_collection_full_size(ws):
     """Detector-scale collection plane (960 wires x 10 impact x 6000 ticks,
     500,000 track depos, fluctuation) in every launch configuration the
