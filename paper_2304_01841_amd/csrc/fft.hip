@@ -457,38 +457,31 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
         return v;
     };
     fft.run_io(lds, tabN2, load, InLds{});
+    // Unpacking straight to the output: the pair (k, N2 - k) goes from LDS to
+    // its two chunk slots, and the padding frequencies above N2 get zeros.
     const int half = N2 / 2;
+    const int F = 1 << F_shift;
+    const int CF = C << F_shift;
     for (int s = 0; s < RPW; ++s) {
-        float2 *b = lds + s * S;
+        const int row = row0 + s;
+        if (row >= nrows)
+            break;
+        const float2 *b = lds + s * S;
+        auto put = [&](int k, float2 v) {
+            X[(((int64_t)(k >> F_shift) * nrows + row) << F_shift) + (k & (F - 1))] = v;
+        };
         for (int k = threadIdx.x; k <= half; k += blockDim.x) {
             const int kn = (k == 0) ? 0 : N2 - k;
             const float2 Zk = b[k], Zn = b[kn];
             const float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
             const float2 D = make_float2(0.5f * (Zk.x - Zn.x), 0.5f * (Zk.y + Zn.y));
             const float2 wD = cmul(tw_at(tabH, k), D);
-            b[k] = csub(E, mul_pi(wD));
-            b[(k == 0) ? N2 : kn] = conjf2(cadd(E, mul_pi(wD)));
+            put(k, csub(E, mul_pi(wD)));
+            put((k == 0) ? N2 : kn, conjf2(cadd(E, mul_pi(wD))));
         }
+        for (int k = N2 + 1 + threadIdx.x; k < CF; k += blockDim.x)
+            put(k, make_float2(0.0f, 0.0f));
     }
-    __syncthreads();
-    const int F = 1 << F_shift;
-    const int total = C << (F_shift + rpw_shift);
-    batched_copy(
-        total,
-        [&](int g) {
-            const int f = g & (F - 1);
-            const int s = (g >> F_shift) & (RPW - 1);
-            const int k = ((g >> (F_shift + rpw_shift)) << F_shift) + f;
-            return (k <= N2) ? lds[s * S + k] : make_float2(0.0f, 0.0f);
-        },
-        [&](int g, float2 v) {
-            const int f = g & (F - 1);
-            const int s = (g >> F_shift) & (RPW - 1);
-            const int c = g >> (F_shift + rpw_shift);
-            const int row = row0 + s;
-            if (row < nrows)
-                X[(((int64_t)c * nrows + row) << F_shift) + f] = v;
-        });
 }
 
 // ---------------------------------------------------------------------------
