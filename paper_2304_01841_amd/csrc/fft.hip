@@ -679,20 +679,28 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
         for (int t = threadIdx.x; t < (L10 << Fb_shift); t += blockDim.x) {
             const int kp = t >> Fb_shift, s = t & ((1 << Fb_shift) - 1);
             float2 acc = make_float2(0.0f, 0.0f);
-            for (int j = 0; j < D; ++j) {
-                const float2 w = conjf2(tw_at(tabL, ((j * n0) % D) * L10));
+            // m = j n0 mod D, stepped (uniform across the workgroup)
+            for (int j = 0, m = 0; j < D; ++j) {
+                const float2 w = conjf2(tw_at(tabL, m * L10));
                 acc = cadd(acc, cmul(lds[((kp + j * L10) << Fb_shift) + s], w));
+                m += n0;
+                m -= (m >= D) ? D : 0;
             }
             // conjugated: the inverse runs as a forward transform
-            Z[t] = conjf2(cmul(acc, conjf2(tw_at(tabL, (kp * n0) % L))));
+            // (kp n0 < L10 D = L: no reduction needed)
+            Z[t] = conjf2(cmul(acc, conjf2(tw_at(tabL, kp * n0))));
         }
         __syncthreads();
+        // kept row n = n0 + D w is grid row p = P0 + n - (Rp - 1), output row
+        // p / D = q0 + w (floor division, exact for every kept row)
+        const int base = P0 + n0 - (Rp - 1);
+        const int q0 = (base >= 0) ? base / D : -((D - 1 - base) / D);
+        const int wmin = (Rp - 1 - n0 + D - 1) / D;  // first w with n >= Rp - 1
+        const int wend = nrows_in - base;              // p < nrows_in  <=>  D w < wend
         fft2.run_io(Z, tab2, InLds{}, [&](int s, int w, float2 v) {
-            const int n = n0 + D * w;
-            const int p = P0 + n - (Rp - 1);
-            if (n < Rp - 1 || p >= nrows_in)
+            if (w < wmin || D * w >= wend)
                 return;
-            dst[((int64_t)(p / D) << F_shift) + s] = conjf2(v);
+            dst[((int64_t)(q0 + w) << F_shift) + s] = conjf2(v);
         });
         return;
     }
