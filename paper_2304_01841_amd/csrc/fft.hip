@@ -271,23 +271,37 @@ __device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab, Load &lo
     constexpr int MAXB = (TOTAL + NT - 1) / NT;
     constexpr int TWSTEP = N / (P * R);
     constexpr int MASK = (1 << NSS) - 1;
+    // Unguarded loads when at most 1/8 of them would be discarded.
+    constexpr bool kLoadAll = 8 * (MAXB * NT - TOTAL) <= MAXB * NT;
     static_assert(!GLOAD || P == 1, "only the first pass reads its inputs from a loader");
     const int tid = threadIdx.x;
     float2 v[MAXB][R];
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
-        const int g = tid + b * NT;
-        if ((TOTAL % NT) == 0 || g < TOTAL) {
+        if constexpr (GLOAD && kLoadAll) {
+            // Threads past the last butterfly load a valid one's inputs and
+            // discard them: no branch separates the loads of the MAXB
+            // butterflies, so all of them are in flight together (loaders
+            // select their padding instead of branching).
+            const int g = min(tid + b * NT, TOTAL - 1);
             const int s = g & MASK, i = g >> NSS;
-            if constexpr (GLOAD) {
 #pragma unroll
-                for (int t = 0; t < R; ++t)
-                    v[b][t] = load(s, i + t * NB);
-            } else {
-                const float2 *src = buf + s * SS + i * ES;
+            for (int t = 0; t < R; ++t)
+                v[b][t] = load(s, i + t * NB);
+        } else {
+            const int g = tid + b * NT;
+            if ((TOTAL % NT) == 0 || g < TOTAL) {
+                const int s = g & MASK, i = g >> NSS;
+                if constexpr (GLOAD) {
 #pragma unroll
-                for (int t = 0; t < R; ++t)
-                    v[b][t] = src[t * NB * ES];
+                    for (int t = 0; t < R; ++t)
+                        v[b][t] = load(s, i + t * NB);
+                } else {
+                    const float2 *src = buf + s * SS + i * ES;
+#pragma unroll
+                    for (int t = 0; t < R; ++t)
+                        v[b][t] = src[t * NB * ES];
+                }
             }
         }
     }
@@ -437,26 +451,28 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
     float2 *tabH = tabN2 + tw.na;
     load_tables(tw, tabN2, tabH);
     const int row0 = blk * RPW;
-    const bool vec2 = ((ncols & 1) == 0) && ((in_stride & 1) == 0);
-    // z_n of row s straight from global memory into the first pass
-    auto load = [&](int s, int n) {
+    // z_n of row s straight from global memory into the first pass.  Every
+    // load is issued unconditionally from a clamped (valid) address and the
+    // padding is selected afterwards, so the loads of a pass stay in flight
+    // together instead of waiting on each other across branches.
+    auto load2 = [&](int s, int n) {  // even ncols and stride: one 8-byte load
         const int row = row0 + s, t = 2 * n;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (row < nrows) {
-            const float *src = in + (int64_t)row * in_stride;
-            if (vec2) {
-                if (t < ncols)
-                    v = *(const float2 *)(src + t);
-            } else {
-                if (t < ncols)
-                    v.x = src[t];
-                if (t + 1 < ncols)
-                    v.y = src[t + 1];
-            }
-        }
-        return v;
+        const float *src = in + (int64_t)min(row, nrows - 1) * in_stride;
+        const float2 v = *(const float2 *)(src + min(t, ncols - 2));
+        const bool ok = row < nrows && t < ncols;
+        return ok ? v : make_float2(0.0f, 0.0f);
     };
-    fft.run_io(lds, tabN2, load, InLds{});
+    auto load1 = [&](int s, int n) {
+        const int row = row0 + s, t = 2 * n;
+        const float *src = in + (int64_t)min(row, nrows - 1) * in_stride;
+        const float a = src[min(t, ncols - 1)], b = src[min(t + 1, ncols - 1)];
+        const bool ok = row < nrows;
+        return make_float2((ok && t < ncols) ? a : 0.0f, (ok && t + 1 < ncols) ? b : 0.0f);
+    };
+    if ((ncols & 1) == 0 && (in_stride & 1) == 0)
+        fft.run_io(lds, tabN2, load2, InLds{});
+    else
+        fft.run_io(lds, tabN2, load1, InLds{});
     // Unpacking straight to the output: the pair (k, N2 - k) goes from LDS to
     // its two chunk slots, and the padding frequencies above N2 get zeros.
     const int half = N2 / 2;
