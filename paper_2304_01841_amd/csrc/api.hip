@@ -162,7 +162,7 @@ wcsim_status choose_schedule(wcsim_plane *pl, const wcsim_schedule *sc)
                twiddle_table_len(L / D) <= 256;
     pl->L10 = pl->fold ? L / D : 0;
     if (sizeof(float2) * ((size_t)L * pl->Fb + (size_t)pl->L10 * pl->Fb + twiddle_table_len(L) +
-                          (pl->fold ? twiddle_table_len(pl->L10) : 0)) > kLdsBytes ||
+                          (pl->fold ? twiddle_table_len(pl->L10) + D : 0)) > kLdsBytes ||
         twiddle_table_len(L) > 256)
         return fail(WCSIM_E_INVALID, "pitch block too large for LDS");
     {

@@ -666,8 +666,17 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
     float2 *Z = lds + LFb;
     float2 *tabL = Z + (fold_ok ? (L10 << Fb_shift) : 0);
     float2 *tab2 = tabL + tw.na;
+    float2 *wfold = tab2 + tw.nb;  // D fold twiddles when folding
     load_tables(tw, tabL, tab2);
     const int P0 = blk * V;
+    // block row n0 is the first kept row (grid row = centre impact of a wire)
+    const int n0 = ((D / 2 - P0 + Rp - 1) % D + D) % D;
+    if (fold && (int)threadIdx.x < D) {
+        // exp(+2 pi i (j n0 mod D) / D) for j = threadIdx.x, from FP64
+        double sv, cv;
+        sincospi(2.0 * (double)((threadIdx.x * n0) % D) / (double)D, &sv, &cv);
+        wfold[threadIdx.x] = make_float2((float)cv, (float)sv);
+    }
     const int in0 = (mode == 2) ? 0 : P0 + r0 - (Rp - 1);
     const int col0 = hf << Fb_shift;
     const float2 *src = X + ((int64_t)c * nrows_in << F_shift) + col0;
@@ -691,17 +700,11 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
             lds[(n << Fb_shift) + s] = cmul(v, Kc[(n << F_shift) + s]);
         });
         __syncthreads();
-        const int n0 = ((D / 2 - P0 + Rp - 1) % D + D) % D;
         for (int t = threadIdx.x; t < (L10 << Fb_shift); t += blockDim.x) {
             const int kp = t >> Fb_shift, s = t & ((1 << Fb_shift) - 1);
             float2 acc = make_float2(0.0f, 0.0f);
-            // m = j n0 mod D, stepped (uniform across the workgroup)
-            for (int j = 0, m = 0; j < D; ++j) {
-                const float2 w = conjf2(tw_at(tabL, m * L10));
-                acc = cadd(acc, cmul(lds[((kp + j * L10) << Fb_shift) + s], w));
-                m += n0;
-                m -= (m >= D) ? D : 0;
-            }
+            for (int j = 0; j < D; ++j)
+                acc = cadd(acc, cmul(lds[((kp + j * L10) << Fb_shift) + s], wfold[j]));
             // conjugated: the inverse runs as a forward transform
             // (kp n0 < L10 D = L: no reduction needed)
             Z[t] = conjf2(cmul(acc, conjf2(tw_at(tabL, kp * n0))));
@@ -899,8 +902,10 @@ void launch_pitch(const wcsim_plane *pl, FFT fft, FFT2 fft2, int threads, const 
 {
     const TwTables tw = {pl->twL, table_len(pl->L), pl->fold ? pl->twF : nullptr,
                          pl->fold ? table_len(pl->L10) : 0};
-    const size_t lds = sizeof(float2) * ((size_t)pl->L * pl->Fb +
-                                         (pl->fold ? (size_t)pl->L10 * pl->Fb : 0) + tw.na + tw.nb);
+    const size_t lds =
+        sizeof(float2) * ((size_t)pl->L * pl->Fb +
+                          (pl->fold ? (size_t)pl->L10 * pl->Fb + pl->kp.nimpact : 0) + tw.na +
+                          tw.nb);
     hipLaunchKernelGGL((k_pitch_conv<FFT, FFT2, B>), dim3(blocks), dim3(threads), lds, s, io, bt,
                        pl->L, pl->V, pl->Rp, pl->r0, pl->C, ilog2(pl->F), ilog2(pl->Fb), fft,
                        fft2, tw, (int)pl->kp.nimpact, pl->fold ? 1 : 0, scale);
