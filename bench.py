@@ -402,7 +402,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 windows/weights)",
+        "dtype": "f32 (f64 windows)",
         "data": "synthetic",
         "config": {"workload": "collection plane 960 wires x 10 impact x 6000 ticks, 500000 "
                                "track depos, Philox fluctuation, 210x200 response, plain "

@@ -644,10 +644,31 @@ __global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_c
         counters[2] = off_c;
 }
 
-// Weights of one axis computed by one thread into a record: erf at the n + 1
-// bin edges, normalised in FP64 by the window total 1/2 (E_n - E_0).  The
-// edge arguments and the normalisation use one FP64 reciprocal each instead
-// of a division per bin (a few ulp in FP64, far below the float32 weights).
+// Weights of one axis computed by one thread into a record: the Gaussian's
+// integral over each bin, normalised by the window total.  The edge arguments
+// x_k = (lo + k - mu) / (sqrt(2) s) are formed in FP64; the integrals come from
+// the float32 complementary error function of |x_k|, c_k = erfc(|x_k|), with
+// erf(x) = sign(x) (1 - c): a bin on one side of the centre is the difference
+// c_a - c_b of two tail values (no cancellation of values near 1, so every
+// weight keeps a few-ulp relative error, tails included), a bin holding the
+// centre is 2 - c_a - c_b.
+__device__ __forceinline__ float edge_tail(int lo, int k, double mu, double inv, bool &neg)
+{
+    const float x = (float)(((double)(lo + k) - mu) * inv);
+    neg = x < 0.0f;
+    return erfcf(fabsf(x));
+}
+
+__device__ __forceinline__ float bin_integral(float ca, bool na, float cb, bool nb)
+{
+    // erf(b) - erf(a) for edges a < b
+    if (!na)
+        return ca - cb;
+    if (nb)
+        return cb - ca;
+    return (2.0f - ca) - cb;
+}
+
 __device__ __forceinline__ void thread_axis_weights(int lo, int n, double mu, double s, float *W)
 {
     if (s == 0.0) {
@@ -655,12 +676,17 @@ __device__ __forceinline__ void thread_axis_weights(int lo, int n, double mu, do
         return;
     }
     const double inv = 1.0 / (kSqrt2 * s);
-    double e_lo = erf(((double)lo - mu) * inv);
-    const double half_over_sum = 1.0 / (erf(((double)(lo + n) - mu) * inv) - e_lo);
+    bool n0, nn;
+    float c_lo = edge_tail(lo, 0, mu, inv, n0);
+    const float c_n = edge_tail(lo, n, mu, inv, nn);
+    const float rtot = 1.0f / bin_integral(c_lo, n0, c_n, nn);
+    bool n_lo = n0;
     for (int i = 0; i < n; ++i) {
-        const double e_hi = erf(((double)(lo + i + 1) - mu) * inv);
-        W[i] = (float)((e_hi - e_lo) * half_over_sum);
-        e_lo = e_hi;
+        bool n_hi;
+        const float c_hi = edge_tail(lo, i + 1, mu, inv, n_hi);
+        W[i] = bin_integral(c_lo, n_lo, c_hi, n_hi) * rtot;
+        c_lo = c_hi;
+        n_lo = n_hi;
     }
 }
 
