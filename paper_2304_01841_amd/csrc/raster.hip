@@ -909,54 +909,49 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
             next = records[(int64_t)(k + 1) * kRecWords + lane];
         const PatchHdr h = patch_header(cur);
 
+        // nb = (row, quad) passes of this patch (uniform): passes b >= nb are
+        // skipped whole, with no zero-filled values to sum, scale or deposit
+        const int nb = (h.items + 63) >> 6;
         float F[kFluctItems][4];
         int cell[kFluctItems];
-#pragma unroll
-        for (int b = 0; b < kFluctItems; ++b) {
-            cell[b] = -1;
-#pragma unroll
-            for (int mm = 0; mm < 4; ++mm)
-                F[b][mm] = 0.0f;
-        }
         if (P.fluct) {
-#pragma unroll
-            for (int b = 0; b < kFluctItems; ++b)
-                if (64 * b < h.items)  // uniform
-                    patch_item<RP, RT, true>(h, lane + 64 * b, cur_bits, p0, c0, P.key0,
-                                             P.key1, E.event, F[b], cell[b]);
-            // renormalise the patch to its charge
             float acc = 0.0f;
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b)
-#pragma unroll
-                for (int mm = 0; mm < 4; ++mm)
-                    acc += F[b][mm];
+                if (b < nb) {
+                    patch_item<RP, RT, true>(h, lane + 64 * b, cur_bits, p0, c0, P.key0,
+                                             P.key1, E.event, F[b], cell[b]);
+                    acc += (F[b][0] + F[b][1]) + (F[b][2] + F[b][3]);
+                }
+            // renormalise the patch to its charge (a uniform factor: the
+            // hardware reciprocal, within an ulp of the quotient)
             const float S = wave_sum_uniform(acc);
             if (S > 0.0f) {
-                const float scale = h.q / S;
+                const float scale = h.q * __builtin_amdgcn_rcpf(S);
 #pragma unroll
                 for (int b = 0; b < kFluctItems; ++b)
+                    if (b < nb)
 #pragma unroll
-                    for (int mm = 0; mm < 4; ++mm)
-                        F[b][mm] *= scale;
+                        for (int mm = 0; mm < 4; ++mm)
+                            F[b][mm] *= scale;
             } else {
                 // every fluctuated bin is zero: deposit the mean
 #pragma unroll
                 for (int b = 0; b < kFluctItems; ++b)
-                    if (64 * b < h.items)
+                    if (b < nb)
                         patch_item<RP, RT, false>(h, lane + 64 * b, cur_bits, p0, c0, 0, 0, 0,
                                                   F[b], cell[b]);
             }
         } else {
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b)
-                if (64 * b < h.items)
+                if (b < nb)
                     patch_item<RP, RT, false>(h, lane + 64 * b, cur_bits, p0, c0, 0, 0, 0,
                                               F[b], cell[b]);
         }
 #pragma unroll
         for (int b = 0; b < kFluctItems; ++b) {
-            if (64 * b < h.items && cell[b] >= 0) {
+            if (b < nb && cell[b] >= 0) {
                 float4 a4 = acc4[cell[b]];
                 a4.x += F[b][0];
                 a4.y += F[b][1];
