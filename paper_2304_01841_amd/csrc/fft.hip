@@ -262,6 +262,15 @@ struct FftRt {
 // in flight together, with no separate copy into LDS.  With GSTORE it hands its
 // outputs to store(s, n, value) instead of writing LDS; the caller then
 // synchronises before LDS is used again.
+// A store functor with a prefetch(s, n) member takes, besides the value, an
+// operand it named in advance (a response-spectrum factor): the last pass
+// issues those loads right after its read barrier, so that they are in
+// flight during the butterflies instead of after them.
+template <class S, class = void>
+struct HasPrefetch : std::false_type {};
+template <class S>
+struct HasPrefetch<S, std::void_t<decltype(&S::prefetch)>> : std::true_type {};
+
 template <int N, int R, int P, int NSS, int SS, int ES, int NT, bool GLOAD, bool GSTORE,
           class Load, class Store>
 __device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab, Load &load, Store &store)
@@ -307,6 +316,22 @@ __device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab, Load &lo
     }
     if constexpr (!GLOAD)
         __syncthreads();  // every input is read before any output lands in LDS
+    constexpr bool kPre = GSTORE && HasPrefetch<Store>::value;
+    float2 pre[kPre ? MAXB : 1][kPre ? R : 1];
+    if constexpr (kPre) {
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b) {
+            const int g = tid + b * NT;
+            if ((TOTAL % NT) == 0 || g < TOTAL) {
+                const int s = g & MASK, i = g >> NSS;
+                const int k = (P == 1) ? 0 : i % P;
+                const int n0 = (i - k) * R + k;
+#pragma unroll
+                for (int t = 0; t < R; ++t)
+                    pre[b][t] = store.prefetch(s, n0 + t * P);
+            }
+        }
+    }
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
         const int g = tid + b * NT;
@@ -319,7 +344,9 @@ __device__ __forceinline__ void ct_pass(float2 *buf, const float2 *tab, Load &lo
             const int n0 = (i - k) * R + k;
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-                if constexpr (GSTORE)
+                if constexpr (kPre)
+                    store(s, n0 + t * P, v[b][t], pre[b][t]);
+                else if constexpr (GSTORE)
                     store(s, n0 + t * P, v[b][t]);
                 else
                     buf[s * SS + (n0 + t * P) * ES] = v[b][t];
@@ -624,6 +651,28 @@ struct PitchIo {
     int nrows_out, nblocks, mode;
 };
 
+// Last forward pass of a pitch block: the value times the resident response
+// spectrum (conjugated when the inverse runs as a forward transform), into LDS.
+template <bool CONJ>
+struct KMulStore {
+    float2 *lds;
+    const float2 *Kc;
+    int F_shift, Fb_shift;
+    __device__ __forceinline__ float2 prefetch(int s, int n) const
+    {
+        return Kc[(n << F_shift) + s];
+    }
+    __device__ __forceinline__ void operator()(int s, int n, float2 v, float2 k) const
+    {
+        const float2 r = cmul(v, k);
+        lds[(n << Fb_shift) + s] = CONJ ? conjf2(r) : r;
+    }
+    __device__ __forceinline__ void operator()(int s, int n, float2 v) const
+    {
+        (*this)(s, n, v, prefetch(s, n));
+    }
+};
+
 template <class FFT, class FFT2, bool BATCH>
 __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, BatchTables bt, int L,
                                                                 int V, int Rp, int r0, int C,
@@ -696,9 +745,7 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
     float2 *dst = Y + ((int64_t)c * nrows_out << F_shift) + col0;
     if (fold) {
         // forward transform times the response spectrum, then the fold
-        fft.run_io(lds, tabL, load, [&](int s, int n, float2 v) {
-            lds[(n << Fb_shift) + s] = cmul(v, Kc[(n << F_shift) + s]);
-        });
+        fft.run_io(lds, tabL, load, KMulStore<false>{lds, Kc, F_shift, Fb_shift});
         __syncthreads();
         for (int t = threadIdx.x; t < (L10 << Fb_shift); t += blockDim.x) {
             const int kp = t >> Fb_shift, s = t & ((1 << Fb_shift) - 1);
@@ -725,9 +772,7 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
     }
     // forward transform; its last pass multiplies by the response spectrum and
     // conjugates (the inverse runs as a forward transform of the conjugate)
-    fft.run_io(lds, tabL, load, [&](int s, int n, float2 v) {
-        lds[(n << Fb_shift) + s] = conjf2(cmul(v, Kc[(n << F_shift) + s]));
-    });
+    fft.run_io(lds, tabL, load, KMulStore<true>{lds, Kc, F_shift, Fb_shift});
     __syncthreads();
     // inverse; its last pass writes the block's valid rows
     fft.run_io(lds, tabL, InLds{}, [&](int s, int n, float2 v) {
