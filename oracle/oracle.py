@@ -56,6 +56,9 @@ def _load():
         lib.oracle_philox_batch.argtypes = [i64, P, P, P]
         lib.oracle_normal.argtypes = [i64, i64, i64, u64, u64, i32]
         lib.oracle_normal.restype = ctypes.c_double
+        lib.oracle_surviving_charge.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                i32, i64, u64, u64, i32]
+        lib.oracle_surviving_charge.restype = ctypes.c_double
         lib.oracle_depo_window.argtypes = [P, P, P, P, P, P]
         lib.oracle_depo_window.restype = ctypes.c_int
         lib.oracle_axis_weights.argtypes = [i64, i64, ctypes.c_double, ctypes.c_double, P]
@@ -76,7 +79,8 @@ def _ptr(a: np.ndarray):
 # Problem description helpers (plain dictionaries, same fields as the C ABI)
 # ---------------------------------------------------------------------------
 def _phys_arr(phys: dict) -> np.ndarray:
-    return np.array([phys["drift_speed"], phys["DL"], phys["DT"], phys["nsigma"]], dtype=np.float64)
+    return np.array([phys["drift_speed"], phys["DL"], phys["DT"], phys["nsigma"],
+                     phys.get("lifetime", 0.0)], dtype=np.float64)
 
 
 def _geom_arr(plane: dict) -> np.ndarray:
@@ -109,6 +113,14 @@ def philox4x32_10(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
 def normal(I: int, J: int, d: int, event_id: int, seed: int, plane_id: int) -> float:
     """Standard normal deviate that fluctuates absolute bin (I, J) of depo d."""
     return _load().oracle_normal(I, J, d, event_id & (2**64 - 1), seed & (2**64 - 1), plane_id)
+
+
+def surviving_charge(q: float, T: float, tau: float, fluctuate: bool, d: int, event_id: int,
+                     seed: int, plane_id: int) -> float:
+    """Electrons of a depo that survive drift time T with electron lifetime
+    tau (0: no absorption); see oracle_surviving_charge."""
+    return _load().oracle_surviving_charge(q, T, tau, int(bool(fluctuate)), d,
+                                           event_id & (2**64 - 1), seed & (2**64 - 1), plane_id)
 
 
 # ---------------------------------------------------------------------------

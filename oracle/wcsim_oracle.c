@@ -70,8 +70,8 @@ void oracle_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, ui
 /* ------------------------------------------------------------------------ */
 /* Problem description, passed as flat arrays so that ctypes needs no        */
 /* structure layout.                                                          */
-/*   phys[4]  = { drift speed v (mm/us), D_L (mm^2/us), D_T (mm^2/us),        */
-/*                nsigma }                                                    */
+/*   phys[5]  = { drift speed v (mm/us), D_L (mm^2/us), D_T (mm^2/us),        */
+/*                nsigma, electron lifetime tau (us; 0: no absorption) }      */
 /*   geom[7]  = { wire pitch (mm), tick (us), t0 (us), plane_x (mm),          */
 /*                dir_y, dir_z (unit pitch direction), pitch_origin (mm) }    */
 /*   dims[4]  = { plane_id, nwires, nimpact, nticks }                         */
@@ -80,6 +80,7 @@ void oracle_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, ui
 enum { ORACLE_OK = 0, ORACLE_INVALID = 1, ORACLE_EMPTY = 2 };
 
 typedef struct {
+    double T;                     /* drift time to the response plane (us)  */
     double mu_p, s_p, mu_t, s_t;  /* bin coordinates and widths (bin units)  */
     int64_t lo_p, lo_t;           /* first bin of the window, per axis       */
     int64_t n_p, n_t;             /* window lengths                           */
@@ -109,6 +110,7 @@ static int depo_window(const double *d, const double *phys, const double *geom,
     double L = x - plane_x;
     double T = L / v;
     double t_arr = t + T;
+    w->T = T;
     double sigma_p = sqrt(2.0 * DT * T);
     double sigma_t = sqrt(2.0 * DL * T) / v;
 
@@ -189,6 +191,35 @@ double oracle_normal(int64_t I, int64_t J, int64_t d, uint64_t event_id, uint64_
     return (m % 2 == 0) ? rho * cos(theta) : rho * sin(theta);
 }
 
+/* Electrons of a depo that survive the drift (an extension beyond the paper,
+ * which starts from the drifted charge): with electron lifetime tau > 0 each
+ * electron survives the drift time T with probability p = exp(-T / tau).
+ * Without fluctuation the depo keeps its mean, q p; with fluctuation the
+ * count is the normal approximation of Binomial(q, p), clamped at zero, its
+ * deviate drawn from Philox4x32-10 under the plane's key at counter
+ * (2^31, 0, depo index in the event, event id low word) -- a counter word 0
+ * that no bin draw uses (bin quads of windows that reach the grid are small
+ * non-negative numbers or, as unsigned words, within 2^10 of 2^32) -- through
+ * the cosine branch of the Box-Muller transform of output words 0 and 1. */
+double oracle_surviving_charge(double q, double T, double tau, int32_t fluctuate, int64_t d,
+                               uint64_t event_id, uint64_t seed, int32_t plane_id)
+{
+    if (!(tau > 0.0))
+        return q;
+    double p = exp(-T / tau);
+    if (!fluctuate)
+        return q * p;
+    uint32_t ctr[4] = {0x80000000u, 0u, (uint32_t)d, (uint32_t)event_id};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)plane_id};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    double ua = ((double)(r[0] >> 9) + 0.5) * 0x1p-23;
+    double ub = ((double)(r[1] >> 9) + 0.5) * 0x1p-23;
+    double z = sqrt(-2.0 * log(ua)) * cos(2.0 * M_PI * ub);
+    double F = q * p + z * sqrt(q * p * (1.0 - p));
+    return (F < 0.0) ? 0.0 : F;
+}
+
 /* Window of one depo, exposed for the tests.  out_d[4] = {mu_p, s_p, mu_t,
  * s_t}, out_i[4] = {lo_p, lo_t, n_p, n_t}.  Returns the status code. */
 int oracle_depo_window(const double *depo, const double *phys, const double *geom,
@@ -213,6 +244,8 @@ void oracle_axis_weights(int64_t lo, int64_t n, double mu, double s, double *W)
  *   exclusive prefix sum of n_p n_t (invalid or empty depos get n_p = n_t = 0).
  *   values[offset + i n_t + j] = charge in absolute bin (lo_p + i, lo_t + j).
  *   status[d] = 0 ok, 1 invalid, 2 empty.
+ * q is the charge that survives the drift (oracle_surviving_charge; the
+ * depo's own charge when the lifetime is 0).
  * Without fluctuation a patch is q W_p[i] W_t[j].  With fluctuation each bin
  * takes the normal approximation of a binomial draw of the q electrons with
  * probability p = W_p W_t, clamped at zero, and the patch is rescaled so that
@@ -249,7 +282,8 @@ int64_t oracle_rasterize(const double *depos, int64_t n, const double *phys, int
             continue;
         oracle_window w;
         depo_window(depos + 5 * d, phys, geom, dims, &w);
-        const double q = depos[5 * d + 4];
+        const double q = oracle_surviving_charge(depos[5 * d + 4], w.T, phys[4], fluctuate,
+                                                 ids ? ids[d] : d, event_id, seed, plane_id);
         double *Wp = (double *)malloc(sizeof(double) * (size_t)n_p);
         double *Wt = (double *)malloc(sizeof(double) * (size_t)n_t);
         axis_weights(w.lo_p, n_p, w.mu_p, w.s_p, Wp);

@@ -436,3 +436,60 @@ def test_grid_of_a_partition_with_event_indices():
     # keyed by positions in the part instead, the fluctuations differ
     idx = np.arange(0, d.shape[0], 3)
     assert np.abs(O.grid(d[idx], ph, pl, 3) - O.grid(d[idx], ph, pl, 3, ids=idx)).max() > 0
+
+
+# ---------------------------------------------------------------------------
+# Electron lifetime (an extension beyond the paper: attachment during drift)
+# ---------------------------------------------------------------------------
+def _with_lifetime(phys: dict, tau: float) -> dict:
+    ph = dict(phys)
+    ph["lifetime"] = tau
+    return ph
+
+
+def test_lifetime_mean_charge_closed_form():
+    """Without fluctuation every patch integrates to q exp(-T / tau), T the
+    drift time (x - plane_x) / v written out here; lifetime 0 is no
+    absorption at all."""
+    rng = np.random.default_rng(41)
+    pl = _plane(nw=60, nt=2000)
+    dep = W.uniform_depos(rng, 400, (20.0, 280.0), (30.0, 900.0))
+    tau = 1800.0
+    ph0 = W.physics(False)
+    meta, vals, st = O.rasterize(dep, _with_lifetime(ph0, tau), pl)
+    meta0, vals0, _ = O.rasterize(dep, ph0, pl)
+    assert (st == 0).all() and np.array_equal(meta, meta0)
+    T = (dep[:, 0] - pl["plane_x"]) / ph0["drift_speed"]
+    for d in range(0, 400, 7):
+        o, n = meta[d, 4], meta[d, 2] * meta[d, 3]
+        assert vals[o:o + n].sum() == pytest.approx(dep[d, 4] * math.exp(-T[d] / tau), rel=1e-12)
+        # absorption scales the patch, its shape is the unabsorbed one
+        assert np.allclose(vals[o:o + n] * math.exp(T[d] / tau), vals0[o:o + n], rtol=1e-12)
+    _, vals_off, _ = O.rasterize(dep, _with_lifetime(ph0, 0.0), pl)
+    assert np.array_equal(vals_off, vals0)
+
+
+def test_lifetime_binomial_loss_statistics():
+    """With fluctuation the surviving count of q electrons at survival
+    probability p has mean q p and variance q p (1 - p) across depos (each
+    depo draws its own deviate), is never negative, and the depo's patch
+    integrates to exactly that count."""
+    ph = _with_lifetime(W.physics(True), 1000.0)
+    pl = _plane()
+    n, q = 4000, 3000.0
+    x = 1.6 * 700.0  # T = 700 us: p = exp(-0.7)
+    dep = np.tile(np.array([[x, 0.0, 100.1, -700.0 + 60.2, q]]), (n, 1))
+    meta, vals, st = O.rasterize(dep, ph, pl, event_id=9)
+    assert (st == 0).all() and (vals >= 0).all()
+    sums = np.array([vals[meta[d, 4]:meta[d, 4] + meta[d, 2] * meta[d, 3]].sum() for d in range(n)])
+    p = math.exp(-0.7)
+    for d in range(0, n, 131):
+        ref = O.surviving_charge(q, 700.0, 1000.0, True, d, 9, ph["seed"], pl["plane_id"])
+        assert sums[d] == pytest.approx(ref, rel=1e-12)
+    sd = math.sqrt(q * p * (1 - p))
+    assert abs(sums.mean() - q * p) < 4.5 * sd / math.sqrt(n)
+    assert 0.9 < sums.var() / (q * p * (1 - p)) < 1.1
+    # the deviate differs between depos and between events
+    assert len(np.unique(np.round(sums, 6))) > 0.9 * n
+    meta2, vals2, _ = O.rasterize(dep[:1], ph, pl, event_id=10)
+    assert vals2.sum() != pytest.approx(sums[0], rel=1e-9)
