@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--schedule", type=str, default=None, metavar="K=V[,K=V]",
                     help="fixed schedule of the benchmark plane (no tuning), e.g. "
                          "fft_pitch=640,freq_chunk=16 (or the same as a JSON object)")
+    ap.add_argument("--lifetime", type=float, default=0.0, metavar="US",
+                    help="electron lifetime of the benchmark plane (an extension beyond the "
+                         "paper; 0, the default, is the paper's workload without absorption)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a plain copy kernel "
                          "whose HBM counters scale the kernels' FETCH_SIZE / WRITE_SIZE)")
@@ -295,6 +298,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = W.collection()
+    if args.lifetime:
+        w["phys"] = dict(w["phys"], lifetime=args.lifetime)
     pl, R = w["planes"][0], w["responses"][0]
     kind = wcsim.OUT_WIRE if args.kind == "wire" else wcsim.OUT_PITCH
     dep = torch.from_numpy(w["depos"]).to(dev)
@@ -406,7 +411,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "collection plane 960 wires x 10 impact x 6000 ticks, 500000 "
                                "track depos, Philox fluctuation, 210x200 response, plain "
-                               "per-event launch, %s output" % args.kind,
+                               "per-event launch, %s output%s" % (
+                                   args.kind, ", electron lifetime %g us" % args.lifetime
+                                   if args.lifetime else ""),
                    "global_batch": 1, "depos_per_event": n,
                    "fft_ticks": P.info["fft_ticks"], "fft_pitch": P.info["fft_pitch"],
                    "freq_chunk": P.info["freq_chunk"], "tile": P.info["tile"],

@@ -73,6 +73,12 @@ typedef struct {
     int32_t fluctuate;  /* 0: mean patch; 1: binomial fluctuation */
     int32_t reserved;   /* must be 0 */
     uint64_t seed;      /* Philox key (mixed with plane_id) */
+    double lifetime;    /* electron lifetime tau, us, >= 0; 0: no absorption.  An
+                         * extension beyond the paper, which starts from the drifted
+                         * charge: each electron survives the drift time T with
+                         * probability exp(-T / tau); the depo keeps the mean q p,
+                         * or with fluctuation a normal-approximated binomial count
+                         * drawn from Philox at counter (2^31, 0, depo, event). */
 } wcsim_physics;
 
 /* Plane geometry and response (Sec. 2 steps 2-3).  The grid has

@@ -82,8 +82,10 @@ wcsim_status validate_plane(const wcsim_plane_desc *d, const wcsim_physics *ph)
     for (int64_t i = 0; i < (int64_t)d->resp_npitch * d->resp_nticks; ++i)
         if (!std::isfinite(d->response[i]))
             return fail(WCSIM_E_INVALID, "non-finite response value");
-    if (!finite_all({ph->drift_speed, ph->DL, ph->DT, ph->nsigma}))
+    if (!finite_all({ph->drift_speed, ph->DL, ph->DT, ph->nsigma, ph->lifetime}))
         return fail(WCSIM_E_INVALID, "non-finite physics constant");
+    if (ph->lifetime < 0.0)
+        return fail(WCSIM_E_INVALID, "lifetime must be >= 0");
     if (!(ph->drift_speed > 0.0) || ph->DL < 0.0 || ph->DT < 0.0 || ph->nsigma < 0.0)
         return fail(WCSIM_E_INVALID, "drift speed must be > 0 and DL, DT, nsigma >= 0");
     if (ph->fluctuate != 0 && ph->fluctuate != 1)
@@ -245,6 +247,7 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     k.key1 = (uint32_t)(phys->seed >> 32) ^ (uint32_t)desc->plane_id;
     k.fluct = phys->fluctuate;
     k.pad_ = 0;
+    k.tau = phys->lifetime;
     if ((st = choose_schedule(pl, sched)) != WCSIM_OK) {
         free_plane(pl);
         return st;

@@ -73,6 +73,7 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &zc, fl
 }
 
 struct Win {
+    double T;  // drift time to the response plane
     double mu_p, s_p, mu_t, s_t, q;
     int lo_p, lo_t, n_p, n_t;
     int status;  // 0 ok, 1 invalid, 2 misses the grid, 3 window too long
@@ -85,6 +86,7 @@ __device__ __forceinline__ Win depo_window(const wcsim_depo &dep, const PlanePar
 {
 #pragma clang fp contract(off)
     Win w;
+    w.T = 0.0;
     w.status = 0;
     w.lo_p = w.lo_t = w.n_p = w.n_t = 0;
     const double x = dep.x, y = dep.y, z = dep.z, t = dep.t, q = dep.q;
@@ -97,6 +99,7 @@ __device__ __forceinline__ Win depo_window(const wcsim_depo &dep, const PlanePar
     }
     const double L = x - P.plane_x;
     const double T = L / P.v;
+    w.T = T;
     const double t_arr = t + T;
     const double sigma_p = sqrt(2.0 * P.DT * T);
     const double sigma_t = sqrt(2.0 * P.DL * T) / P.v;
@@ -166,6 +169,30 @@ __device__ __forceinline__ float wave_sum_uniform(float v)
     const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
     const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
     return (r0 + r1) + (r2 + r3);
+}
+
+// Electrons of a depo that survive the drift (electron lifetime tau; an
+// extension beyond the paper, which starts from the drifted charge): each
+// survives the drift time T with probability p = exp(-T / tau).  The depo
+// keeps q p, or with fluctuation the normal approximation of Binomial(q, p),
+// clamped at zero, whose deviate comes from Philox under the plane's key at
+// counter (2^31, 0, depo index in the event, event) -- a word 0 that no bin
+// draw uses -- through the cosine branch of Box-Muller on words 0 and 1, all
+// in FP64 (one draw per depo).
+__device__ __forceinline__ double surviving_charge(const Win &w, const PlaneParams &P, int d,
+                                                   uint32_t event)
+{
+    if (!(P.tau > 0.0))
+        return w.q;
+    const double p = exp(-w.T / P.tau);
+    if (!P.fluct)
+        return w.q * p;
+    const uint4 r = philox4x32_10(make_uint4(0x80000000u, 0u, (uint32_t)d, event), P.key0, P.key1);
+    const double ua = ((double)(r.x >> 9) + 0.5) * 0x1p-23;
+    const double ub = ((double)(r.y >> 9) + 0.5) * 0x1p-23;
+    const double z = sqrt(-2.0 * log(ua)) * cospi(2.0 * ub);
+    const double F = w.q * p + z * sqrt(w.q * p * (1.0 - p));
+    return (F < 0.0) ? 0.0 : F;
 }
 
 // Fluctuated bin value before rescaling: normal approximation of the binomial
@@ -379,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables b
             continue;
         block_axis_weights<NT>(w.lo_p, w.n_p, w.mu_p, w.s_p, Wp, E, red);
         block_axis_weights<NT>(w.lo_t, w.n_t, w.mu_t, w.s_t, Wt, E, red);
-        const float qf = (float)w.q;
+        const float qf = (float)surviving_charge(w, P, d, event);
         float *out = FLAT ? values + offsets[d] : nullptr;
         if (!P.fluct) {
             const int cnt = w.n_p * w.n_t;
@@ -530,7 +557,7 @@ __global__ __launch_bounds__(256) void k_prep_bin(EventCtx e0, BatchTables bt, i
         const PlaneParams &P = E.kp;
         const int64_t dl = d - E.depo_base;
         // a batch reserves capacity per event; depos past its count are absent
-        const Win w = (dl < E.n) ? depo_window(E.depos[dl], P) : Win{0, 0, 0, 0, 0, 0, 0, 0, 0, 2};
+        const Win w = (dl < E.n) ? depo_window(E.depos[dl], P) : Win{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 2};
         if (w.status == 1 || w.status == 3) {
             bad = true;
         } else if (w.status == 0) {
@@ -742,7 +769,7 @@ __global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt
         h[kHNp] = w.n_p;
         h[kHNt] = w.n_t;
         h[kHDepo] = (int)d;
-        rec[kHQ] = (float)w.q;
+        rec[kHQ] = (float)surviving_charge(w, E.kp, (int)d, E.event);
         h[kHMq] = magic_small(nq);
         float *Wt = rec + kRecWt;
         for (int k = 0; k < off; ++k)

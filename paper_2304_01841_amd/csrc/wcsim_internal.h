@@ -39,6 +39,7 @@ struct PlaneParams {
     uint32_t key0, key1;  // Philox key: seed low word, seed high word ^ plane_id
     int32_t fluct;
     int32_t pad_;
+    double tau;  // electron lifetime (us), 0: no absorption
 };
 
 // Maximum window length per axis handled anywhere in the library.

@@ -43,7 +43,7 @@ class Physics(ctypes.Structure):
     _fields_ = [("drift_speed", ctypes.c_double), ("DL", ctypes.c_double),
                 ("DT", ctypes.c_double), ("nsigma", ctypes.c_double),
                 ("fluctuate", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("lifetime", ctypes.c_double)]
 
 
 class PlaneDesc(ctypes.Structure):
@@ -146,7 +146,7 @@ def version() -> int:
 def physics_struct(phys: dict) -> Physics:
     return Physics(float(phys["drift_speed"]), float(phys["DL"]), float(phys["DT"]),
                    float(phys["nsigma"]), int(phys["fluctuate"]), 0,
-                   int(phys["seed"]) & (2**64 - 1))
+                   int(phys["seed"]) & (2**64 - 1), float(phys.get("lifetime", 0.0)))
 
 
 def plane_desc_struct(plane: dict, resp: np.ndarray, r0: int) -> PlaneDesc:

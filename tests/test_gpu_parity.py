@@ -265,6 +265,28 @@ def test_simulate_collection_full_size(ws):
     _sim_and_compare(ws, w, kinds=(ws.OUT_WIRE,), schedules=autotune.candidates())
 
 
+def test_lifetime_absorption(ws):
+    """Electron-lifetime absorption (an extension beyond the paper): patch
+    sets, the fused path's grid and the convolved output agree with the
+    oracle with and without fluctuation, on the small workload (drift times
+    up to 2.5 ms against a 1.5 ms lifetime) and on the full collection plane;
+    a negative lifetime is rejected."""
+    log("case: lifetime absorption")
+    w = W.small()
+    for fl in (False, True):
+        ph = W.physics(fl)
+        ph["lifetime"] = 1500.0
+        _compare_patches(ws, w["planes"][0], ph, w["depos"], event_id=4)
+        _sim_and_compare(ws, dict(w, phys=ph), kinds=(ws.OUT_PITCH, ws.OUT_WIRE), event_id=4)
+    ph = W.physics(True)
+    ph["lifetime"] = 3000.0
+    log("  collection plane, full size")
+    _sim_and_compare(ws, dict(W.collection(), phys=ph), kinds=(ws.OUT_WIRE,))
+    ph["lifetime"] = -1.0
+    with pytest.raises(ws.WcsimError):
+        ws.Plane(w["planes"][0], ph, w["responses"][0])
+
+
 def _pitch_bins(depos, pl):
     """Mean pitch bin of each depo (projection of (y, z) on the pitch
     direction); used only to pick a superset of the depos that can reach
