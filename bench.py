@@ -102,11 +102,19 @@ def raster_work(wcsim, P, dep) -> dict:
             "ops": calls * OPS_PER_PHILOX_CALL + bins * OPS_PER_BIN}
 
 
+# Schedule fields that change what each profiled kernel does (the raster
+# kernel depends only on the tile shape, the FFT passes only on their sizes).
+SCHEDULE_FIELDS = {"k_raster_tiles": ("tile",), "k_fill_records": ("tile",),
+                   "k_rows_r2c": ("fft_ticks", "freq_chunk"),
+                   "k_rows_c2r": ("fft_ticks", "freq_chunk"),
+                   "k_pitch_conv": ("fft_ticks", "fft_pitch", "freq_chunk")}
+
+
 def measured_traffic(kernel: str, schedule: dict):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel), or None when
     the kernel's source changed since the counters were taken or they were
-    taken under another schedule."""
+    taken under a schedule that runs the kernel differently."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic_collection.json")
@@ -115,7 +123,9 @@ def measured_traffic(kernel: str, schedule: dict):
     with open(path) as f:
         rec = json.load(f)
     k = rec.get("kernels", {}).get(kernel)
-    if not k or rec.get("schedule") != schedule:
+    taken = rec.get("schedule") or {}
+    fields = SCHEDULE_FIELDS.get(kernel, tuple(schedule))
+    if not k or any(taken.get(f) != schedule.get(f) for f in fields):
         return None
     src = os.path.join(ROOT, k["source"])
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
