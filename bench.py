@@ -293,7 +293,7 @@ def serve_measurement(W, nreq: int, tuner=None) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (events and "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (events and "
               "planes would shard with no communication); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
