@@ -36,10 +36,12 @@ def _events(seed, spec, nticks):
     return out
 
 
-@pytest.mark.parametrize("kind", [0, 1])
-def test_batch_equals_single_and_oracle(ws, kind):
-    print("case: batch vs single, kind %d" % kind, flush=True)
+@pytest.mark.parametrize("kind,tau", [(0, 0.0), (1, 0.0), (0, 1500.0)])
+def test_batch_equals_single_and_oracle(ws, kind, tau):
+    """tau > 0: electron-lifetime absorption, keyed per event as alone."""
+    print("case: batch vs single, kind %d, lifetime %g" % (kind, tau), flush=True)
     phys = W.physics(True)
+    phys["lifetime"] = tau
     R = W.response("bipolar", Rp=41, Rt=40, r0=20)
     evs = _events(77, [(30, 4000), (7, 0), (52, 9000), (12, 300), (30, 2500)], 700)
     planes = [ws.Plane(e["plane"], phys, R, r0=20) for e in evs]
