@@ -124,6 +124,53 @@ def surviving_charge(q: float, T: float, tau: float, fluctuate: bool, d: int, ev
 
 
 # ---------------------------------------------------------------------------
+# Digitisation with white noise (an extension beyond the paper, which ends at
+# the current induced on the wires)
+# ---------------------------------------------------------------------------
+DIGITIZE_KEY_XOR = 0x6E6F6973  # XORed into the seed's low word for the noise stream
+
+
+def digitize_normals(nrows: int, ncols: int, seed: int, event_id: int) -> np.ndarray:
+    """Standard normal per sample (row, col): Philox4x32-10 under the key
+    (seed low word ^ 0x6e6f6973, seed high word) at counter (col // 4, row, 0,
+    event low word); words (0,1) serve columns with col % 4 in {0,1}, words
+    (2,3) the others, each pair through Box-Muller (cosine branch to the even
+    column), the uniform of a word r being ((r >> 9) + 1/2) 2^-23.  FP64."""
+    nq = (ncols + 3) // 4
+    q, r = np.meshgrid(np.arange(nq), np.arange(nrows))
+    ctr = np.stack([q.ravel(), r.ravel(), np.zeros(q.size, np.int64),
+                    np.full(q.size, event_id & 0xFFFFFFFF)], axis=1).astype(np.uint32)
+    key = np.tile(np.array([(seed & 0xFFFFFFFF) ^ DIGITIZE_KEY_XOR, (seed >> 32) & 0xFFFFFFFF],
+                           np.uint32), (q.size, 1))
+    words = philox4x32_10(ctr, key).astype(np.float64).reshape(nrows, nq, 4)
+    u = (np.floor(words / 512.0) + 0.5) * 2.0 ** -23
+    z = np.empty((nrows, nq, 4))
+    for a in (0, 2):
+        rho = np.sqrt(-2.0 * np.log(u[..., a]))
+        theta = 2.0 * np.pi * u[..., a + 1]
+        z[..., a] = rho * np.cos(theta)
+        z[..., a + 1] = rho * np.sin(theta)
+    return z.reshape(nrows, 4 * nq)[:, :ncols]
+
+
+def digitize(wave: np.ndarray, gain: float, pedestal: float, sigma: float, bits: int, seed: int,
+             event_id: int) -> np.ndarray:
+    """ADC codes min(max(rint(((w gain) + pedestal) + sigma z), 0), 2^bits - 1)
+    as uint16, with float32 arithmetic in that order (each operation rounded,
+    no fused multiply-add) and rint rounding half to even."""
+    w = np.asarray(wave, np.float32)
+    f32 = np.float32
+    v = w * f32(gain)
+    v = v + f32(pedestal)
+    if sigma > 0:
+        z = digitize_normals(w.shape[0], w.shape[1], seed, event_id).astype(np.float32)
+        v = v + f32(sigma) * z
+    v = np.rint(v)
+    v = np.minimum(np.maximum(v, f32(0.0)), f32(2 ** bits - 1))
+    return v.astype(np.uint16)
+
+
+# ---------------------------------------------------------------------------
 # Rasterization and Scatter-Add (Sec. 2 steps 1 and 2)
 # ---------------------------------------------------------------------------
 def depo_window(depo, phys: dict, plane: dict):

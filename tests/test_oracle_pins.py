@@ -493,3 +493,36 @@ def test_lifetime_binomial_loss_statistics():
     assert len(np.unique(np.round(sums, 6))) > 0.9 * n
     meta2, vals2, _ = O.rasterize(dep[:1], ph, pl, event_id=10)
     assert vals2.sum() != pytest.approx(sums[0], rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Digitisation with white noise (an extension beyond the paper)
+# ---------------------------------------------------------------------------
+def test_digitize_rounding_and_clamping():
+    """Hand-computed codes: gain 2, pedestal 100, 12 bits; halves round to
+    even, negatives clamp to 0, overflow to 4095."""
+    w = np.array([[0.25, 0.75, 1.0, -0.25, -60.0, 5000.0, 1997.25, 1997.75]], np.float32)
+    got = O.digitize(w, 2.0, 100.0, 0.0, 12, 1, 0)
+    assert got.dtype == np.uint16
+    assert got.tolist() == [[100, 102, 102, 100, 0, 4095, 4094, 4095]]
+    # 1 bit: codes 0 or 1
+    assert O.digitize(np.array([[-1.0, 0.2, 0.9, 7.0]], np.float32), 1.0, 0.0, 0.0, 1, 1,
+                      0).tolist() == [[0, 0, 1, 1]]
+
+
+def test_digitize_noise_statistics_and_keying():
+    """White noise: mean pedestal and standard deviation sqrt(sigma^2 + 1/12)
+    (the rounding adds a uniform error) over 240,000 samples; each sample's
+    deviate is the scalar oracle normal under the noise key; events differ."""
+    nrows, ncols, sigma, seed = 40, 6001, 3.0, 0x1234_5678_9ABC_DEF0
+    codes = O.digitize(np.zeros((nrows, ncols), np.float32), 1.0, 1000.0, sigma, 12, seed, 5)
+    c = codes.astype(np.float64)
+    n = c.size
+    assert abs(c.mean() - 1000.0) < 4.5 * sigma / math.sqrt(n)
+    assert abs(c.std() / math.sqrt(sigma ** 2 + 1.0 / 12.0) - 1.0) < 0.01
+    z = O.digitize_normals(nrows, ncols, seed, 5)
+    for r, col in [(0, 0), (0, 1), (3, 2), (7, 3), (39, 6000), (20, 4097)]:
+        ref = O.normal(r, col, 0, 5, seed ^ O.DIGITIZE_KEY_XOR, 0)
+        assert z[r, col] == pytest.approx(ref, rel=1e-12, abs=1e-12)
+    other = O.digitize(np.zeros((nrows, ncols), np.float32), 1.0, 1000.0, sigma, 12, seed, 6)
+    assert (other != codes).mean() > 0.5
