@@ -216,6 +216,26 @@ def batch_comparison(wcsim, W, dev, nevents: int, tuner=None, rounds: int = 3) -
     return res
 
 
+def digitize_measurement(wcsim, out, reps: int = 20) -> dict:
+    """Digitisation with white noise (an extension beyond the paper) of the
+    benchmark event's output: time per call and HBM rate (4 B read + 2 B
+    written per sample), HIP events on torch's current stream."""
+    import torch
+
+    codes = torch.empty(out.shape, dtype=torch.int16, device=out.device)
+    for _ in range(3):
+        wcsim.digitize(out, 1.0, 2048.0, 3.0, 12, seed=7, event_id=0, out=codes)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for e in range(reps):
+        wcsim.digitize(out, 1.0, 2048.0, 3.0, 12, seed=7, event_id=e, out=codes)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    n = out.numel()
+    return {"samples": int(n), "ms": ms, "hbm_gbs": 6.0 * n / (ms * 1e-3) / 1e9}
+
+
 def three_plane_measurement(wcsim, W, dev, tuner=None, steps: int = 10) -> dict:
     """The three-plane event (U/V/W 800/800/960 wires x 6000 ticks, 2,000,000
     track + 400,000 background depos, fluctuation on, wire output): the three
@@ -394,6 +414,8 @@ def main():
     if not args.no_batch:
         batch = batch_comparison(wcsim, W, dev, args.batch_events, tuner)
 
+    digit = digitize_measurement(wcsim, out)
+
     three = None
     if not args.no_three_plane:
         three = three_plane_measurement(wcsim, W, dev, tuner)
@@ -437,6 +459,7 @@ def main():
         "stage_hbm_gbs": per_stage_hbm,
         "roofline": roofline,
         "three_plane": three,
+        "digitize": digit,
         "batch": batch,
         "serve": served,
         "cpu_baseline": cpu,

@@ -296,6 +296,25 @@ wcsim_status wcsim_batch_run(wcsim_batch *batch, const wcsim_depo *const *depos,
                              void *stream);
 void wcsim_batch_destroy(wcsim_batch *batch);
 
+/* Digitisation with white noise: an extension beyond the paper, which ends at
+ * the current induced on the wires (Sec. 2).  Each sample w of a waveform
+ * `wave` [nrows][ncols] float32 (device memory; e.g. a simulate_event output)
+ * becomes the ADC code
+ *   adc = min(max(rint(((w * gain) + pedestal) + sigma * z), 0), 2^bits - 1)
+ * stored as uint16 in `adc` [nrows][ncols] (device memory, caller-owned).  The
+ * arithmetic is float32 in exactly that order with no fused multiply-add,
+ * rint rounds half to even.  z is a standard normal deviate per sample (white
+ * noise of sigma ADC counts; sigma = 0: none) from Philox4x32-10 under the key
+ * (seed low word XOR 0x6e6f6973, seed high word) at counter (floor(col / 4),
+ * row, 0, event_id low word): one call serves four consecutive columns, words
+ * (0,1) the columns with col mod 4 in {0,1} and words (2,3) the others, each
+ * pair through Box-Muller with the cosine branch to the even column.
+ * Requires nrows, ncols >= 0, 1 <= bits <= 16, finite gain and pedestal,
+ * finite sigma >= 0; otherwise WCSIM_E_INVALID.  Asynchronous on `stream`. */
+wcsim_status wcsim_digitize(const float *wave, int64_t nrows, int64_t ncols, float gain,
+                            float pedestal, float sigma, int32_t bits, uint64_t seed,
+                            uint64_t event_id, uint16_t *adc, void *stream);
+
 /* Diagnostic: the Philox4x32-10 generator the fluctuation uses (Sec. 4.1,
  * random123), evaluated on the GPU: out[i] = Philox4x32-10(ctr[i], key[i]).
  * ctr/out: n x 4 uint32, key: n x 2 uint32, all device memory. */

@@ -1068,6 +1068,51 @@ hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+// One thread per four consecutive samples of a row (one Philox call).
+__global__ __launch_bounds__(256) void k_digitize(const float *__restrict__ wave, int64_t nrows,
+                                                  int64_t ncols, float gain, float pedestal,
+                                                  float sigma, float top, uint32_t k0, uint32_t k1,
+                                                  uint32_t event, uint16_t *__restrict__ adc)
+{
+#pragma clang fp contract(off)
+    const int64_t nq = (ncols + 3) / 4;
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nrows * nq)
+        return;
+    const int64_t row = g / nq, q = g - row * nq;
+    float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (sigma > 0.0f) {
+        const uint4 r = philox4x32_10(make_uint4((uint32_t)q, (uint32_t)row, 0u, event), k0, k1);
+        box_muller(r.x, r.y, z[0], z[1]);
+        box_muller(r.z, r.w, z[2], z[3]);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int64_t col = 4 * q + m;
+        if (col < ncols) {
+            const int64_t i = row * ncols + col;
+            float v = wave[i] * gain;
+            v = v + pedestal;
+            v = v + sigma * z[m];
+            v = fminf(fmaxf(rintf(v), 0.0f), top);
+            adc[i] = (uint16_t)v;
+        }
+    }
+}
+
+hipError_t launch_digitize(const float *wave, int64_t nrows, int64_t ncols, float gain,
+                           float pedestal, float sigma, int bits, uint64_t seed, uint32_t event,
+                           uint16_t *adc, hipStream_t s)
+{
+    const int64_t n = nrows * ((ncols + 3) / 4);
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_digitize, dim3(blocks_for(n, 256)), dim3(256), 0, s, wave, nrows, ncols,
+                       gain, pedestal, sigma, (float)((1 << bits) - 1),
+                       (uint32_t)seed ^ 0x6e6f6973u, (uint32_t)(seed >> 32), event, adc);
+    return hipGetLastError();
+}
+
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
                          hipStream_t s)
 {

@@ -107,6 +107,8 @@ _SIGS = {
     "wcsim_batch_run": (_st, [_P, _P, _P, _P, _P, _P]),
     "wcsim_batch_destroy": (None, [_P]),
     "wcsim_philox4x32_10": (_st, [_P, _P, _i64, _P, _P]),
+    "wcsim_digitize": (_st, [_P, _i64, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i32,
+                             _u64, _u64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -468,6 +470,25 @@ class Batch:
             self.destroy()
         except Exception:
             pass
+
+
+def digitize(wave: torch.Tensor, gain: float, pedestal: float, sigma: float = 0.0, bits: int = 12,
+             seed: int = 0, event_id: int = 0, out: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+    """ADC codes of a [nrows, ncols] float32 device waveform (wcsim_digitize):
+    uint16 codes returned as an int16 tensor of the same bit patterns."""
+    if wave.dim() != 2:
+        raise ValueError("wave must be [nrows, ncols]")
+    nrows, ncols = wave.shape
+    if out is None:
+        out = torch.empty((nrows, ncols), dtype=torch.int16, device=wave.device)
+    elif tuple(out.shape) != (nrows, ncols):
+        raise ValueError("out must be [nrows, ncols]")
+    _check(_lib.wcsim_digitize(_dev_ptr(wave, torch.float32, "wave"), nrows, ncols, float(gain),
+                               float(pedestal), float(sigma), int(bits),
+                               int(seed) & (2**64 - 1), int(event_id) & (2**64 - 1),
+                               _dev_ptr(out, torch.int16, "out"), _stream(stream)))
+    return out
 
 
 def philox4x32_10(ctr: torch.Tensor, key: torch.Tensor, stream=None) -> torch.Tensor:

@@ -373,3 +373,64 @@ def test_simulate_long_windows_use_generic_path(ws):
     phys["DL"] *= 30
     w = dict(planes=[pl], responses=[W.response("bipolar")], depos=dep, phys=phys, event_id=2)
     _sim_and_compare(ws, w)
+
+
+# ---------------------------------------------------------------------------
+# Digitisation with white noise (an extension beyond the paper)
+# ---------------------------------------------------------------------------
+def _digitize_wave(rng, nrows, ncols):
+    """Seeded float32 waveform spanning negative values, exact halves after
+    the gain, and values past the top code."""
+    w = rng.normal(0.0, 600.0, (nrows, ncols)).astype(np.float32)
+    w[:, ::7] = (np.rint(w[:, ::7]) + 0.25).astype(np.float32)  # x 2 + 100: exact .5
+    edge = np.array([-1e6, 1e6, 0.25, 0.75, 1997.75], np.float32)[:ncols]
+    w[0, :edge.size] = edge
+    return w
+
+
+def test_digitize_bit_exact_without_noise(ws):
+    """Codes of a seeded waveform (ragged sizes) equal the oracle's exactly,
+    including halves and both clamps; empty input is a no-op and bad
+    parameters are rejected."""
+    log("case: digitize without noise")
+    rng = np.random.default_rng(23)
+    for nrows, ncols in [(7, 1001), (96, 6000), (1, 3)]:
+        w = _digitize_wave(rng, nrows, ncols)
+        got = ws.digitize(torch.from_numpy(w).cuda(), 2.0, 100.0, 0.0, 12).cpu().numpy()
+        ref = O.digitize(w, 2.0, 100.0, 0.0, 12, 0, 0)
+        assert np.array_equal(got.view(np.uint16), ref), (nrows, ncols)
+    empty = torch.zeros((0, 5), dtype=torch.float32, device="cuda")
+    assert ws.digitize(empty, 1.0, 0.0).shape == (0, 5)
+    w = torch.zeros((2, 2), dtype=torch.float32, device="cuda")
+    for bad in [dict(bits=0), dict(bits=17), dict(sigma=-1.0), dict(gain=float("nan"))]:
+        kw = dict(gain=1.0, pedestal=0.0, sigma=0.0, bits=12)
+        kw.update(bad)
+        with pytest.raises(ws.WcsimError):
+            ws.digitize(w, **kw)
+
+
+def test_digitize_with_noise_and_simulated_output(ws):
+    """With white noise the codes differ from the oracle's by at most one (the
+    float32 Box-Muller of the GPU and the FP64 one of the oracle differ by an
+    ulp, which can move a sample across a rounding boundary) and almost never;
+    the digitised simulate output agrees with the digitised oracle output to
+    one code."""
+    log("case: digitize with noise")
+    rng = np.random.default_rng(29)
+    w = _digitize_wave(rng, 64, 3001)
+    seed = 0x0123_4567_89AB_CDEF
+    got = ws.digitize(torch.from_numpy(w).cuda(), 1.5, 800.0, 2.5, 14, seed, 11).cpu().numpy()
+    ref = O.digitize(w, 1.5, 800.0, 2.5, 14, seed, 11)
+    d = np.abs(got.view(np.uint16).astype(np.int64) - ref.astype(np.int64))
+    assert d.max() <= 1 and (d == 0).mean() > 0.999
+    wk = W.small()
+    pl, R = wk["planes"][0], wk["responses"][0]
+    P = ws.Plane(pl, wk["phys"], R)
+    out = ws.simulate_event(P, torch.from_numpy(wk["depos"]).cuda(), wk["event_id"])
+    full = O.convolve(O.grid(wk["depos"], wk["phys"], pl, wk["event_id"]), R.astype(float),
+                      R.shape[0] // 2)
+    oref = O.wire_rows(full, pl["nimpact"])
+    gain = 1500.0 / np.abs(oref).max()
+    got = ws.digitize(out, gain, 2048.0, 0.0, 12).cpu().numpy().view(np.uint16)
+    ref = O.digitize(oref.astype(np.float32), gain, 2048.0, 0.0, 12, 0, 0)
+    assert np.abs(got.astype(np.int64) - ref.astype(np.int64)).max() <= 1
