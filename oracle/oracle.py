@@ -123,6 +123,17 @@ def surviving_charge(q: float, T: float, tau: float, fluctuate: bool, d: int, ev
                                            event_id & (2**64 - 1), seed & (2**64 - 1), plane_id)
 
 
+def combined_response(R: np.ndarray, E) -> np.ndarray:
+    """Detector response followed by an electronics response along ticks (an
+    extension beyond the paper): each response row convolved with E, FP64,
+    Rp x (Rt + len(E) - 1); E empty or None leaves R unchanged."""
+    R = np.asarray(R, np.float64)
+    if E is None or np.size(E) == 0:
+        return R.copy()
+    E = np.asarray(E, np.float64).reshape(-1)
+    return np.stack([np.convolve(R[r], E) for r in range(R.shape[0])])
+
+
 # ---------------------------------------------------------------------------
 # Digitisation with white noise (an extension beyond the paper, which ends at
 # the current induced on the wires)

@@ -526,3 +526,33 @@ def test_digitize_noise_statistics_and_keying():
         assert z[r, col] == pytest.approx(ref, rel=1e-12, abs=1e-12)
     other = O.digitize(np.zeros((nrows, ncols), np.float32), 1.0, 1000.0, sigma, 12, seed, 6)
     assert (other != codes).mean() > 0.5
+
+
+# ---------------------------------------------------------------------------
+# Electronics response (an extension beyond the paper)
+# ---------------------------------------------------------------------------
+def test_combined_response_special_cases():
+    rng = np.random.default_rng(51)
+    R = rng.normal(size=(7, 9))
+    assert np.array_equal(O.combined_response(R, [1.0]), R)
+    assert np.array_equal(O.combined_response(R, None), R)
+    shifted = O.combined_response(R, [0.0, 0.0, 1.0])
+    assert shifted.shape == (7, 11)
+    assert np.array_equal(shifted[:, 2:], R) and not shifted[:, :2].any()
+
+
+def test_electronics_is_a_causal_tick_convolution_of_the_output():
+    """Convolving the grid with R (x) E equals convolving the output of R
+    along ticks with E (truncated to the readout), by associativity; checked
+    against the defining double sum on small random inputs."""
+    rng = np.random.default_rng(52)
+    G = rng.normal(size=(30, 80))
+    R = rng.normal(size=(9, 12))
+    E = rng.normal(size=15)
+    for r0 in (0, 4, 8):
+        direct = O.convolve_direct(G, O.combined_response(R, E), r0)
+        base = O.convolve_direct(G, R, r0)
+        ref = np.stack([np.convolve(base[p], E)[:G.shape[1]] for p in range(G.shape[0])])
+        assert np.abs(direct - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert np.abs(O.convolve(G, O.combined_response(R, E), r0) - ref).max() \
+            <= 1e-10 * np.abs(ref).max()
