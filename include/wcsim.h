@@ -95,6 +95,14 @@ typedef struct {
     double plane_x, dir_y, dir_z, pitch_origin;
     int32_t resp_npitch, resp_nticks, resp_origin, reserved;
     const float *response;
+    /* Electronics response (an extension beyond the paper, which stops at the
+     * induced current): elec_nticks samples, host memory, copied; 0 = none.
+     * The plane convolves with R (x) E, each response row convolved along
+     * ticks with E (starting at tick 0), so the effective response is
+     * resp_npitch x (resp_nticks + elec_nticks - 1) and the tick transform
+     * must cover nticks + that length - 1.  At most 8192 samples, finite. */
+    int32_t elec_nticks, reserved2; /* reserved2 must be 0 */
+    const float *elec_response;
 } wcsim_plane_desc;
 
 /* Execution schedule of a plane; 0 in a field means "choose".  The result of

@@ -50,6 +50,9 @@ def arch() -> str:
 def cache_key(plane: dict, response: np.ndarray, r0: int, fluctuate: bool, ndepos: int,
               kind: int, device_arch: str | None = None) -> str:
     Rp, Rt = np.shape(response)
+    elec = plane.get("elec_response")
+    if elec is not None and np.size(elec) > 0:
+        Rt += int(np.size(elec)) - 1  # the plane convolves with response x electronics
     bucket = int(math.log2(ndepos)) if ndepos > 0 else -1
     return "%s|%dx%dx%d|R%dx%d@%d|fl%d|n2^%d|out%d" % (
         device_arch or arch(), int(plane["nwires"]), int(plane["nimpact"]), int(plane["nticks"]), Rp, Rt,

@@ -16,7 +16,7 @@
 // host response they were built from (to recognise a compatible donor).
 struct wcs_spectrum {
     float2 *K = nullptr, *twT = nullptr, *twHalf = nullptr, *twL = nullptr, *twF = nullptr;
-    std::vector<float> response;
+    std::vector<float> response, elec;
     int Rp = 0, Rt = 0, r0 = 0, Nfft = 0, L = 0, F = 0, device = -1;
     ~wcs_spectrum()
     {
@@ -58,6 +58,13 @@ bool finite_all(std::initializer_list<double> v)
     return true;
 }
 
+// Tick extent of the response a plane convolves with: the caller's response
+// convolved along ticks with the electronics response, if there is one.
+int effective_resp_nticks(const wcsim_plane_desc *d)
+{
+    return d->resp_nticks + (d->elec_nticks > 0 ? d->elec_nticks - 1 : 0);
+}
+
 wcsim_status validate_plane(const wcsim_plane_desc *d, const wcsim_physics *ph)
 {
     if (!d || !ph)
@@ -82,6 +89,11 @@ wcsim_status validate_plane(const wcsim_plane_desc *d, const wcsim_physics *ph)
     for (int64_t i = 0; i < (int64_t)d->resp_npitch * d->resp_nticks; ++i)
         if (!std::isfinite(d->response[i]))
             return fail(WCSIM_E_INVALID, "non-finite response value");
+    if (d->elec_nticks < 0 || d->elec_nticks > 8192 || (d->elec_nticks > 0 && !d->elec_response))
+        return fail(WCSIM_E_INVALID, "electronics response: 0..8192 samples");
+    for (int i = 0; i < d->elec_nticks; ++i)
+        if (!std::isfinite(d->elec_response[i]))
+            return fail(WCSIM_E_INVALID, "non-finite electronics response value");
     if (!finite_all({ph->drift_speed, ph->DL, ph->DT, ph->nsigma, ph->lifetime}))
         return fail(WCSIM_E_INVALID, "non-finite physics constant");
     if (ph->lifetime < 0.0)
@@ -90,7 +102,7 @@ wcsim_status validate_plane(const wcsim_plane_desc *d, const wcsim_physics *ph)
         return fail(WCSIM_E_INVALID, "drift speed must be > 0 and DL, DT, nsigma >= 0");
     if (ph->fluctuate != 0 && ph->fluctuate != 1)
         return fail(WCSIM_E_INVALID, "fluctuate must be 0 or 1");
-    if (ph->reserved != 0 || d->reserved != 0)
+    if (ph->reserved != 0 || d->reserved != 0 || d->reserved2 != 0)
         return fail(WCSIM_E_INVALID, "reserved fields must be 0");
     return WCSIM_OK;
 }
@@ -225,7 +237,7 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     pl->Nt = desc->nticks;
     pl->Nw = desc->nwires;
     pl->Rp = desc->resp_npitch;
-    pl->Rt = desc->resp_nticks;
+    pl->Rt = effective_resp_nticks(desc);
     pl->r0 = desc->resp_origin;
     PlaneParams &k = pl->kp;
     k.v = phys->drift_speed;
@@ -252,12 +264,18 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
         free_plane(pl);
         return st;
     }
+    // the caller's response and electronics response; the plane convolves
+    // with their combination, Rp x Rt (effective) built on the device
+    const size_t nresp0 = (size_t)pl->Rp * desc->resp_nticks;
+    const size_t nelec = (size_t)desc->elec_nticks;
     const size_t nresp = (size_t)pl->Rp * pl->Rt;
     if (donor && donor->spectrum) {
         const wcs_spectrum &d = *donor->spectrum;
         if (d.Rp == pl->Rp && d.Rt == pl->Rt && d.r0 == pl->r0 && d.Nfft == pl->Nfft &&
             d.L == pl->L && d.F == pl->F && d.device == pl->device && (d.twF != nullptr) == pl->fold &&
-            memcmp(d.response.data(), desc->response, sizeof(float) * nresp) == 0) {
+            d.response.size() == nresp0 && d.elec.size() == nelec &&
+            memcmp(d.response.data(), desc->response, sizeof(float) * nresp0) == 0 &&
+            (nelec == 0 || memcmp(d.elec.data(), desc->elec_response, sizeof(float) * nelec) == 0)) {
             pl->spectrum = donor->spectrum;
             pl->K = d.K;
             pl->twT = d.twT;
@@ -279,7 +297,9 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     };
     auto spec = std::make_shared<wcs_spectrum>();
     pl->spectrum = spec;
-    spec->response.assign(desc->response, desc->response + nresp);
+    spec->response.assign(desc->response, desc->response + nresp0);
+    if (nelec)
+        spec->elec.assign(desc->elec_response, desc->elec_response + nelec);
     spec->Rp = pl->Rp;
     spec->Rt = pl->Rt;
     spec->r0 = pl->r0;
@@ -301,14 +321,27 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     if ((e = hipMalloc((void **)&spec->K, kbytes)) != hipSuccess)
         return cleanup(check_hip(e, "hipMalloc(response spectrum)"));
     pl->K = spec->K;
-    const size_t rbytes = sizeof(float) * nresp;
+    // device copies: [combined Rp x Rt | caller's Rp x Rt0 | electronics]
+    const size_t rbytes = sizeof(float) * (nresp + nresp0 + nelec);
     if ((e = hipMalloc((void **)&resp, rbytes)) != hipSuccess)
         return cleanup(check_hip(e, "hipMalloc(response)"));
     if ((e = hipMalloc(&work, response_work_bytes(pl))) != hipSuccess)
         return cleanup(check_hip(e, "hipMalloc(response work)"));
-    if ((e = hipMemcpyAsync(resp, desc->response, rbytes, hipMemcpyHostToDevice, s)) !=
-        hipSuccess)
-        return cleanup(check_hip(e, "hipMemcpyAsync(response)"));
+    if (nelec == 0) {
+        if ((e = hipMemcpyAsync(resp, desc->response, sizeof(float) * nresp,
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return cleanup(check_hip(e, "hipMemcpyAsync(response)"));
+    } else {
+        float *r0d = resp + nresp, *ed = r0d + nresp0;
+        if ((e = hipMemcpyAsync(r0d, desc->response, sizeof(float) * nresp0,
+                                hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ed, desc->elec_response, sizeof(float) * nelec,
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return cleanup(check_hip(e, "hipMemcpyAsync(response)"));
+        if ((e = launch_combine_response(r0d, pl->Rp, desc->resp_nticks, ed, (int)nelec, resp,
+                                         s)) != hipSuccess)
+            return cleanup(check_hip(e, "combined response"));
+    }
     if ((e = build_response_spectrum(pl, resp, work, s)) != hipSuccess)
         return cleanup(check_hip(e, "response spectrum"));
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
@@ -377,7 +410,7 @@ wcsim_status wcsim_plane_create_sharing(const wcsim_plane_desc *desc, const wcsi
     sc.freq_chunk = donor->F;
     sc.tile = donor->tile;
     // the donor's transform may be too short for a longer readout
-    if (desc && donor->Nfft < desc->nticks + desc->resp_nticks - 1)
+    if (desc && donor->Nfft < desc->nticks + effective_resp_nticks(desc) - 1)
         return plane_create(desc, phys, nullptr, nullptr, stream, out);
     return plane_create(desc, phys, &sc, donor, stream, out);
 }

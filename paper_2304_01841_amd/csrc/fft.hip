@@ -1118,6 +1118,32 @@ size_t response_work_bytes(const wcsim_plane *pl)
 
 // Response spectrum K[c][l][f] = sum_{i<Rp} sum_{s<Rt} R[i][s]
 //   exp(-2 pi i (l i / L + k s / N')) / (L N'), k = c F + f.
+// Response combined with the electronics response along ticks:
+// out[r][t] = sum_s R[r][s] E[t - s], t < Rt0 + Ne - 1 (FP64 sums).  Runs once
+// per plane creation.
+__global__ void k_combine_response(const float *R, int Rp, int Rt0, const float *E, int Ne,
+                                   float *out)
+{
+    const int Rt = Rt0 + Ne - 1;
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= (int64_t)Rp * Rt)
+        return;
+    const int r = (int)(g / Rt), t = (int)(g - (int64_t)r * Rt);
+    double acc = 0.0;
+    for (int s = max(0, t - Ne + 1); s <= min(Rt0 - 1, t); ++s)
+        acc += (double)R[(int64_t)r * Rt0 + s] * (double)E[t - s];
+    out[g] = (float)acc;
+}
+
+hipError_t launch_combine_response(const float *R, int Rp, int Rt0, const float *E, int Ne,
+                                   float *out, hipStream_t s)
+{
+    const int64_t n = (int64_t)Rp * (Rt0 + Ne - 1);
+    hipLaunchKernelGGL(k_combine_response, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, R,
+                       Rp, Rt0, E, Ne, out);
+    return hipGetLastError();
+}
+
 hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void *work,
                                    hipStream_t s)
 {

@@ -162,6 +162,8 @@ namespace wcs {
 // ---------------------------------------------------------------------------
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s);
 
+hipError_t launch_combine_response(const float *R, int Rp, int Rt0, const float *E, int Ne,
+                                   float *out, hipStream_t s);
 hipError_t launch_digitize(const float *wave, int64_t nrows, int64_t ncols, float gain,
                            float pedestal, float sigma, int bits, uint64_t seed, uint32_t event,
                            uint16_t *adc, hipStream_t s);

@@ -54,7 +54,9 @@ class PlaneDesc(ctypes.Structure):
                 ("dir_z", ctypes.c_double), ("pitch_origin", ctypes.c_double),
                 ("resp_npitch", ctypes.c_int32), ("resp_nticks", ctypes.c_int32),
                 ("resp_origin", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("response", ctypes.POINTER(ctypes.c_float))]
+                ("response", ctypes.POINTER(ctypes.c_float)),
+                ("elec_nticks", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("elec_response", ctypes.POINTER(ctypes.c_float))]
 
 
 class Schedule(ctypes.Structure):
@@ -153,13 +155,21 @@ def physics_struct(phys: dict) -> Physics:
 
 def plane_desc_struct(plane: dict, resp: np.ndarray, r0: int) -> PlaneDesc:
     """wcsim_plane_desc of a plane dict and a contiguous float32 response (the
-    caller keeps `resp` alive while the struct is in use)."""
+    caller keeps `resp` alive while the struct is in use).  An optional
+    plane["elec_response"] (1-D) is the electronics response; the struct keeps
+    its float32 copy alive."""
     Rp, Rt = resp.shape
-    return PlaneDesc(int(plane["plane_id"]), int(plane["nwires"]), int(plane["nimpact"]),
-                     int(plane["nticks"]), float(plane["pitch"]), float(plane["tick"]),
-                     float(plane["t0"]), float(plane["plane_x"]), float(plane["dir_y"]),
-                     float(plane["dir_z"]), float(plane["pitch_origin"]), Rp, Rt, int(r0), 0,
-                     resp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    elec = plane.get("elec_response")
+    e32 = None if elec is None else np.ascontiguousarray(elec, dtype=np.float32).reshape(-1)
+    d = PlaneDesc(int(plane["plane_id"]), int(plane["nwires"]), int(plane["nimpact"]),
+                  int(plane["nticks"]), float(plane["pitch"]), float(plane["tick"]),
+                  float(plane["t0"]), float(plane["plane_x"]), float(plane["dir_y"]),
+                  float(plane["dir_z"]), float(plane["pitch_origin"]), Rp, Rt, int(r0), 0,
+                  resp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                  0 if e32 is None else int(e32.size), 0,
+                  None if e32 is None else e32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    d._keep = e32
+    return d
 
 
 def schedule_struct(schedule: dict | None) -> Schedule:

@@ -434,3 +434,45 @@ def test_digitize_with_noise_and_simulated_output(ws):
     got = ws.digitize(out, gain, 2048.0, 0.0, 12).cpu().numpy().view(np.uint16)
     ref = O.digitize(oref.astype(np.float32), gain, 2048.0, 0.0, 12, 0, 0)
     assert np.abs(got.astype(np.int64) - ref.astype(np.int64)).max() <= 1
+
+
+# ---------------------------------------------------------------------------
+# Electronics response (an extension beyond the paper)
+# ---------------------------------------------------------------------------
+def test_electronics_response(ws):
+    """A plane with an electronics response convolves with R (x) E: simulated
+    output (pitch and wire) and the convolve entry point agree with the
+    oracle; a plane sharing the same detector response but another
+    electronics response does not share its spectrum; non-finite samples are
+    rejected."""
+    log("case: electronics response")
+    w = W.small()
+    rng = np.random.default_rng(61)
+    E = (np.exp(-np.arange(60) / 12.0) * np.sin(np.arange(60) / 5.0)).astype(np.float32)
+    pl = dict(w["planes"][0], elec_response=E)
+    R = w["responses"][0]
+    Rc = O.combined_response(R.astype(np.float64), E.astype(np.float64))
+    ev = w["event_id"]
+    G = O.grid(w["depos"], w["phys"], pl, ev)
+    full = O.convolve(G, Rc, R.shape[0] // 2)
+    P = ws.Plane(pl, w["phys"], R)
+    assert P.info["fft_ticks"] >= pl["nticks"] + Rc.shape[1] - 1
+    dep = torch.from_numpy(w["depos"]).cuda()
+    for kind in (ws.OUT_PITCH, ws.OUT_WIRE):
+        out = ws.simulate_event(P, dep, ev, kind=kind).cpu().numpy()
+        ref = full if kind == ws.OUT_PITCH else O.wire_rows(full, pl["nimpact"])
+        assert normwise(out, ref) <= CONV_TOL, kind
+    Gr = rng.normal(size=G.shape).astype(np.float32)
+    out = ws.convolve(P, torch.from_numpy(Gr).cuda(), kind=ws.OUT_PITCH).cpu().numpy()
+    assert normwise(out, O.convolve(Gr.astype(np.float64), Rc, R.shape[0] // 2)) <= CONV_TOL
+    # same detector response, another electronics response: its own spectrum
+    E2 = E[::-1].copy()
+    pl2 = dict(w["planes"][0], elec_response=E2)
+    P2 = ws.Plane(pl2, w["phys"], R, share=P)
+    out2 = ws.simulate_event(P2, dep, ev, kind=ws.OUT_PITCH).cpu().numpy()
+    full2 = O.convolve(G, O.combined_response(R.astype(np.float64), E2.astype(np.float64)),
+                       R.shape[0] // 2)
+    assert normwise(out2, full2) <= CONV_TOL
+    bad = dict(w["planes"][0], elec_response=np.array([1.0, np.nan], np.float32))
+    with pytest.raises(ws.WcsimError):
+        ws.Plane(bad, w["phys"], R)
