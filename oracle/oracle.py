@@ -164,17 +164,29 @@ def digitize_normals(nrows: int, ncols: int, seed: int, event_id: int) -> np.nda
     return z.reshape(nrows, 4 * nq)[:, :ncols]
 
 
+def coloured_noise(nrows: int, ncols: int, seed: int, event_id: int, fir) -> np.ndarray:
+    """White deviates (digitize_normals) filtered by the causal FIR `fir`:
+    n[r][c] = sum_k fir[k] z[r][c - k], no white noise before column 0. FP64."""
+    z = digitize_normals(nrows, ncols, seed, event_id)
+    h = np.asarray(fir, np.float64).reshape(-1)
+    return np.stack([np.convolve(z[r], h)[:ncols] for r in range(nrows)]) if nrows else z
+
+
 def digitize(wave: np.ndarray, gain: float, pedestal: float, sigma: float, bits: int, seed: int,
-             event_id: int) -> np.ndarray:
-    """ADC codes min(max(rint(((w gain) + pedestal) + sigma z), 0), 2^bits - 1)
+             event_id: int, fir=None) -> np.ndarray:
+    """ADC codes min(max(rint(((w gain) + pedestal) + sigma n), 0), 2^bits - 1)
     as uint16, with float32 arithmetic in that order (each operation rounded,
-    no fused multiply-add) and rint rounding half to even."""
+    no fused multiply-add) and rint rounding half to even; n is the white
+    deviate, or with `fir` the coloured noise."""
     w = np.asarray(wave, np.float32)
     f32 = np.float32
     v = w * f32(gain)
     v = v + f32(pedestal)
     if sigma > 0:
-        z = digitize_normals(w.shape[0], w.shape[1], seed, event_id).astype(np.float32)
+        if fir is None:
+            z = digitize_normals(w.shape[0], w.shape[1], seed, event_id).astype(np.float32)
+        else:
+            z = coloured_noise(w.shape[0], w.shape[1], seed, event_id, fir).astype(np.float32)
         v = v + f32(sigma) * z
     v = np.rint(v)
     v = np.minimum(np.maximum(v, f32(0.0)), f32(2 ** bits - 1))

@@ -556,3 +556,19 @@ def test_electronics_is_a_causal_tick_convolution_of_the_output():
         assert np.abs(direct - ref).max() <= 1e-12 * np.abs(ref).max()
         assert np.abs(O.convolve(G, O.combined_response(R, E), r0) - ref).max() \
             <= 1e-10 * np.abs(ref).max()
+
+
+def test_coloured_noise_filter_and_correlation():
+    """fir = {1} is the white noise; fir = {0, 1} delays it by one column with
+    a zero first column; fir = {1, 1}/sqrt(2) keeps unit variance and gives a
+    lag-1 correlation of 1/2 (from h0 h1 / (h0^2 + h1^2)) over 200,000
+    samples."""
+    nrows, ncols, seed = 20, 10001, 99
+    z = O.digitize_normals(nrows, ncols, seed, 3)
+    assert np.array_equal(O.coloured_noise(nrows, ncols, seed, 3, [1.0]), z)
+    d = O.coloured_noise(nrows, ncols, seed, 3, [0.0, 1.0])
+    assert not d[:, 0].any() and np.array_equal(d[:, 1:], z[:, :-1])
+    c = O.coloured_noise(nrows, ncols, seed, 3, [math.sqrt(0.5), math.sqrt(0.5)])[:, 1:]
+    assert abs(c.var() - 1.0) < 0.02
+    lag1 = (c[:, 1:] * c[:, :-1]).mean() / c.var()
+    assert abs(lag1 - 0.5) < 0.01
