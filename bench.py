@@ -232,8 +232,19 @@ def digitize_measurement(wcsim, out, reps: int = 20) -> dict:
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / reps
+    # coloured noise through a 64-tap filter
+    fir = torch.exp(-torch.arange(64, dtype=torch.float32, device=out.device) / 9.0)
+    for _ in range(3):
+        wcsim.digitize(out, 1.0, 2048.0, 3.0, 12, seed=7, event_id=0, out=codes, fir=fir)
+    t0.record()
+    for e in range(reps):
+        wcsim.digitize(out, 1.0, 2048.0, 3.0, 12, seed=7, event_id=e, out=codes, fir=fir)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_c = t0.elapsed_time(t1) / reps
     n = out.numel()
-    return {"samples": int(n), "ms": ms, "hbm_gbs": 6.0 * n / (ms * 1e-3) / 1e9}
+    return {"samples": int(n), "ms": ms, "hbm_gbs": 6.0 * n / (ms * 1e-3) / 1e9,
+            "coloured_64tap_ms": ms_c}
 
 
 def three_plane_measurement(wcsim, W, dev, tuner=None, steps: int = 10) -> dict:

@@ -323,6 +323,19 @@ wcsim_status wcsim_digitize(const float *wave, int64_t nrows, int64_t ncols, flo
                             float pedestal, float sigma, int32_t bits, uint64_t seed,
                             uint64_t event_id, uint16_t *adc, void *stream);
 
+/* Digitisation with coloured noise (same extension): as wcsim_digitize, with
+ * the white deviates z filtered by the causal FIR filter fir[0..nfir) (device
+ * memory, float32) before scaling by sigma:
+ *   n[row][col] = sum_{k < nfir, k <= col} fir[k] z[row][col - k]
+ *   adc = min(max(rint(((w * gain) + pedestal) + sigma * n), 0), 2^bits - 1),
+ * the noise spectrum being |DFT(fir)|^2 (white noise before column 0 is
+ * zero).  z is the deviate wcsim_digitize uses, so fir = {1} reproduces it.
+ * 1 <= nfir <= 1024; other requirements and errors as wcsim_digitize. */
+wcsim_status wcsim_digitize_coloured(const float *wave, int64_t nrows, int64_t ncols, float gain,
+                                     float pedestal, float sigma, const float *fir, int32_t nfir,
+                                     int32_t bits, uint64_t seed, uint64_t event_id, uint16_t *adc,
+                                     void *stream);
+
 /* Diagnostic: the Philox4x32-10 generator the fluctuation uses (Sec. 4.1,
  * random123), evaluated on the GPU: out[i] = Philox4x32-10(ctr[i], key[i]).
  * ctr/out: n x 4 uint32, key: n x 2 uint32, all device memory. */

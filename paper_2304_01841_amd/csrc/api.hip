@@ -470,6 +470,26 @@ wcsim_status wcsim_digitize(const float *wave, int64_t nrows, int64_t ncols, flo
     return WCSIM_OK;
 }
 
+wcsim_status wcsim_digitize_coloured(const float *wave, int64_t nrows, int64_t ncols, float gain,
+                                     float pedestal, float sigma, const float *fir, int32_t nfir,
+                                     int32_t bits, uint64_t seed, uint64_t event_id, uint16_t *adc,
+                                     void *stream)
+{
+    if (nrows < 0 || ncols < 0 || (nrows > 0 && ncols > 0 && (!wave || !adc)))
+        return fail(WCSIM_E_INVALID, "bad digitize sizes or pointers");
+    if (ncols > 0 && nrows > INT64_MAX / 4 / ncols)
+        return fail(WCSIM_E_INVALID, "waveform too large");
+    if (nfir < 1 || nfir > kMaxFir || !fir)
+        return fail(WCSIM_E_INVALID, "noise filter: 1..1024 taps");
+    if (ncols > 0 && nrows * ((ncols + 1023) / 1024) > (int64_t)UINT32_MAX)
+        return fail(WCSIM_E_INVALID, "waveform too large");
+    if (bits < 1 || bits > 16 || !finite_all({gain, pedestal, sigma}) || sigma < 0.0f)
+        return fail(WCSIM_E_INVALID, "bad digitize parameters");
+    WCS_HIP(launch_digitize_fir(wave, nrows, ncols, gain, pedestal, sigma, fir, nfir, bits, seed,
+                                (uint32_t)event_id, adc, (hipStream_t)stream));
+    return WCSIM_OK;
+}
+
 wcsim_status wcsim_rasterize(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
                              wcsim_mem mem, uint64_t event_id, void *stream, wcsim_patches **out)
 {

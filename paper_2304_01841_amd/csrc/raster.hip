@@ -1113,6 +1113,77 @@ hipError_t launch_digitize(const float *wave, int64_t nrows, int64_t ncols, floa
     return hipGetLastError();
 }
 
+// Coloured noise: a workgroup takes 1024 columns of one row, draws the white
+// deviates of those columns and of the nfir - 1 before them into LDS (one
+// Philox call per quad, as k_digitize), then each thread filters four of the
+// columns (taps in LDS, float32 sums in increasing tap order) and digitises.
+constexpr int kFirCols = 1024;
+__global__ __launch_bounds__(256) void k_digitize_fir(const float *__restrict__ wave, int64_t nrows,
+                                                      int64_t ncols, float gain, float pedestal,
+                                                      float sigma, const float *__restrict__ fir,
+                                                      int nfir, float top, uint32_t k0,
+                                                      uint32_t k1, uint32_t event,
+                                                      uint16_t *__restrict__ adc)
+{
+#pragma clang fp contract(off)
+    __shared__ float h[kMaxFir];
+    __shared__ float z[kFirCols + kMaxFir + 4];
+    const int64_t tiles = (ncols + kFirCols - 1) / kFirCols;
+    const int64_t row = blockIdx.x / tiles;
+    const int64_t t0 = (blockIdx.x - row * tiles) * kFirCols;
+    // z[i] holds the deviate of column base + i; base is a multiple of four
+    const int64_t first = t0 - (nfir - 1);
+    const int64_t base = (first >= 0) ? (first & ~(int64_t)3) : -((-first + 3) & ~(int64_t)3);
+    const int64_t end = min(t0 + kFirCols, ncols);
+    const int nz = (int)(end - base);
+    for (int k = threadIdx.x; k < nfir; k += blockDim.x)
+        h[k] = fir[k];
+    for (int qi = threadIdx.x; 4 * qi < nz; qi += blockDim.x) {
+        const int64_t c = base + 4 * qi;  // first column of the quad
+        float zz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (c >= 0 && sigma > 0.0f) {
+            const uint4 r =
+                philox4x32_10(make_uint4((uint32_t)(c >> 2), (uint32_t)row, 0u, event), k0, k1);
+            box_muller(r.x, r.y, zz[0], zz[1]);
+            box_muller(r.z, r.w, zz[2], zz[3]);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            z[4 * qi + m] = zz[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kFirCols / 256; ++m) {
+        const int64_t col = t0 + threadIdx.x + 256 * m;
+        if (col >= ncols)
+            break;
+        float n = 0.0f;
+        const int kmax = (int)min((int64_t)nfir - 1, col);
+        const int zi = (int)(col - base);
+        for (int k = 0; k <= kmax; ++k)
+            n = n + h[k] * z[zi - k];
+        const int64_t i = row * ncols + col;
+        float v = wave[i] * gain;
+        v = v + pedestal;
+        v = v + sigma * n;
+        v = fminf(fmaxf(rintf(v), 0.0f), top);
+        adc[i] = (uint16_t)v;
+    }
+}
+
+hipError_t launch_digitize_fir(const float *wave, int64_t nrows, int64_t ncols, float gain,
+                               float pedestal, float sigma, const float *fir, int nfir, int bits,
+                               uint64_t seed, uint32_t event, uint16_t *adc, hipStream_t s)
+{
+    const int64_t blocks = nrows * ((ncols + kFirCols - 1) / kFirCols);
+    if (blocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_digitize_fir, dim3((unsigned)blocks), dim3(256), 0, s, wave, nrows, ncols,
+                       gain, pedestal, sigma, fir, nfir, (float)((1 << bits) - 1),
+                       (uint32_t)seed ^ 0x6e6f6973u, (uint32_t)(seed >> 32), event, adc);
+    return hipGetLastError();
+}
+
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
                          hipStream_t s)
 {

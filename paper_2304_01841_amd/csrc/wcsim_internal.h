@@ -167,6 +167,10 @@ hipError_t launch_combine_response(const float *R, int Rp, int Rt0, const float 
 hipError_t launch_digitize(const float *wave, int64_t nrows, int64_t ncols, float gain,
                            float pedestal, float sigma, int bits, uint64_t seed, uint32_t event,
                            uint16_t *adc, hipStream_t s);
+constexpr int kMaxFir = 1024;
+hipError_t launch_digitize_fir(const float *wave, int64_t nrows, int64_t ncols, float gain,
+                               float pedestal, float sigma, const float *fir, int nfir, int bits,
+                               uint64_t seed, uint32_t event, uint16_t *adc, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out,
                          hipStream_t s);
 

@@ -111,6 +111,8 @@ _SIGS = {
     "wcsim_philox4x32_10": (_st, [_P, _P, _i64, _P, _P]),
     "wcsim_digitize": (_st, [_P, _i64, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i32,
                              _u64, _u64, _P, _P]),
+    "wcsim_digitize_coloured": (_st, [_P, _i64, _i64, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, _P, _i32, _i32, _u64, _u64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -484,9 +486,11 @@ class Batch:
 
 def digitize(wave: torch.Tensor, gain: float, pedestal: float, sigma: float = 0.0, bits: int = 12,
              seed: int = 0, event_id: int = 0, out: torch.Tensor | None = None,
-             stream=None) -> torch.Tensor:
-    """ADC codes of a [nrows, ncols] float32 device waveform (wcsim_digitize):
-    uint16 codes returned as an int16 tensor of the same bit patterns."""
+             stream=None, fir: torch.Tensor | None = None) -> torch.Tensor:
+    """ADC codes of a [nrows, ncols] float32 device waveform (wcsim_digitize,
+    or wcsim_digitize_coloured with `fir`, a float32 device tensor of noise
+    filter taps): uint16 codes returned as an int16 tensor of the same bit
+    patterns."""
     if wave.dim() != 2:
         raise ValueError("wave must be [nrows, ncols]")
     nrows, ncols = wave.shape
@@ -494,10 +498,16 @@ def digitize(wave: torch.Tensor, gain: float, pedestal: float, sigma: float = 0.
         out = torch.empty((nrows, ncols), dtype=torch.int16, device=wave.device)
     elif tuple(out.shape) != (nrows, ncols):
         raise ValueError("out must be [nrows, ncols]")
-    _check(_lib.wcsim_digitize(_dev_ptr(wave, torch.float32, "wave"), nrows, ncols, float(gain),
-                               float(pedestal), float(sigma), int(bits),
-                               int(seed) & (2**64 - 1), int(event_id) & (2**64 - 1),
-                               _dev_ptr(out, torch.int16, "out"), _stream(stream)))
+    common = (float(gain), float(pedestal), float(sigma))
+    tail = (int(seed) & (2**64 - 1), int(event_id) & (2**64 - 1),
+            _dev_ptr(out, torch.int16, "out"), _stream(stream))
+    if fir is None:
+        _check(_lib.wcsim_digitize(_dev_ptr(wave, torch.float32, "wave"), nrows, ncols, *common,
+                                   int(bits), *tail))
+    else:
+        _check(_lib.wcsim_digitize_coloured(_dev_ptr(wave, torch.float32, "wave"), nrows, ncols,
+                                            *common, _dev_ptr(fir, torch.float32, "fir"),
+                                            int(fir.numel()), int(bits), *tail))
     return out
 
 

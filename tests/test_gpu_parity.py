@@ -476,3 +476,28 @@ def test_electronics_response(ws):
     bad = dict(w["planes"][0], elec_response=np.array([1.0, np.nan], np.float32))
     with pytest.raises(ws.WcsimError):
         ws.Plane(bad, w["phys"], R)
+
+
+def test_digitize_coloured_noise(ws):
+    """FIR-coloured noise: fir = {1} gives exactly the white-noise codes; a
+    64-tap filter gives codes within one of the oracle's (float32 filter sums
+    against FP64 ones) on ragged sizes spanning several 1024-column tiles;
+    bad filters are rejected."""
+    log("case: digitize with coloured noise")
+    rng = np.random.default_rng(31)
+    w = _digitize_wave(rng, 9, 2500)
+    wt = torch.from_numpy(w).cuda()
+    seed = 0xFEED_F00D
+    white = ws.digitize(wt, 1.5, 800.0, 2.5, 14, seed, 4).cpu().numpy()
+    one = torch.ones(1, dtype=torch.float32, device="cuda")
+    same = ws.digitize(wt, 1.5, 800.0, 2.5, 14, seed, 4, fir=one).cpu().numpy()
+    assert np.array_equal(same, white)
+    h = (np.exp(-np.arange(64) / 9.0) * np.cos(np.arange(64) / 3.0)).astype(np.float32)
+    got = ws.digitize(wt, 1.5, 800.0, 2.5, 14, seed, 4,
+                      fir=torch.from_numpy(h).cuda()).cpu().numpy().view(np.uint16)
+    ref = O.digitize(w, 1.5, 800.0, 2.5, 14, seed, 4, fir=h.astype(np.float64))
+    diff = np.abs(got.astype(np.int64) - ref.astype(np.int64))
+    assert diff.max() <= 1 and (diff == 0).mean() > 0.999
+    long_h = torch.ones(1025, dtype=torch.float32, device="cuda")
+    with pytest.raises(ws.WcsimError):
+        ws.digitize(wt, 1.0, 0.0, 1.0, 12, fir=long_h)
