@@ -88,3 +88,32 @@ def test_null_arguments_are_rejected(ws):
     assert L.wcsim_convolve_workspace_bytes(None, 0) == 0
     L.wcsim_plane_destroy(None)
     L.wcsim_patches_destroy(None)
+
+
+def test_binding_structs_match_the_header(ws, tmp_path):
+    """The ctypes structures of the binding have the C header's sizes and
+    field offsets (compiled and printed by the host compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"wcsim_depo": ws.Depo, "wcsim_physics": ws.Physics,
+               "wcsim_plane_desc": ws.PlaneDesc, "wcsim_schedule": ws.Schedule,
+               "wcsim_plane_info": ws.PlaneInfo}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "wcsim.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                           str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[cname + "." + f]) == getattr(py, f).offset, (cname, f)
