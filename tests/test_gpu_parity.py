@@ -1,7 +1,8 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
 
 Tolerances (normwise, max|gpu - oracle| / max|oracle| over the array):
-  * patch values and the plane grid: 1e-5 (FP32 arithmetic on FP64 weights);
+  * patch values and the plane grid: 1e-5 (FP32 arithmetic; bin weights from
+    FP32 erfc tails on the fused path, FP64 erf on the generic one);
   * convolved output: 1e-4 (FP32 FFTs of length up to ~10^4);
   * integer window bounds and the Philox words: bit-exact.
 """
@@ -373,6 +374,8 @@ def test_simulate_long_windows_use_generic_path(ws):
     phys["DL"] *= 30
     w = dict(planes=[pl], responses=[W.response("bipolar")], depos=dep, phys=phys, event_id=2)
     _sim_and_compare(ws, w)
+    # the generic path applies electron-lifetime absorption as the tile path does
+    _sim_and_compare(ws, dict(w, phys=dict(phys, lifetime=1200.0)), kinds=(ws.OUT_PITCH,))
 
 
 # ---------------------------------------------------------------------------
