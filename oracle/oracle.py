@@ -57,7 +57,7 @@ def _load():
         lib.oracle_normal.argtypes = [i64, i64, i64, u64, u64, i32]
         lib.oracle_normal.restype = ctypes.c_double
         lib.oracle_surviving_charge.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                                i32, i64, u64, u64, i32]
+                                                i32, i64, u64, u64]
         lib.oracle_surviving_charge.restype = ctypes.c_double
         lib.oracle_depo_window.argtypes = [P, P, P, P, P, P]
         lib.oracle_depo_window.restype = ctypes.c_int
@@ -80,7 +80,7 @@ def _ptr(a: np.ndarray):
 # ---------------------------------------------------------------------------
 def _phys_arr(phys: dict) -> np.ndarray:
     return np.array([phys["drift_speed"], phys["DL"], phys["DT"], phys["nsigma"],
-                     phys.get("lifetime", 0.0)], dtype=np.float64)
+                     phys.get("lifetime", 0.0), phys.get("drift_accel", 0.0)], dtype=np.float64)
 
 
 def _geom_arr(plane: dict) -> np.ndarray:
@@ -116,11 +116,12 @@ def normal(I: int, J: int, d: int, event_id: int, seed: int, plane_id: int) -> f
 
 
 def surviving_charge(q: float, T: float, tau: float, fluctuate: bool, d: int, event_id: int,
-                     seed: int, plane_id: int) -> float:
+                     seed: int) -> float:
     """Electrons of a depo that survive drift time T with electron lifetime
-    tau (0: no absorption); see oracle_surviving_charge."""
+    tau (0: no absorption); see oracle_surviving_charge.  The draw depends on
+    the depo and the event only, never on a plane."""
     return _load().oracle_surviving_charge(q, T, tau, int(bool(fluctuate)), d,
-                                           event_id & (2**64 - 1), seed & (2**64 - 1), plane_id)
+                                           event_id & (2**64 - 1), seed & (2**64 - 1))
 
 
 def combined_response(R: np.ndarray, E) -> np.ndarray:
@@ -196,14 +197,26 @@ def digitize(wave: np.ndarray, gain: float, pedestal: float, sigma: float, bits:
 # ---------------------------------------------------------------------------
 # Rasterization and Scatter-Add (Sec. 2 steps 1 and 2)
 # ---------------------------------------------------------------------------
-def depo_window(depo, phys: dict, plane: dict):
-    """(status, (mu_p, s_p, mu_t, s_t), (lo_p, lo_t, n_p, n_t)) of one depo."""
+def _window(depo, phys: dict, plane: dict):
     d = np.ascontiguousarray(depo, dtype=np.float64).reshape(5)
-    od = np.zeros(4, np.float64)
+    od = np.zeros(5, np.float64)
     oi = np.zeros(4, np.int64)
     st = _load().oracle_depo_window(_ptr(d), _ptr(_phys_arr(phys)), _ptr(_geom_arr(plane)),
                                     _ptr(_dims_arr(plane)), _ptr(od), _ptr(oi))
-    return st, tuple(od.tolist()), tuple(int(v) for v in oi)
+    return st, od, oi
+
+
+def depo_window(depo, phys: dict, plane: dict):
+    """(status, (mu_p, s_p, mu_t, s_t), (lo_p, lo_t, n_p, n_t)) of one depo."""
+    st, od, oi = _window(depo, phys, plane)
+    return st, tuple(od[:4].tolist()), tuple(int(v) for v in oi)
+
+
+def drift_time(depo, phys: dict, plane: dict) -> float:
+    """Drift time T (us) of one depo to the response plane (0 for an invalid
+    depo)."""
+    st, od, _ = _window(depo, phys, plane)
+    return float(od[4]) if st != STATUS_INVALID else 0.0
 
 
 def axis_weights(lo: int, n: int, mu: float, s: float) -> np.ndarray:

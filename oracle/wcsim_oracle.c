@@ -70,8 +70,10 @@ void oracle_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, ui
 /* ------------------------------------------------------------------------ */
 /* Problem description, passed as flat arrays so that ctypes needs no        */
 /* structure layout.                                                          */
-/*   phys[5]  = { drift speed v (mm/us), D_L (mm^2/us), D_T (mm^2/us),        */
-/*                nsigma, electron lifetime tau (us; 0: no absorption) }      */
+/*   phys[6]  = { drift speed v (mm/us) on the response plane, D_L (mm^2/us), */
+/*                D_T (mm^2/us), nsigma, electron lifetime tau (us; 0: no     */
+/*                absorption), drift acceleration a (mm/us^2; 0: constant     */
+/*                speed) }                                                    */
 /*   geom[7]  = { wire pitch (mm), tick (us), t0 (us), plane_x (mm),          */
 /*                dir_y, dir_z (unit pitch direction), pitch_origin (mm) }    */
 /*   dims[4]  = { plane_id, nwires, nimpact, nticks }                         */
@@ -87,13 +89,14 @@ typedef struct {
 } oracle_window;
 
 /* Drift, diffusion and window of one depo.  Returns ORACLE_INVALID for a
- * malformed depo (non-finite field, negative charge, or behind the response
- * plane) and ORACLE_EMPTY for a depo whose window misses the grid. */
+ * malformed depo (non-finite field, negative charge, behind the response
+ * plane, or unable to reach it) and ORACLE_EMPTY for a depo whose window
+ * misses the grid. */
 static int depo_window(const double *d, const double *phys, const double *geom,
                        const int32_t *dims, oracle_window *w)
 {
     const double x = d[0], y = d[1], z = d[2], t = d[3], q = d[4];
-    const double v = phys[0], DL = phys[1], DT = phys[2], nsig = phys[3];
+    const double v = phys[0], DL = phys[1], DT = phys[2], nsig = phys[3], a = phys[5];
     const double pitch = geom[0], tick = geom[1], t0 = geom[2], plane_x = geom[3];
     const double dir_y = geom[4], dir_z = geom[5], pitch_origin = geom[6];
     const int64_t nimpact = dims[2];
@@ -104,11 +107,23 @@ static int depo_window(const double *d, const double *phys, const double *geom,
     if (q < 0.0 || x < plane_x)
         return ORACLE_INVALID;
 
-    /* Drift from the deposition point to the response plane; the Gaussian
-     * widths grow as sqrt(2 D T), the longitudinal one converted to time by
-     * the drift speed. */
+    /* Drift from the deposition point to the response plane.  The drift
+     * speed changes linearly with drift time at the rate a and equals v on
+     * the response plane (an extension beyond the paper, whose drift speed
+     * is constant): over the remaining distance l to the plane the speed is
+     * sqrt(v^2 - 2 a l), so a depo at distance L starts at
+     * v_s = sqrt(v^2 - 2 a L) and arrives after T = 2 L / (v + v_s), the
+     * distance over the mean of the start and end speeds.  A depo with
+     * v^2 - 2 a L < 0 never reaches the plane and is invalid.  With a = 0,
+     * v_s = v and T = L / v exactly.  The Gaussian widths grow as
+     * sqrt(2 D T), the longitudinal one converted to time by the speed on
+     * the plane. */
     double L = x - plane_x;
-    double T = L / v;
+    double disc = v * v - 2.0 * a * L;
+    if (disc < 0.0)
+        return ORACLE_INVALID;
+    double v_s = sqrt(disc);
+    double T = (2.0 * L) / (v + v_s);
     double t_arr = t + T;
     w->T = T;
     double sigma_p = sqrt(2.0 * DT * T);
@@ -195,22 +210,26 @@ double oracle_normal(int64_t I, int64_t J, int64_t d, uint64_t event_id, uint64_
  * which starts from the drifted charge): with electron lifetime tau > 0 each
  * electron survives the drift time T with probability p = exp(-T / tau).
  * Without fluctuation the depo keeps its mean, q p; with fluctuation the
- * count is the normal approximation of Binomial(q, p), clamped at zero, its
- * deviate drawn from Philox4x32-10 under the plane's key at counter
- * (2^31, 0, depo index in the event, event id low word) -- a counter word 0
- * that no bin draw uses (bin quads of windows that reach the grid are small
- * non-negative numbers or, as unsigned words, within 2^10 of 2^32) -- through
- * the cosine branch of the Box-Muller transform of output words 0 and 1. */
+ * count is the normal approximation of Binomial(q, p), clamped at zero.
+ * Absorption happens during the drift, before any readout plane is reached,
+ * so the draw belongs to the depo alone: its deviate comes from
+ * Philox4x32-10 under the lifetime key (seed low word XOR 0x6c696665, seed
+ * high word) -- no plane enters it, so every plane of an event sees the same
+ * surviving charge -- at counter (0, 0, depo index in the event, event id low
+ * word), through the cosine branch of the Box-Muller transform of output
+ * words 0 and 1. */
+#define LIFETIME_KEY_XOR 0x6c696665u
+
 double oracle_surviving_charge(double q, double T, double tau, int32_t fluctuate, int64_t d,
-                               uint64_t event_id, uint64_t seed, int32_t plane_id)
+                               uint64_t event_id, uint64_t seed)
 {
     if (!(tau > 0.0))
         return q;
     double p = exp(-T / tau);
     if (!fluctuate)
         return q * p;
-    uint32_t ctr[4] = {0x80000000u, 0u, (uint32_t)d, (uint32_t)event_id};
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)plane_id};
+    uint32_t ctr[4] = {0u, 0u, (uint32_t)d, (uint32_t)event_id};
+    uint32_t key[2] = {(uint32_t)seed ^ LIFETIME_KEY_XOR, (uint32_t)(seed >> 32)};
     uint32_t r[4];
     oracle_philox4x32_10(ctr, key, r);
     double ua = ((double)(r[0] >> 9) + 0.5) * 0x1p-23;
@@ -220,15 +239,15 @@ double oracle_surviving_charge(double q, double T, double tau, int32_t fluctuate
     return (F < 0.0) ? 0.0 : F;
 }
 
-/* Window of one depo, exposed for the tests.  out_d[4] = {mu_p, s_p, mu_t,
- * s_t}, out_i[4] = {lo_p, lo_t, n_p, n_t}.  Returns the status code. */
+/* Window of one depo, exposed for the tests.  out_d[5] = {mu_p, s_p, mu_t,
+ * s_t, T}, out_i[4] = {lo_p, lo_t, n_p, n_t}.  Returns the status code. */
 int oracle_depo_window(const double *depo, const double *phys, const double *geom,
                        const int32_t *dims, double *out_d, int64_t *out_i)
 {
     oracle_window w;
     memset(&w, 0, sizeof w);
     int st = depo_window(depo, phys, geom, dims, &w);
-    out_d[0] = w.mu_p; out_d[1] = w.s_p; out_d[2] = w.mu_t; out_d[3] = w.s_t;
+    out_d[0] = w.mu_p; out_d[1] = w.s_p; out_d[2] = w.mu_t; out_d[3] = w.s_t; out_d[4] = w.T;
     out_i[0] = w.lo_p; out_i[1] = w.lo_t; out_i[2] = w.n_p; out_i[3] = w.n_t;
     return st;
 }
@@ -283,7 +302,7 @@ int64_t oracle_rasterize(const double *depos, int64_t n, const double *phys, int
         oracle_window w;
         depo_window(depos + 5 * d, phys, geom, dims, &w);
         const double q = oracle_surviving_charge(depos[5 * d + 4], w.T, phys[4], fluctuate,
-                                                 ids ? ids[d] : d, event_id, seed, plane_id);
+                                                 ids ? ids[d] : d, event_id, seed);
         double *Wp = (double *)malloc(sizeof(double) * (size_t)n_p);
         double *Wt = (double *)malloc(sizeof(double) * (size_t)n_t);
         axis_weights(w.lo_p, n_p, w.mu_p, w.s_p, Wp);

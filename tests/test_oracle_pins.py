@@ -484,7 +484,7 @@ def test_lifetime_binomial_loss_statistics():
     sums = np.array([vals[meta[d, 4]:meta[d, 4] + meta[d, 2] * meta[d, 3]].sum() for d in range(n)])
     p = math.exp(-0.7)
     for d in range(0, n, 131):
-        ref = O.surviving_charge(q, 700.0, 1000.0, True, d, 9, ph["seed"], pl["plane_id"])
+        ref = O.surviving_charge(q, 700.0, 1000.0, True, d, 9, ph["seed"])
         assert sums[d] == pytest.approx(ref, rel=1e-12)
     sd = math.sqrt(q * p * (1 - p))
     assert abs(sums.mean() - q * p) < 4.5 * sd / math.sqrt(n)
@@ -493,6 +493,110 @@ def test_lifetime_binomial_loss_statistics():
     assert len(np.unique(np.round(sums, 6))) > 0.9 * n
     meta2, vals2, _ = O.rasterize(dep[:1], ph, pl, event_id=10)
     assert vals2.sum() != pytest.approx(sums[0], rel=1e-9)
+
+
+def test_lifetime_draw_is_shared_by_the_planes():
+    """Absorption happens during the drift, before any plane is reached: with
+    fluctuation and a lifetime on, each depo's patch on the U, V and W planes
+    of one event integrates to the same surviving count (a per-plane draw
+    would give three different counts), and that count differs from the
+    unabsorbed charge and between depos."""
+    w = W.three_plane()
+    rng = np.random.default_rng(17)
+    dep = W.uniform_depos(rng, 300, (1500.0, 3300.0), (100.0, 2000.0), y_range=(600.0, 1200.0))
+    ph = _with_lifetime(W.physics(True), 1500.0)
+    totals = []
+    for pl in w["planes"]:
+        meta, vals, st = O.rasterize(dep, ph, pl, event_id=4)
+        assert (st == 0).all()
+        totals.append(np.array([vals[m[4]:m[4] + m[2] * m[3]].sum() for m in meta]))
+    assert np.allclose(totals[0], totals[1], rtol=1e-12, atol=0)
+    assert np.allclose(totals[0], totals[2], rtol=1e-12, atol=0)
+    assert np.all(np.abs(totals[0] - dep[:, 4]) > 1e-6 * dep[:, 4])
+    assert len(np.unique(np.round(totals[0] / dep[:, 4], 9))) > 290
+
+
+# ---------------------------------------------------------------------------
+# Drift speed changing with drift time (an extension beyond the paper)
+# ---------------------------------------------------------------------------
+def _with_accel(phys: dict, a: float) -> dict:
+    ph = dict(phys)
+    ph["drift_accel"] = a
+    return ph
+
+
+@pytest.mark.parametrize("a", [-2e-4, -3e-5, 1e-5, 2.5e-4])
+def test_drift_time_with_accelerating_speed(a):
+    """With the drift speed changing linearly in drift time at rate a and
+    equal to v on the response plane, the drift time T over a distance L
+    satisfies the kinematic relation L = v T - a T^2 / 2 with a start speed
+    v - a T >= 0, and equals the integral of dl / v(l) over the path, v(l)^2 =
+    v^2 - 2 a l the speed at distance l (scipy quadrature).  The diffusion
+    widths follow sqrt(2 D T), the longitudinal one over v."""
+    from scipy.integrate import quad
+
+    phys = _with_accel(W.physics(False), a)
+    pl = _plane(nw=100, nt=20000)
+    v = phys["drift_speed"]
+    for L in (1.0, 350.0, 2000.0, 4000.0):
+        if v * v - 2 * a * L < 0:
+            continue
+        depo = [L, 0.0, 100.0, 10.0, 1.0]
+        st, (mu_p, s_p, mu_t, s_t), _ = O.depo_window(depo, phys, pl)
+        T = O.drift_time(depo, phys, pl)
+        assert st == O.STATUS_OK
+        assert v * T - a * T * T / 2 == pytest.approx(L, rel=1e-13)
+        assert v - a * T >= 0.0
+        ref, _ = quad(lambda l: 1.0 / math.sqrt(v * v - 2 * a * l), 0.0, L, epsabs=0, epsrel=1e-13,
+                      limit=200)
+        assert T == pytest.approx(ref, rel=1e-11)
+        assert s_p == pytest.approx(math.sqrt(2 * phys["DT"] * T) / 0.5, rel=1e-14)
+        assert s_t == pytest.approx(math.sqrt(2 * phys["DL"] * T) / v / 0.5, rel=1e-14)
+        assert mu_t == pytest.approx((10.0 + T) / 0.5, rel=1e-14)
+
+
+def test_drift_accel_zero_is_constant_speed_and_unreachable_depos_are_invalid():
+    """a = 0 reproduces the constant-speed windows and patches bit for bit;
+    a depo farther than v^2 / (2 a) from the plane (its speed would have to
+    start below zero) is invalid, one just inside is valid."""
+    rng = np.random.default_rng(8)
+    pl = _plane(nw=60, nt=2000)
+    dep = W.uniform_depos(rng, 300, (20.0, 280.0), (30.0, 900.0))
+    for fl in (False, True):
+        ph = W.physics(fl)
+        m0, v0, s0 = O.rasterize(dep, ph, pl, event_id=2)
+        m1, v1, s1 = O.rasterize(dep, _with_accel(ph, 0.0), pl, event_id=2)
+        assert np.array_equal(m0, m1) and np.array_equal(v0, v1) and np.array_equal(s0, s1)
+    a = 1e-3
+    ph = _with_accel(W.physics(False), a)
+    reach = 1.6 * 1.6 / (2 * a)
+    st_in, _, _ = O.depo_window([reach * (1 - 1e-9), 0.0, 100.0, -500.0, 1.0], ph, pl)
+    st_out, _, _ = O.depo_window([reach * (1 + 1e-9), 0.0, 100.0, -500.0, 1.0], ph, pl)
+    assert st_in != O.STATUS_INVALID and st_out == O.STATUS_INVALID
+
+
+def test_drift_accel_feeds_lifetime_and_arrival():
+    """The lifetime survival and the arrival tick use the same drift time:
+    each patch integrates to q exp(-T / tau) with T from the kinematic
+    relation, and a faster approach (a > 0 makes the start speed lower, so
+    the drift longer) moves the patch later."""
+    rng = np.random.default_rng(12)
+    pl = _plane(nw=60, nt=4000)
+    dep = W.uniform_depos(rng, 200, (20.0, 280.0), (30.0, 900.0))
+    dep[:, 3] = 0.0
+    a, tau = 2e-4, 2000.0
+    ph = _with_lifetime(_with_accel(W.physics(False), a), tau)
+    meta, vals, st = O.rasterize(dep, ph, pl)
+    meta0, _, _ = O.rasterize(dep, W.physics(False), pl)
+    v = 1.6
+    for d in range(0, 200, 9):
+        if st[d] != 0:
+            continue
+        L = dep[d, 0]
+        T = (v - math.sqrt(v * v - 2 * a * L)) / a  # root of L = v T - a T^2 / 2
+        o, n = meta[d, 4], meta[d, 2] * meta[d, 3]
+        assert vals[o:o + n].sum() == pytest.approx(dep[d, 4] * math.exp(-T / tau), rel=1e-9)
+        assert meta[d, 1] >= meta0[d, 1]
 
 
 # ---------------------------------------------------------------------------
