@@ -78,7 +78,17 @@ typedef struct {
                          * charge: each electron survives the drift time T with
                          * probability exp(-T / tau); the depo keeps the mean q p,
                          * or with fluctuation a normal-approximated binomial count
-                         * drawn from Philox at counter (2^31, 0, depo, event). */
+                         * drawn from Philox under the key (seed low word XOR
+                         * 0x6c696665, seed high word) at counter (0, 0, depo,
+                         * event).  No plane enters that draw: every plane of an
+                         * event sees the same surviving charge. */
+    double drift_accel; /* mm/us^2, finite; 0: constant drift speed.  An extension
+                         * beyond the paper: the drift speed changes linearly with
+                         * drift time at this rate and equals drift_speed on the
+                         * response plane, so a depo at distance L from the plane
+                         * starts at v_s = sqrt(v^2 - 2 a L) and drifts for
+                         * T = 2 L / (v + v_s); a depo with v^2 - 2 a L < 0 cannot
+                         * reach the plane and is invalid. */
 } wcsim_physics;
 
 /* Plane geometry and response (Sec. 2 steps 2-3).  The grid has
@@ -172,7 +182,8 @@ wcsim_status wcsim_plane_get_info(const wcsim_plane *plane, wcsim_plane_info *in
  * A patch covers the inclusive window floor(mu - nsigma s) ..
  * floor(mu + nsigma s) along pitch and ticks.  Depos whose window misses the
  * grid, and invalid depos, get an empty patch.  Host depos are validated on
- * the host (non-finite field, q < 0 or x < plane_x -> WCSIM_E_INVALID);
+ * the host (non-finite field, q < 0, x < plane_x or a depo that cannot reach
+ * the plane under drift_accel -> WCSIM_E_INVALID);
  * invalid device depos contribute nothing.  A window longer than 1024 bins on
  * either axis is rejected (host) or dropped (device).
  * The patch set is allocated by the library (the call synchronises `stream`
@@ -316,7 +327,10 @@ void wcsim_batch_destroy(wcsim_batch *batch);
  * (seed low word XOR 0x6e6f6973, seed high word) at counter (floor(col / 4),
  * row, 0, event_id low word): one call serves four consecutive columns, words
  * (0,1) the columns with col mod 4 in {0,1} and words (2,3) the others, each
- * pair through Box-Muller with the cosine branch to the even column.
+ * pair through Box-Muller with the cosine branch to the even column; the
+ * uniform of a word r is ((r >> 9) + 1/2) 2^-23 and the transform is evaluated
+ * in FP64 (rho = sqrt(-2 ln u_a), theta = 2 pi u_b), z rounded once to
+ * float32.
  * Requires nrows, ncols >= 0, 1 <= bits <= 16, finite gain and pedestal,
  * finite sigma >= 0; otherwise WCSIM_E_INVALID.  Asynchronous on `stream`. */
 wcsim_status wcsim_digitize(const float *wave, int64_t nrows, int64_t ncols, float gain,
@@ -327,6 +341,7 @@ wcsim_status wcsim_digitize(const float *wave, int64_t nrows, int64_t ncols, flo
  * the white deviates z filtered by the causal FIR filter fir[0..nfir) (device
  * memory, float32) before scaling by sigma:
  *   n[row][col] = sum_{k < nfir, k <= col} fir[k] z[row][col - k]
+ * with z the FP64 deviates and the sum in FP64, n rounded once to float32:
  *   adc = min(max(rint(((w * gain) + pedestal) + sigma * n), 0), 2^bits - 1),
  * the noise spectrum being |DFT(fir)|^2 (white noise before column 0 is
  * zero).  z is the deviate wcsim_digitize uses, so fir = {1} reproduces it.
@@ -344,7 +359,7 @@ wcsim_status wcsim_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64
 
 const char *wcsim_last_error(void);
 
-/* Library version (major*10000 + minor*100 + patch). */
+/* Library version (major*10000 + minor*100 + patch): 10100. */
 int32_t wcsim_version(void);
 
 #ifdef __cplusplus

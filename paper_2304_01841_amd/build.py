@@ -31,15 +31,18 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source into one shared library (always recompiles)."""
     bdir = os.path.join(ROOT, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
-    for src in SRC:
+    objs, procs = [], []
+    for src in SRC:  # the translation units compile side by side
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f != "-shared"] + [
             "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc()] + HIPCC_FLAGS + objs + ["-o", tmp]
     if verbose:

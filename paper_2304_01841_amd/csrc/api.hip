@@ -94,7 +94,7 @@ wcsim_status validate_plane(const wcsim_plane_desc *d, const wcsim_physics *ph)
     for (int i = 0; i < d->elec_nticks; ++i)
         if (!std::isfinite(d->elec_response[i]))
             return fail(WCSIM_E_INVALID, "non-finite electronics response value");
-    if (!finite_all({ph->drift_speed, ph->DL, ph->DT, ph->nsigma, ph->lifetime}))
+    if (!finite_all({ph->drift_speed, ph->DL, ph->DT, ph->nsigma, ph->lifetime, ph->drift_accel}))
         return fail(WCSIM_E_INVALID, "non-finite physics constant");
     if (ph->lifetime < 0.0)
         return fail(WCSIM_E_INVALID, "lifetime must be >= 0");
@@ -257,9 +257,12 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     k.plane_id = desc->plane_id;
     k.key0 = (uint32_t)phys->seed;
     k.key1 = (uint32_t)(phys->seed >> 32) ^ (uint32_t)desc->plane_id;
+    k.lkey0 = (uint32_t)phys->seed ^ 0x6c696665u;
+    k.lkey1 = (uint32_t)(phys->seed >> 32);
     k.fluct = phys->fluctuate;
     k.pad_ = 0;
     k.tau = phys->lifetime;
+    k.accel = phys->drift_accel;
     if ((st = choose_schedule(pl, sched)) != WCSIM_OK) {
         free_plane(pl);
         return st;
@@ -350,23 +353,29 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     return cleanup(WCSIM_OK);
 }
 
-// Host-side checks of host depos: finite fields, q >= 0, x >= plane_x, and a
-// window no longer than kMaxWindow bins at the longest drift.
+// Host-side checks of host depos: finite fields, q >= 0, x >= plane_x, a depo
+// that can reach the plane, and a window no longer than kMaxWindow bins at the
+// longest drift time.
 wcsim_status validate_host_depos(const wcsim_plane *pl, const wcsim_depo *d, int64_t n)
 {
-    double xmax = pl->kp.plane_x;
+    const PlaneParams &k = pl->kp;
+    double T = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         const wcsim_depo &q = d[i];
         if (!finite_all({q.x, q.y, q.z, q.t, q.q}))
             return fail(WCSIM_E_INVALID, "depo " + std::to_string(i) + " has a non-finite field");
         if (q.q < 0.0)
             return fail(WCSIM_E_INVALID, "depo " + std::to_string(i) + " has negative charge");
-        if (q.x < pl->kp.plane_x)
+        if (q.x < k.plane_x)
             return fail(WCSIM_E_INVALID,
                         "depo " + std::to_string(i) + " lies behind the response plane");
-        xmax = std::max(xmax, q.x);
+        const double L = q.x - k.plane_x;
+        const double disc = k.v * k.v - 2.0 * k.accel * L;
+        if (disc < 0.0)
+            return fail(WCSIM_E_INVALID,
+                        "depo " + std::to_string(i) + " cannot reach the response plane");
+        T = std::max(T, (2.0 * L) / (k.v + sqrt(disc)));
     }
-    const double T = (xmax - pl->kp.plane_x) / pl->kp.v;
     const double sp = sqrt(2.0 * pl->kp.DT * T) / pl->kp.dp;
     const double stt = sqrt(2.0 * pl->kp.DL * T) / pl->kp.v / pl->kp.tick;
     if (2.0 * pl->kp.nsigma * std::max(sp, stt) + 2.0 > (double)kMaxWindow)
@@ -381,7 +390,7 @@ using namespace wcs;
 
 extern "C" {
 
-int32_t wcsim_version(void) { return 10000; }
+int32_t wcsim_version(void) { return 10100; }
 
 const char *wcsim_last_error(void) { return g_last_error.c_str(); }
 

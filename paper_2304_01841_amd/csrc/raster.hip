@@ -72,6 +72,22 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &zc, fl
     zs = rho * __builtin_amdgcn_sinf(u);
 }
 
+// FP64 Box-Muller pair of the digitisation noise: the uniforms of the two
+// words, rho = sqrt(-2 ln u_a), theta = 2 pi u_b, cosine branch (even column)
+// and sine branch (odd column), all in double precision.
+constexpr double kPi = 3.14159265358979323846;
+__device__ __forceinline__ void box_muller_d(uint32_t a, uint32_t b, double &zc, double &zs)
+{
+    const double ua = ((double)(a >> 9) + 0.5) * 0x1p-23;
+    const double ub = ((double)(b >> 9) + 0.5) * 0x1p-23;
+    const double rho = sqrt(-2.0 * log(ua));
+    const double theta = 2.0 * kPi * ub;
+    double sn, cs;
+    sincos(theta, &sn, &cs);
+    zc = rho * cs;
+    zs = rho * sn;
+}
+
 struct Win {
     double T;  // drift time to the response plane
     double mu_p, s_p, mu_t, s_t, q;
@@ -97,8 +113,17 @@ __device__ __forceinline__ Win depo_window(const wcsim_depo &dep, const PlanePar
         w.status = 1;
         return w;
     }
+    // The drift speed changes linearly with drift time at the rate accel and
+    // equals v on the response plane: the depo starts at v_s = sqrt(v^2 -
+    // 2 accel L) and drifts for T = 2 L / (v + v_s) (T = L / v exactly when
+    // accel = 0); a depo with v^2 - 2 accel L < 0 cannot reach the plane.
     const double L = x - P.plane_x;
-    const double T = L / P.v;
+    const double disc = P.v * P.v - 2.0 * P.accel * L;
+    if (disc < 0.0) {
+        w.status = 1;
+        return w;
+    }
+    const double T = (2.0 * L) / (P.v + sqrt(disc));
     w.T = T;
     const double t_arr = t + T;
     const double sigma_p = sqrt(2.0 * P.DT * T);
@@ -155,30 +180,72 @@ __device__ __forceinline__ float dpp_move(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
-// Sum over the wavefront, returned as a wave-uniform value: quad swaps and
-// row mirrors give every lane its row's sum, then the four row sums are read
-// out.  The summation order is fixed, so the result is reproducible.
-__device__ __forceinline__ float wave_sum_uniform(float v)
+// FP64 sum over the wavefront, the same value in every lane: quad swaps and
+// row mirrors (DPP) give every lane its 16-lane row's sum, then the rows are
+// combined by swapping row halves and wave halves between lanes (gfx950
+// permlane swaps), so no value passes through scalar registers.  Each 64-bit
+// value moves as two 32-bit halves.  The summation order is fixed, so the
+// result is reproducible, and a + b = b + a makes it identical in all lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move_d(double v)
 {
-    v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
-    v += dpp_move<0x141>(v);  // row_half_mirror
-    v += dpp_move<0x140>(v);  // row_mirror
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-    return (r0 + r1) + (r2 + r3);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)b >> 32), CTRL, 0xf,
+                                               0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// v + (the value of the lane `width` away, across a 16- or 32-lane boundary):
+// a permlane swap of a register with itself yields its own lane's value in one
+// result and the partner's in the other.
+template <int WIDTH>
+__device__ __forceinline__ double swap_add_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)b, hi = (uint32_t)((uint64_t)b >> 32);
+    if (WIDTH == 16) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        return __longlong_as_double((long long)(((uint64_t)h[0] << 32) | l[0])) +
+               __longlong_as_double((long long)(((uint64_t)h[1] << 32) | l[1]));
+    } else {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return __longlong_as_double((long long)(((uint64_t)h[0] << 32) | l[0])) +
+               __longlong_as_double((long long)(((uint64_t)h[1] << 32) | l[1]));
+    }
+}
+
+__device__ __forceinline__ double wave_sum_uniform_d(double v)
+{
+    v += dpp_move_d<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move_d<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move_d<0x141>(v);  // row_half_mirror
+    v += dpp_move_d<0x140>(v);  // row_mirror
+    v = swap_add_d<16>(v);      // rows 0+1 and 2+3
+    return swap_add_d<32>(v);   // all four rows
+}
+
+// q / S in FP64 for S > 0 of ordinary magnitude (a patch total): hardware
+// reciprocal refined by two Newton steps, then the product, within a few FP64
+// ulps of the quotient -- far below the float32 rounding the factor gets.
+__device__ __forceinline__ double div_pos_d(double q, double S)
+{
+    double r = __builtin_amdgcn_rcp(S);
+    r = fma(fma(-S, r, 1.0), r, r);
+    r = fma(fma(-S, r, 1.0), r, r);
+    return q * r;
 }
 
 // Electrons of a depo that survive the drift (electron lifetime tau; an
 // extension beyond the paper, which starts from the drifted charge): each
 // survives the drift time T with probability p = exp(-T / tau).  The depo
 // keeps q p, or with fluctuation the normal approximation of Binomial(q, p),
-// clamped at zero, whose deviate comes from Philox under the plane's key at
-// counter (2^31, 0, depo index in the event, event) -- a word 0 that no bin
-// draw uses -- through the cosine branch of Box-Muller on words 0 and 1, all
-// in FP64 (one draw per depo).
+// clamped at zero.  Absorption precedes the readout planes, so the deviate
+// belongs to the depo alone: Philox under the lifetime key (no plane in it)
+// at counter (0, 0, depo index in the event, event), the cosine branch of
+// Box-Muller on words 0 and 1, all in FP64 (one draw per depo).
 __device__ __forceinline__ double surviving_charge(const Win &w, const PlaneParams &P, int d,
                                                    uint32_t event)
 {
@@ -187,7 +254,7 @@ __device__ __forceinline__ double surviving_charge(const Win &w, const PlanePara
     const double p = exp(-w.T / P.tau);
     if (!P.fluct)
         return w.q * p;
-    const uint4 r = philox4x32_10(make_uint4(0x80000000u, 0u, (uint32_t)d, event), P.key0, P.key1);
+    const uint4 r = philox4x32_10(make_uint4(0u, 0u, (uint32_t)d, event), P.lkey0, P.lkey1);
     const double ua = ((double)(r.x >> 9) + 0.5) * 0x1p-23;
     const double ub = ((double)(r.y >> 9) + 0.5) * 0x1p-23;
     const double z = sqrt(-2.0 * log(ua)) * cospi(2.0 * ub);
@@ -406,7 +473,8 @@ __global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables b
             continue;
         block_axis_weights<NT>(w.lo_p, w.n_p, w.mu_p, w.s_p, Wp, E, red);
         block_axis_weights<NT>(w.lo_t, w.n_t, w.mu_t, w.s_t, Wt, E, red);
-        const float qf = (float)surviving_charge(w, P, d, event);
+        const double qd = surviving_charge(w, P, d, event);
+        const float qf = (float)qd;
         float *out = FLAT ? values + offsets[d] : nullptr;
         if (!P.fluct) {
             const int cnt = w.n_p * w.n_t;
@@ -424,7 +492,7 @@ __global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables b
         } else {
             const int qlo = quad_of(w.lo_t), nq = quad_of(w.lo_t + w.n_t - 1) - qlo + 1;
             const int items = w.n_p * nq;
-            float S = 0.0f;
+            double S = 0.0;
             for (int it = threadIdx.x; it < items; it += NT) {
                 const int i = it / nq, qd = qlo + (it - i * nq);
                 const uint4 r = philox4x32_10(
@@ -438,14 +506,14 @@ __global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables b
                     const int j = 4 * qd + m - w.lo_t;
                     if (j >= 0 && j < w.n_t) {
                         const float F = fluct_value(qf, Wp[i] * Wt[j], z[m]);
-                        S += F;
+                        S += (double)F;
                         if (FLAT)
                             out[i * w.n_t + j] = F;
                     }
                 }
             }
-            S = (float)block_sum_d<NT>((double)S, red);
-            const float scale = (S > 0.0f) ? qf / S : 0.0f;
+            S = block_sum_d<NT>(S, red);
+            const float scale = (S > 0.0) ? (float)(qd / S) : 0.0f;
             for (int it = threadIdx.x; it < items; it += NT) {
                 const int i = it / nq, qd = qlo + (it - i * nq);
                 float z[4];
@@ -463,12 +531,12 @@ __global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables b
                         const float p = Wp[i] * Wt[j];
                         if (FLAT) {
                             float &o = out[i * w.n_t + j];
-                            o = (S > 0.0f) ? o * scale : qf * p;
+                            o = (S > 0.0) ? o * scale : qf * p;
                         } else {
                             const int I = w.lo_p + i, J = w.lo_t + j;
                             if ((unsigned)I < (unsigned)P.Np && (unsigned)J < (unsigned)P.Nt) {
                                 const float v =
-                                    (S > 0.0f) ? fluct_value(qf, p, z[m]) * scale : qf * p;
+                                    (S > 0.0) ? fluct_value(qf, p, z[m]) * scale : qf * p;
                                 unsafeAtomicAdd(grid + (size_t)I * P.Nt + J, v);
                             }
                         }
@@ -671,29 +739,30 @@ __global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_c
         counters[2] = off_c;
 }
 
-// Weights of one axis computed by one thread into a record: the Gaussian's
-// integral over each bin, normalised by the window total.  The edge arguments
-// x_k = (lo + k - mu) / (sqrt(2) s) are formed in FP64; the integrals come from
-// the float32 complementary error function of |x_k|, c_k = erfc(|x_k|), with
-// erf(x) = sign(x) (1 - c): a bin on one side of the centre is the difference
-// c_a - c_b of two tail values (no cancellation of values near 1, so every
-// weight keeps a few-ulp relative error, tails included), a bin holding the
-// centre is 2 - c_a - c_b.
-__device__ __forceinline__ float edge_tail(int lo, int k, double mu, double inv, bool &neg)
+// Weights of one axis computed by one thread into a record, in FP64: the
+// Gaussian's integral over each bin, normalised by the window total, rounded
+// once to float32.  The edge arguments are x_k = (lo + k - mu) / (sqrt(2) s);
+// the integrals come from the complementary error function of |x_k|,
+// c_k = erfc(|x_k|), with erf(x) = sign(x) (1 - c): a bin on one side of the
+// centre is the difference c_a - c_b of two tail values (no cancellation of
+// values near 1, so tail bins keep their full relative precision), a bin
+// holding the centre is 2 - c_a - c_b.  The window total is the same
+// difference taken between the window's outer edges.
+__device__ __forceinline__ double edge_tail(int lo, int k, double mu, double inv, bool &neg)
 {
-    const float x = (float)(((double)(lo + k) - mu) * inv);
-    neg = x < 0.0f;
-    return erfcf(fabsf(x));
+    const double x = ((double)(lo + k) - mu) * inv;
+    neg = x < 0.0;
+    return erfc(fabs(x));
 }
 
-__device__ __forceinline__ float bin_integral(float ca, bool na, float cb, bool nb)
+__device__ __forceinline__ double bin_integral(double ca, bool na, double cb, bool nb)
 {
     // erf(b) - erf(a) for edges a < b
     if (!na)
         return ca - cb;
     if (nb)
         return cb - ca;
-    return (2.0f - ca) - cb;
+    return (2.0 - ca) - cb;
 }
 
 __device__ __forceinline__ void thread_axis_weights(int lo, int n, double mu, double s, float *W)
@@ -704,14 +773,14 @@ __device__ __forceinline__ void thread_axis_weights(int lo, int n, double mu, do
     }
     const double inv = 1.0 / (kSqrt2 * s);
     bool n0, nn;
-    float c_lo = edge_tail(lo, 0, mu, inv, n0);
-    const float c_n = edge_tail(lo, n, mu, inv, nn);
-    const float rtot = 1.0f / bin_integral(c_lo, n0, c_n, nn);
+    double c_lo = edge_tail(lo, 0, mu, inv, n0);
+    const double c_n = edge_tail(lo, n, mu, inv, nn);
+    const double rtot = 1.0 / bin_integral(c_lo, n0, c_n, nn);
     bool n_lo = n0;
     for (int i = 0; i < n; ++i) {
         bool n_hi;
-        const float c_hi = edge_tail(lo, i + 1, mu, inv, n_hi);
-        W[i] = bin_integral(c_lo, n_lo, c_hi, n_hi) * rtot;
+        const double c_hi = edge_tail(lo, i + 1, mu, inv, n_hi);
+        W[i] = (float)(bin_integral(c_lo, n_lo, c_hi, n_hi) * rtot);
         c_lo = c_hi;
         n_lo = n_hi;
     }
@@ -723,11 +792,12 @@ __device__ __forceinline__ int div_small(int a, int m) { return (int)(__umul24(a
 __device__ __forceinline__ int magic_small(int b) { return ((1 << 20) + b - 1) / b; }
 
 // Depo records in tile-list order.  Header words: lo_p, lo_t, n_p, n_t, depo
-// index, charge (float) and the division magic of the tick quad count; then
+// index, charge (FP64, two words) and the division magic of the tick quad
+// count; then
 // the pitch weights, and the tick weights placed by tick quad: entry
 // 4 (floor(J / 4) - floor(lo_t / 4)) + J mod 4 holds the weight of tick J, and
 // the entries of the first and last quad outside the window hold zero.
-enum { kHLoP, kHLoT, kHNp, kHNt, kHDepo, kHQ, kHMq, kHeaderWords };
+enum { kHLoP, kHLoT, kHNp, kHNt, kHDepo, kHQlo, kHQhi, kHMq, kHeaderWords };
 static_assert(kHeaderWords <= kRecWp, "record header overflow");
 constexpr int kStageStride = kRecWords + 1;  // odd: one LDS bank per lane
 
@@ -769,7 +839,9 @@ __global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt
         h[kHNp] = w.n_p;
         h[kHNt] = w.n_t;
         h[kHDepo] = (int)d;
-        rec[kHQ] = (float)surviving_charge(w, E.kp, (int)d, E.event);
+        const double qs = surviving_charge(w, E.kp, (int)d, E.event);
+        h[kHQlo] = (int)(uint32_t)__double_as_longlong(qs);
+        h[kHQhi] = (int)(uint32_t)((uint64_t)__double_as_longlong(qs) >> 32);
         h[kHMq] = magic_small(nq);
         float *Wt = rec + kRecWt;
         for (int k = 0; k < off; ++k)
@@ -805,7 +877,8 @@ constexpr int region_cols()
 // word w): window, depo, charge and the (row, tick quad) work items.
 struct PatchHdr {
     int lo_p, lo_t, d, m, qlo, nq, items;
-    float q;
+    float q;   // charge, float32 (the bin values)
+    double qd; // charge, FP64 (the renormalisation)
 };
 
 __device__ __forceinline__ PatchHdr patch_header(float cur)
@@ -817,7 +890,10 @@ __device__ __forceinline__ PatchHdr patch_header(float cur)
     const int n_p = __builtin_amdgcn_readlane(w, kHNp);
     const int n_t = __builtin_amdgcn_readlane(w, kHNt);
     h.d = __builtin_amdgcn_readlane(w, kHDepo);
-    h.q = __int_as_float(__builtin_amdgcn_readlane(w, kHQ));
+    const uint32_t qlo = (uint32_t)__builtin_amdgcn_readlane(w, kHQlo);
+    const uint32_t qhi = (uint32_t)__builtin_amdgcn_readlane(w, kHQhi);
+    h.qd = __longlong_as_double((long long)(((uint64_t)qhi << 32) | qlo));
+    h.q = (float)h.qd;
     h.m = __builtin_amdgcn_readlane(w, kHMq);
     h.qlo = quad_of(h.lo_t);
     h.nq = quad_of(h.lo_t + n_t - 1) - h.qlo + 1;
@@ -942,19 +1018,20 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
         float F[kFluctItems][4];
         int cell[kFluctItems];
         if (P.fluct) {
-            float acc = 0.0f;
+            double acc = 0.0;
 #pragma unroll
             for (int b = 0; b < kFluctItems; ++b)
                 if (b < nb) {
                     patch_item<RP, RT, true>(h, lane + 64 * b, cur_bits, p0, c0, P.key0,
                                              P.key1, E.event, F[b], cell[b]);
-                    acc += (F[b][0] + F[b][1]) + (F[b][2] + F[b][3]);
+                    acc += ((double)F[b][0] + (double)F[b][1]) +
+                           ((double)F[b][2] + (double)F[b][3]);
                 }
-            // renormalise the patch to its charge (a uniform factor: the
-            // hardware reciprocal, within an ulp of the quotient)
-            const float S = wave_sum_uniform(acc);
-            if (S > 0.0f) {
-                const float scale = h.q * __builtin_amdgcn_rcpf(S);
+            // renormalise the patch to its charge: the patch total and the
+            // factor q / S in FP64, the factor rounded once to float32
+            const double S = wave_sum_uniform_d(acc);
+            if (S > 0.0) {
+                const float scale = (float)div_pos_d(h.qd, S);
 #pragma unroll
                 for (int b = 0; b < kFluctItems; ++b)
                     if (b < nb)
@@ -1068,7 +1145,9 @@ hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
-// One thread per four consecutive samples of a row (one Philox call).
+// One thread per four consecutive samples of a row (one Philox call).  The
+// deviates are evaluated in FP64 and rounded once to float32, the decision is
+// taken in float32 in the order the definition states.
 __global__ __launch_bounds__(256) void k_digitize(const float *__restrict__ wave, int64_t nrows,
                                                   int64_t ncols, float gain, float pedestal,
                                                   float sigma, float top, uint32_t k0, uint32_t k1,
@@ -1083,8 +1162,12 @@ __global__ __launch_bounds__(256) void k_digitize(const float *__restrict__ wave
     float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (sigma > 0.0f) {
         const uint4 r = philox4x32_10(make_uint4((uint32_t)q, (uint32_t)row, 0u, event), k0, k1);
-        box_muller(r.x, r.y, z[0], z[1]);
-        box_muller(r.z, r.w, z[2], z[3]);
+        double zd[4];
+        box_muller_d(r.x, r.y, zd[0], zd[1]);
+        box_muller_d(r.z, r.w, zd[2], zd[3]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            z[m] = (float)zd[m];
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -1114,9 +1197,10 @@ hipError_t launch_digitize(const float *wave, int64_t nrows, int64_t ncols, floa
 }
 
 // Coloured noise: a workgroup takes 1024 columns of one row, draws the white
-// deviates of those columns and of the nfir - 1 before them into LDS (one
-// Philox call per quad, as k_digitize), then each thread filters four of the
-// columns (taps in LDS, float32 sums in increasing tap order) and digitises.
+// deviates of those columns and of the nfir - 1 before them into LDS in FP64
+// (one Philox call per quad, as k_digitize), then each thread filters four of
+// the columns (FP64 taps and sums in LDS and registers), rounds the filtered
+// noise once to float32 and digitises.
 constexpr int kFirCols = 1024;
 __global__ __launch_bounds__(256) void k_digitize_fir(const float *__restrict__ wave, int64_t nrows,
                                                       int64_t ncols, float gain, float pedestal,
@@ -1126,8 +1210,8 @@ __global__ __launch_bounds__(256) void k_digitize_fir(const float *__restrict__ 
                                                       uint16_t *__restrict__ adc)
 {
 #pragma clang fp contract(off)
-    __shared__ float h[kMaxFir];
-    __shared__ float z[kFirCols + kMaxFir + 4];
+    __shared__ double h[kMaxFir];
+    __shared__ double z[kFirCols + kMaxFir + 4];
     const int64_t tiles = (ncols + kFirCols - 1) / kFirCols;
     const int64_t row = blockIdx.x / tiles;
     const int64_t t0 = (blockIdx.x - row * tiles) * kFirCols;
@@ -1137,15 +1221,15 @@ __global__ __launch_bounds__(256) void k_digitize_fir(const float *__restrict__ 
     const int64_t end = min(t0 + kFirCols, ncols);
     const int nz = (int)(end - base);
     for (int k = threadIdx.x; k < nfir; k += blockDim.x)
-        h[k] = fir[k];
+        h[k] = (double)fir[k];
     for (int qi = threadIdx.x; 4 * qi < nz; qi += blockDim.x) {
         const int64_t c = base + 4 * qi;  // first column of the quad
-        float zz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        double zz[4] = {0.0, 0.0, 0.0, 0.0};
         if (c >= 0 && sigma > 0.0f) {
             const uint4 r =
                 philox4x32_10(make_uint4((uint32_t)(c >> 2), (uint32_t)row, 0u, event), k0, k1);
-            box_muller(r.x, r.y, zz[0], zz[1]);
-            box_muller(r.z, r.w, zz[2], zz[3]);
+            box_muller_d(r.x, r.y, zz[0], zz[1]);
+            box_muller_d(r.z, r.w, zz[2], zz[3]);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -1157,15 +1241,15 @@ __global__ __launch_bounds__(256) void k_digitize_fir(const float *__restrict__ 
         const int64_t col = t0 + threadIdx.x + 256 * m;
         if (col >= ncols)
             break;
-        float n = 0.0f;
+        double n = 0.0;
         const int kmax = (int)min((int64_t)nfir - 1, col);
         const int zi = (int)(col - base);
         for (int k = 0; k <= kmax; ++k)
-            n = n + h[k] * z[zi - k];
+            n = fma(h[k], z[zi - k], n);
         const int64_t i = row * ncols + col;
         float v = wave[i] * gain;
         v = v + pedestal;
-        v = v + sigma * n;
+        v = v + sigma * (float)n;
         v = fminf(fmaxf(rintf(v), 0.0f), top);
         adc[i] = (uint16_t)v;
     }

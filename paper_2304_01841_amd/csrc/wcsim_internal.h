@@ -36,10 +36,12 @@ struct PlaneParams {
     double v, DL, DT, nsigma;
     double dp, tick, t0, plane_x, dir_y, dir_z, pitch_origin;
     int32_t Np, Nt, nimpact, plane_id;
-    uint32_t key0, key1;  // Philox key: seed low word, seed high word ^ plane_id
+    uint32_t key0, key1;  // Philox key of the bin draws: seed low word, seed high word ^ plane_id
+    uint32_t lkey0, lkey1;  // Philox key of the lifetime draw: seed low word ^ 0x6c696665, seed high word
     int32_t fluct;
     int32_t pad_;
-    double tau;  // electron lifetime (us), 0: no absorption
+    double tau;    // electron lifetime (us), 0: no absorption
+    double accel;  // rate of change of the drift speed with drift time (mm/us^2)
 };
 
 // Maximum window length per axis handled anywhere in the library.

@@ -43,7 +43,8 @@ class Physics(ctypes.Structure):
     _fields_ = [("drift_speed", ctypes.c_double), ("DL", ctypes.c_double),
                 ("DT", ctypes.c_double), ("nsigma", ctypes.c_double),
                 ("fluctuate", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("lifetime", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("lifetime", ctypes.c_double),
+                ("drift_accel", ctypes.c_double)]
 
 
 class PlaneDesc(ctypes.Structure):
@@ -152,7 +153,8 @@ def version() -> int:
 def physics_struct(phys: dict) -> Physics:
     return Physics(float(phys["drift_speed"]), float(phys["DL"]), float(phys["DT"]),
                    float(phys["nsigma"]), int(phys["fluctuate"]), 0,
-                   int(phys["seed"]) & (2**64 - 1), float(phys.get("lifetime", 0.0)))
+                   int(phys["seed"]) & (2**64 - 1), float(phys.get("lifetime", 0.0)),
+                   float(phys.get("drift_accel", 0.0)))
 
 
 def plane_desc_struct(plane: dict, resp: np.ndarray, r0: int) -> PlaneDesc:

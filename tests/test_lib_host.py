@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(ws):
 
 
 def test_version_and_error_string(ws):
-    assert ws.version() == 10000
+    assert ws.version() == 10100
     assert isinstance(ws._lib.wcsim_last_error(), bytes)
 
 
@@ -65,7 +65,8 @@ def test_plane_create_rejects_bad_descriptor(ws, field, value):
 
 
 @pytest.mark.parametrize("field,value", [("drift_speed", 0.0), ("DL", -1.0), ("nsigma", -3.0),
-                                         ("fluctuate", 2), ("DT", float("inf"))])
+                                         ("fluctuate", 2), ("DT", float("inf")),
+                                         ("drift_accel", float("nan"))])
 def test_plane_create_rejects_bad_physics(ws, field, value):
     d, R = _desc(ws)
     p = W.physics(False)
