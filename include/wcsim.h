@@ -245,6 +245,26 @@ wcsim_status wcsim_simulate_event(const wcsim_plane *plane, const wcsim_depo *de
                                   wcsim_out out_kind, wcsim_mem out_mem, void *workspace,
                                   void *stream);
 
+/* Allocation-free variant of wcsim_simulate_event, for callers that cannot
+ * allocate device memory or pass a workspace of their own (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace is a fixed device array of WCSIM_NOALLOC_SCRATCH_BYTES bytes that
+ * the library holds on every GPU it runs on until the process ends; the call
+ * makes no allocation of any kind.  Depos and output are device memory (the
+ * caller's, as in wcsim_simulate_event with WCSIM_MEM_DEVICE for both); the
+ * current device must be the plane's.  Same results as wcsim_simulate_event.
+ * Errors: WCSIM_E_INVALID when the event needs more workspace than the array
+ * holds (wcsim_simulate_workspace_bytes(plane, n, out_kind) >
+ * WCSIM_NOALLOC_SCRATCH_BYTES) or for bad arguments, with nothing launched.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call clears what it needs): calls whose executions
+ * overlap on one GPU (other streams, other threads) race and must not be
+ * issued; calls in order on one stream are safe. */
+#define WCSIM_NOALLOC_SCRATCH_BYTES (64u << 20)
+wcsim_status wcsim_simulate_event_noalloc(const wcsim_plane *plane, const wcsim_depo *depos,
+                                          int64_t n, uint64_t event_id, float *out,
+                                          wcsim_out out_kind, void *stream);
+
 /* wcsim_simulate_event with stage timing, for measuring each kernel on the
  * stream it runs on (the paper times Rasterization, Scatter-Add and FFT
  * separately, Sec. 5.2).  `events` holds WCSIM_NUM_STAGE_EVENTS hipEvent_t

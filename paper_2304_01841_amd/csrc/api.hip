@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -769,6 +770,69 @@ wcsim_status wcsim_simulate_event_profiled(const wcsim_plane *pl, const wcsim_de
             return fail(WCSIM_E_INVALID, "NULL event in the event array");
     return simulate_event(pl, depos, n, depo_mem, event_id, out, out_kind, out_mem, workspace,
                           stream, (const hipEvent_t *)events);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free simulate: the workspace lives in a fixed device array that
+// every GPU holds from the library's load until the process ends.  In host
+// code `scratch` only names the symbol; its device address on each GPU comes
+// from hipGetSymbolAddress, taken once per device and cached.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[WCSIM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device (nullptr: not yet)
+
+wcsim_status scratch_of_current_device(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(WCSIM_E_DEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return check_hip(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                             "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return WCSIM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+wcsim_status wcsim_simulate_event_noalloc(const wcsim_plane *pl, const wcsim_depo *depos,
+                                          int64_t n, uint64_t event_id, float *out,
+                                          wcsim_out out_kind, void *stream)
+{
+    if (!pl)
+        return fail(WCSIM_E_STATE, "NULL plane");
+    if (n < 0 || (n > 0 && !depos) || !out)
+        return fail(WCSIM_E_INVALID, "bad simulate arguments");
+    if (out_kind != WCSIM_OUT_WIRE && out_kind != WCSIM_OUT_PITCH)
+        return fail(WCSIM_E_INVALID, "bad output kind");
+    const size_t need = wcsim_simulate_workspace_bytes(pl, n, out_kind);
+    if (need > (size_t)WCSIM_NOALLOC_SCRATCH_BYTES)
+        return fail(WCSIM_E_INVALID,
+                    "event needs " + std::to_string(need) +
+                        " bytes of workspace; the allocation-free entry point holds " +
+                        std::to_string((size_t)WCSIM_NOALLOC_SCRATCH_BYTES));
+    int dev = -1;
+    WCS_HIP(hipGetDevice(&dev));
+    if (dev != pl->device)
+        return fail(WCSIM_E_INVALID, "the current device is not the plane's device");
+    void *ws = nullptr;
+    wcsim_status st = scratch_of_current_device(dev, &ws);
+    if (st != WCSIM_OK)
+        return st;
+    return simulate_event(pl, depos, n, WCSIM_MEM_DEVICE, event_id, out, out_kind,
+                          WCSIM_MEM_DEVICE, ws, stream, nullptr);
 }
 
 wcsim_status wcsim_tune_schedules(const wcsim_plane_desc *desc, const wcsim_physics *phys,

@@ -101,6 +101,7 @@ _SIGS = {
     "wcsim_simulate_event": (_st, [_P, _P, _i64, _i32, _u64, _P, _i32, _i32, _P, _P]),
     "wcsim_simulate_event_profiled": (_st, [_P, _P, _i64, _i32, _u64, _P, _i32, _i32, _P, _P,
                                             _P]),
+    "wcsim_simulate_event_noalloc": (_st, [_P, _P, _i64, _u64, _P, _i32, _P]),
     "wcsim_tune_schedules": (_st, [_P, _P, _P, _i32, _P, _i64, _i32, _i32, _P, _P]),
     "wcsim_workspace_grid": (_P, [_P, _P, _i64]),
     "wcsim_workspace_invalid_count": (_st, [_P, _P, _P]),
@@ -371,6 +372,24 @@ def simulate_event(plane: Plane, depos, event_id: int = 0, out=None, kind: int =
     _check(_lib.wcsim_simulate_event(plane.handle, ptr, n, mem, int(event_id) & (2**64 - 1),
                                      out_ptr, kind, out_mem, _dev_ptr(workspace, what="workspace"),
                                      _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def simulate_event_noalloc(plane: Plane, depos: torch.Tensor, event_id: int, out: torch.Tensor,
+                           kind: int = OUT_WIRE, stream=None) -> torch.Tensor:
+    """wcsim_simulate_event_noalloc: device depos and output, the library's
+    fixed device workspace (no allocation in the call)."""
+    ptr, n, mem, _keep = _depo_arg(depos)
+    if mem != MEM_DEVICE:
+        raise ValueError("depos must be a CUDA tensor")
+    if tuple(out.shape) != (plane.out_rows(kind), plane.nticks):
+        raise ValueError("out has the wrong shape")
+    _check(_lib.wcsim_simulate_event_noalloc(plane.handle, ptr, n, int(event_id) & (2**64 - 1),
+                                             _dev_ptr(out, torch.float32, "out"), kind,
+                                             _stream(stream)))
     return out
 
 
