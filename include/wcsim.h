@@ -305,9 +305,11 @@ float *wcsim_workspace_grid(const wcsim_plane *plane, void *workspace, int64_t n
 wcsim_status wcsim_workspace_invalid_count(const void *workspace, void *stream, int64_t *count);
 
 /* Batched form: nevents events, each with its own plane (planes may repeat),
- * depos (device memory), event id and output (device memory), run as one
- * sequence of launches whose kernels each cover every event.  `workspace`:
- * device memory of at least wcsim_batch_workspace_bytes bytes. */
+ * depos (device memory), event id and output (device memory), run as chunks
+ * of launch sequences whose kernels each cover every event of a chunk (see
+ * wcsim_batch_chunk_count).  Asynchronous on `stream`: the batch is complete
+ * in `stream`'s order.  `workspace`: device memory of at least
+ * wcsim_batch_workspace_bytes bytes. */
 size_t wcsim_batch_workspace_bytes(const wcsim_plane *const *planes, const int64_t *n,
                                    int32_t nevents, wcsim_out out_kind);
 wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
@@ -315,6 +317,34 @@ wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
                                   const uint64_t *event_ids, int32_t nevents,
                                   float *const *outs, wcsim_out out_kind, void *workspace,
                                   void *stream);
+
+/* Number of chunks wcsim_simulate_batch cuts these events into: the events
+ * are grouped by schedule class (planes whose kernels can share a launch) and
+ * each class is cut into chunks of at most 8 events, in the callers' order.
+ * A chunk's rasterization (binning, records, LDS-tiled raster) runs as one
+ * launch sequence on `stream`, its three FFT passes as another on a second
+ * stream of the library's, so that one chunk's rasterization overlaps the
+ * previous chunk's passes; chunk data alternate between two halves of the
+ * workspace.  0 for bad arguments. */
+int32_t wcsim_batch_chunk_count(const wcsim_plane *const *planes, const int64_t *n,
+                                int32_t nevents, wcsim_out out_kind);
+
+/* wcsim_simulate_batch with stage timing (the paper's per-kernel timers,
+ * Sec. 5.2): `events` holds WCSIM_BATCH_STAGE_EVENTS hipEvent_t handles per
+ * chunk (nevents_events = chunks * WCSIM_BATCH_STAGE_EVENTS), recorded for
+ * chunk c at [8c + 0] start of its rasterization, [8c + 1] depos binned and
+ * records built, [8c + 2] LDS-tiled raster done, [8c + 3] large-patch raster
+ * done (all on `stream`), [8c + 4] start of its passes, [8c + 5] tick-axis
+ * FFT done, [8c + 6] pitch-axis convolution done, [8c + 7] inverse tick-axis
+ * FFT done (on the library's second stream).  WCSIM_E_INVALID when the count
+ * does not match or an entry is NULL. */
+#define WCSIM_BATCH_STAGE_EVENTS 8
+wcsim_status wcsim_simulate_batch_profiled(const wcsim_plane *const *planes,
+                                           const wcsim_depo *const *depos, const int64_t *n,
+                                           const uint64_t *event_ids, int32_t nevents,
+                                           float *const *outs, wcsim_out out_kind,
+                                           void *workspace, void *stream, void *const *events,
+                                           int32_t nevents_events);
 
 /* Captured batch (hipGraph): the launch sequence of a batch of up to
  * capacity[e] depos per event on the given planes is captured once; each run

@@ -904,20 +904,46 @@ wcsim_status wcsim_tune_schedules(const wcsim_plane_desc *desc, const wcsim_phys
 namespace wcs {
 namespace {
 
-// Layout of a batch workspace for events `idx` (all of one schedule class).
-struct BatchLayout {
+// ---------------------------------------------------------------------------
+// Batched form.  The events of a call are grouped by schedule class (planes
+// whose kernels can share one launch) and each class is cut into chunks of a
+// few events.  A chunk runs as two launch sequences whose kernels each cover
+// all of its events: the raster sequence (binning, records, LDS-tiled
+// raster) and the convolution sequence (the three FFT passes).  Chunks are
+// pipelined over two streams, rasters on one and convolutions on the other,
+// so that one chunk's rasterization (bound by vector ALU work) overlaps the
+// previous chunk's FFT passes (bound by memory and LDS traffic).  Chunk data
+// (raster work, grids, spectra) alternate between two workspace slots: the
+// raster of chunk c waits until the convolution of chunk c - 2 has finished
+// with the slot.  The descriptor tables of all chunks sit in front of the
+// slots and are uploaded once per call.
+// ---------------------------------------------------------------------------
+constexpr int kChunkEvents = 8;  // events per chunk at most
+
+// Layout of one chunk: its tables (relative to the chunk's table offset) and
+// its data (relative to the base of the slot it runs in).
+struct ChunkLayout {
     int64_t n_total = 0, ntiles_total = 0;
     int nblk_r = 0, nblk_p = 0, nblk_c = 0;
-    size_t off_ev = 0, off_bases = 0, off_raster = 0, off_grid = 0, off_X = 0, off_Y = 0;
-    size_t grid_bytes = 0, total = 0;
+    size_t off_bases = 0, tables_bytes = 0;
+    size_t off_grid = 0, off_X = 0, off_Y = 0, grid_bytes = 0, data_bytes = 0;
     std::vector<EventCtx> ev;
     std::vector<int32_t> bases;  // 5 arrays of nev + 1
 };
 
-BatchLayout plan_batch(const wcsim_plane *const *planes, const int64_t *n,
+struct BatchPlan {
+    std::vector<std::vector<int>> chunks;  // event indices of each chunk
+    std::vector<ChunkLayout> layouts;
+    std::vector<size_t> table_off;         // offset of each chunk's tables
+    size_t tables_total = 0, slot_bytes = 0, total = 0;
+    int nslots = 1;
+    size_t slot_base(int c) const { return tables_total + (size_t)(c % nslots) * slot_bytes; }
+};
+
+ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
                        const std::vector<int> &idx, wcsim_out kind)
 {
-    BatchLayout L;
+    ChunkLayout L;
     const int nev = (int)idx.size();
     L.ev.resize((size_t)nev);
     L.bases.assign(5 * (size_t)(nev + 1), 0);
@@ -938,7 +964,7 @@ BatchLayout plan_batch(const wcsim_plane *const *planes, const int64_t *n,
         e.nout = (int32_t)nout;
         e.nblocks = pl->nblocks;
         e.mode = (kind == WCSIM_OUT_WIRE) ? 1 : 0;
-        // device offsets, turned into pointers once the base is known
+        // offsets within the chunk's data, turned into pointers per run
         e.grid = (float *)(uintptr_t)grid_off;
         e.X = (float2 *)(uintptr_t)x_off;
         e.Y = (float2 *)(uintptr_t)y_off;
@@ -961,117 +987,99 @@ BatchLayout plan_batch(const wcsim_plane *const *planes, const int64_t *n,
     br[nev] = L.nblk_r;
     bp[nev] = L.nblk_p;
     bc[nev] = L.nblk_c;
-    const wcsim_plane *pl0 = planes[idx[0]];
-    L.off_ev = 0;
     L.off_bases = align_up(sizeof(EventCtx) * (size_t)nev);
-    L.off_raster = L.off_bases + align_up(sizeof(int32_t) * L.bases.size());
-    L.off_grid = L.off_raster + raster_work_bytes_batch(pl0, L.n_total, L.ntiles_total);
+    L.tables_bytes = L.off_bases + align_up(sizeof(int32_t) * L.bases.size());
+    const wcsim_plane *pl0 = planes[idx[0]];
+    L.off_grid = raster_work_bytes_batch(pl0, L.n_total, L.ntiles_total);
     L.grid_bytes = grid_off;
     L.off_X = L.off_grid + grid_off;
     L.off_Y = L.off_X + x_off;
-    L.total = L.off_Y + y_off;
+    L.data_bytes = L.off_Y + y_off;
     return L;
 }
 
-// Pinned host staging of the descriptor tables of this thread's batches; the
-// event marks when the last upload from it has completed.
-struct HostStaging {
-    void *buf = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-    ~HostStaging()
-    {
-        if (done)
-            (void)hipEventSynchronize(done);
-        if (buf)
-            (void)hipHostFree(buf);
-        if (done)
-            (void)hipEventDestroy(done);
-    }
-};
-thread_local HostStaging g_staging;
-
-}  // namespace
-}  // namespace wcs
-
-struct wcsim_batch {
-    std::vector<const wcsim_plane *> planes;
-    std::vector<int64_t> capacity;
-    wcsim_out kind;
-    char *ws = nullptr;
+std::vector<std::vector<int>> schedule_groups(const wcsim_plane *const *planes, int nevents)
+{
     std::vector<std::vector<int>> groups;
-    std::vector<wcs::BatchLayout> layouts;
-    std::vector<size_t> host_off;
-    void *pinned = nullptr;
-    hipEvent_t done = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-namespace wcs {
-namespace {
-
-void destroy_batch(wcsim_batch *b)
-{
-    if (b->done)
-        (void)hipEventSynchronize(b->done);
-    if (b->exec)
-        (void)hipGraphExecDestroy(b->exec);
-    if (b->pinned)
-        (void)hipHostFree(b->pinned);
-    if (b->done)
-        (void)hipEventDestroy(b->done);
-    delete b;
-}
-
-wcsim_status stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s)
-{
-    HostStaging &h = g_staging;
-    if (!h.done)
-        WCS_HIP(hipEventCreateWithFlags(&h.done, hipEventDisableTiming));
-    WCS_HIP(hipEventSynchronize(h.done));  // the previous upload has left the buffer
-    if (h.cap < bytes) {
-        if (h.buf)
-            WCS_HIP(hipHostFree(h.buf));
-        h.buf = nullptr;
-        h.cap = 0;
-        WCS_HIP(hipHostMalloc(&h.buf, bytes, hipHostMallocDefault));
-        h.cap = bytes;
+    for (int e = 0; e < nevents; ++e) {
+        bool placed = false;
+        for (auto &g : groups)
+            if (same_schedule_class(planes[g[0]], planes[e])) {
+                g.push_back(e);
+                placed = true;
+                break;
+            }
+        if (!placed)
+            groups.push_back({e});
     }
-    memcpy(h.buf, src, bytes);
-    WCS_HIP(hipMemcpyAsync(dst, h.buf, bytes, hipMemcpyHostToDevice, s));
-    WCS_HIP(hipEventRecord(h.done, s));
-    return WCSIM_OK;
+    return groups;
 }
 
-// Per-run fields of the descriptors and the device pointers of the layout.
-void fill_descriptors(BatchLayout &L, const std::vector<int> &g, char *ws,
-                      const wcsim_depo *const *depos, const int64_t *n, const uint64_t *event_ids,
-                      float *const *outs)
+// Chunks of each schedule class: as many as kChunkEvents requires, with event
+// counts differing by at most one, in the callers' order.
+BatchPlan plan_batch(const wcsim_plane *const *planes, const int64_t *n, int nevents,
+                     wcsim_out kind)
 {
-    for (size_t k = 0; k < g.size(); ++k) {
-        EventCtx &e = L.ev[k];
-        e.depos = depos[g[k]];
-        e.n = (int32_t)n[g[k]];
-        e.event = (uint32_t)event_ids[g[k]];
-        e.out = outs[g[k]];
-        e.grid = (float *)(ws + L.off_grid + (uintptr_t)e.grid);
-        e.X = (float2 *)(ws + L.off_X + (uintptr_t)e.X);
-        e.Y = (float2 *)(ws + L.off_Y + (uintptr_t)e.Y);
+    BatchPlan bp;
+    for (const auto &g : schedule_groups(planes, nevents)) {
+        const int nch = ((int)g.size() + kChunkEvents - 1) / kChunkEvents;
+        size_t pos = 0;
+        for (int c = 0; c < nch; ++c) {
+            const size_t take = g.size() / nch + ((size_t)c < g.size() % nch ? 1 : 0);
+            bp.chunks.emplace_back(g.begin() + pos, g.begin() + pos + take);
+            pos += take;
+        }
+    }
+    for (const auto &c : bp.chunks) {
+        bp.layouts.push_back(plan_chunk(planes, n, c, kind));
+        bp.table_off.push_back(bp.tables_total);
+        bp.tables_total += align_up(bp.layouts.back().tables_bytes);
+        bp.slot_bytes = std::max(bp.slot_bytes, align_up(bp.layouts.back().data_bytes));
+    }
+    bp.nslots = bp.chunks.size() > 1 ? 2 : 1;
+    bp.total = bp.tables_total + (size_t)bp.nslots * bp.slot_bytes;
+    return bp;
+}
+
+// Per-run fields of the descriptors and their device pointers.
+void fill_descriptors(BatchPlan &bp, char *ws, const wcsim_depo *const *depos, const int64_t *n,
+                      const uint64_t *event_ids, float *const *outs)
+{
+    for (size_t c = 0; c < bp.chunks.size(); ++c) {
+        ChunkLayout &L = bp.layouts[c];
+        const std::vector<int> &g = bp.chunks[c];
+        char *data = ws + bp.slot_base((int)c);
+        for (size_t k = 0; k < g.size(); ++k) {
+            EventCtx &e = L.ev[k];
+            e.depos = depos[g[k]];
+            e.n = (int32_t)n[g[k]];
+            e.event = (uint32_t)event_ids[g[k]];
+            e.out = outs[g[k]];
+            e.grid = (float *)(data + L.off_grid + (uintptr_t)e.grid);
+            e.X = (float2 *)(data + L.off_X + (uintptr_t)e.X);
+            e.Y = (float2 *)(data + L.off_Y + (uintptr_t)e.Y);
+        }
     }
 }
 
-void pack_tables(const BatchLayout &L, char *host)
+void pack_tables(const BatchPlan &bp, char *host)
 {
-    memcpy(host + L.off_ev, L.ev.data(), sizeof(EventCtx) * L.ev.size());
-    memcpy(host + L.off_bases, L.bases.data(), sizeof(int32_t) * L.bases.size());
+    for (size_t c = 0; c < bp.chunks.size(); ++c) {
+        const ChunkLayout &L = bp.layouts[c];
+        char *h = host + bp.table_off[c];
+        memcpy(h, L.ev.data(), sizeof(EventCtx) * L.ev.size());
+        memcpy(h + L.off_bases, L.bases.data(), sizeof(int32_t) * L.bases.size());
+    }
 }
 
-BatchTables tables_of(const BatchLayout &L, char *ws)
+BatchTables tables_of(const BatchPlan &bp, int c, char *ws)
 {
+    const ChunkLayout &L = bp.layouts[(size_t)c];
     const int nev = (int)L.ev.size();
+    char *t = ws + bp.table_off[(size_t)c];
     BatchTables bt;
-    bt.ev = (const EventCtx *)(ws + L.off_ev);
-    const int32_t *b0 = (const int32_t *)(ws + L.off_bases);
+    bt.ev = (const EventCtx *)t;
+    const int32_t *b0 = (const int32_t *)(t + L.off_bases);
     bt.depo_base = b0;
     bt.tile_base = b0 + (nev + 1);
     bt.rblk_base = b0 + 2 * (nev + 1);
@@ -1081,17 +1089,41 @@ BatchTables tables_of(const BatchLayout &L, char *ws)
     return bt;
 }
 
-// Kernels of one group (its tables already uploaded to the workspace head).
-hipError_t launch_batch_group(const wcsim_plane *pl0, const BatchLayout &L, char *ws,
-                              hipStream_t s)
+// Launches of a whole batch whose tables are already in the workspace:
+// rasters on sR, convolutions on sF, ordered by the four events (two per
+// slot); sR finally waits for the last convolution, so the batch is complete
+// in sR's order.  `marks` (nullable): WCSIM_BATCH_STAGE_EVENTS timing events
+// per chunk (see wcsim_simulate_batch_profiled).
+hipError_t launch_pipeline(const BatchPlan &bp, const wcsim_plane *const *planes, char *ws,
+                           hipStream_t sR, hipStream_t sF, const hipEvent_t *evR,
+                           const hipEvent_t *evF, const hipEvent_t *marks = nullptr)
 {
-    const BatchTables bt = tables_of(L, ws);
-    const RasterWork rw = raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, ws + L.off_raster);
     hipError_t e;
-    if ((e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, ws + L.off_grid,
-                                 L.grid_bytes, s)) != hipSuccess)
-        return e;
-    return launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, s);
+    const int nch = (int)bp.chunks.size();
+    for (int c = 0; c < nch; ++c) {
+        const ChunkLayout &L = bp.layouts[(size_t)c];
+        const wcsim_plane *pl0 = planes[bp.chunks[(size_t)c][0]];
+        const BatchTables bt = tables_of(bp, c, ws);
+        const int slot = c % bp.nslots;
+        char *data = ws + bp.slot_base(c);
+        if (c >= bp.nslots && (e = hipStreamWaitEvent(sR, evF[slot], 0)) != hipSuccess)
+            return e;
+        const hipEvent_t *mk = marks ? marks + (size_t)c * WCSIM_BATCH_STAGE_EVENTS : nullptr;
+        const RasterWork rw = raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, data);
+        if ((mk && (e = hipEventRecord(mk[0], sR)) != hipSuccess) ||
+            (e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, data + L.off_grid,
+                                     L.grid_bytes, sR, mk ? mk + 1 : nullptr)) != hipSuccess ||
+            (e = hipEventRecord(evR[slot], sR)) != hipSuccess ||
+            (e = hipStreamWaitEvent(sF, evR[slot], 0)) != hipSuccess ||
+            (mk && (e = hipEventRecord(mk[4], sF)) != hipSuccess) ||
+            (e = launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, sF,
+                                       mk ? mk + 5 : nullptr)) != hipSuccess ||
+            (e = hipEventRecord(evF[slot], sF)) != hipSuccess)
+            return e;
+    }
+    if (nch > 0)
+        return hipStreamWaitEvent(sR, evF[(nch - 1) % bp.nslots], 0);
+    return hipSuccess;
 }
 
 wcsim_status check_batch_args(const wcsim_plane *const *planes, const wcsim_depo *const *depos,
@@ -1117,21 +1149,112 @@ wcsim_status check_batch_args(const wcsim_plane *const *planes, const wcsim_depo
     return WCSIM_OK;
 }
 
-std::vector<std::vector<int>> schedule_groups(const wcsim_plane *const *planes, int nevents)
-{
-    std::vector<std::vector<int>> groups;
-    for (int e = 0; e < nevents; ++e) {
-        bool placed = false;
-        for (auto &g : groups)
-            if (same_schedule_class(planes[g[0]], planes[e])) {
-                g.push_back(e);
-                placed = true;
-                break;
-            }
-        if (!placed)
-            groups.push_back({e});
+// Pinned host staging of the descriptor tables of this thread's direct batch
+// calls; the event marks when the last upload from it has completed.
+struct HostStaging {
+    void *buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    ~HostStaging()
+    {
+        if (done)
+            (void)hipEventSynchronize(done);
+        if (buf)
+            (void)hipHostFree(buf);
+        if (done)
+            (void)hipEventDestroy(done);
     }
-    return groups;
+};
+thread_local HostStaging g_staging;
+
+wcsim_status stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s)
+{
+    HostStaging &h = g_staging;
+    if (!h.done)
+        WCS_HIP(hipEventCreateWithFlags(&h.done, hipEventDisableTiming));
+    WCS_HIP(hipEventSynchronize(h.done));  // the previous upload has left the buffer
+    if (h.cap < bytes) {
+        if (h.buf)
+            WCS_HIP(hipHostFree(h.buf));
+        h.buf = nullptr;
+        h.cap = 0;
+        WCS_HIP(hipHostMalloc(&h.buf, bytes, hipHostMallocDefault));
+        h.cap = bytes;
+    }
+    memcpy(h.buf, src, bytes);
+    WCS_HIP(hipMemcpyAsync(dst, h.buf, bytes, hipMemcpyHostToDevice, s));
+    WCS_HIP(hipEventRecord(h.done, s));
+    return WCSIM_OK;
+}
+
+// The second stream and the four ordering events of this thread's direct
+// batch calls, one set per device (default priority, non-blocking).
+struct PipeStreams {
+    int device = -1;
+    hipStream_t sF = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~PipeStreams()
+    {
+        if (sF) {
+            (void)hipStreamSynchronize(sF);
+            (void)hipStreamDestroy(sF);
+        }
+        for (hipEvent_t e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    }
+};
+thread_local std::vector<std::unique_ptr<PipeStreams>> g_pipes;
+
+wcsim_status pipe_streams(PipeStreams **out)
+{
+    int dev = -1;
+    WCS_HIP(hipGetDevice(&dev));
+    for (auto &p : g_pipes)
+        if (p->device == dev) {
+            *out = p.get();
+            return WCSIM_OK;
+        }
+    std::unique_ptr<PipeStreams> p(new (std::nothrow) PipeStreams());
+    if (!p)
+        return fail(WCSIM_E_NOMEM, "host allocation failed");
+    p->device = dev;
+    WCS_HIP(hipStreamCreateWithFlags(&p->sF, hipStreamNonBlocking));
+    for (hipEvent_t &e : p->ev)
+        WCS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    *out = p.get();
+    g_pipes.push_back(std::move(p));
+    return WCSIM_OK;
+}
+
+}  // namespace
+}  // namespace wcs
+
+struct wcsim_batch {
+    std::vector<const wcsim_plane *> planes;
+    std::vector<int64_t> capacity;
+    wcsim_out kind;
+    char *ws = nullptr;
+    wcs::BatchPlan plan;
+    void *pinned = nullptr;
+    hipEvent_t done = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace wcs {
+namespace {
+
+void destroy_batch(wcsim_batch *b)
+{
+    if (b->done)
+        (void)hipEventSynchronize(b->done);
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->pinned)
+        (void)hipHostFree(b->pinned);
+    if (b->done)
+        (void)hipEventDestroy(b->done);
+    delete b;
 }
 
 }  // namespace
@@ -1144,10 +1267,46 @@ size_t wcsim_batch_workspace_bytes(const wcsim_plane *const *planes, const int64
 {
     if (!planes || !n || nevents <= 0)
         return 0;
-    size_t m = 0;
-    for (const auto &g : schedule_groups(planes, nevents))
-        m = std::max(m, plan_batch(planes, n, g, out_kind).total);
-    return m;
+    for (int32_t e = 0; e < nevents; ++e)
+        if (!planes[e] || n[e] < 0)
+            return 0;
+    return plan_batch(planes, n, nevents, out_kind).total;
+}
+
+int32_t wcsim_batch_chunk_count(const wcsim_plane *const *planes, const int64_t *n,
+                                int32_t nevents, wcsim_out out_kind)
+{
+    if (!planes || !n || nevents <= 0)
+        return 0;
+    for (int32_t e = 0; e < nevents; ++e)
+        if (!planes[e] || n[e] < 0)
+            return 0;
+    return (int32_t)plan_batch(planes, n, nevents, out_kind).chunks.size();
+}
+
+static wcsim_status simulate_batch(const wcsim_plane *const *planes,
+                                   const wcsim_depo *const *depos, const int64_t *n,
+                                   const uint64_t *event_ids, int32_t nevents,
+                                   float *const *outs, wcsim_out out_kind, void *workspace,
+                                   void *stream, const hipEvent_t *marks)
+{
+    wcsim_status st = check_batch_args(planes, depos, n, event_ids, nevents, outs, out_kind,
+                                       workspace);
+    if (st != WCSIM_OK || nevents == 0)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    PipeStreams *ps = nullptr;
+    if ((st = pipe_streams(&ps)) != WCSIM_OK)
+        return st;
+    BatchPlan bp = plan_batch(planes, n, nevents, out_kind);
+    fill_descriptors(bp, ws, depos, n, event_ids, outs);
+    std::vector<char> host(bp.tables_total);
+    pack_tables(bp, host.data());
+    if ((st = stage_upload(host.data(), host.size(), ws, s)) != WCSIM_OK)
+        return st;
+    WCS_HIP(launch_pipeline(bp, planes, ws, s, ps->sF, ps->ev, ps->ev + 2, marks));
+    return WCSIM_OK;
 }
 
 wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
@@ -1155,22 +1314,27 @@ wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
                                   const uint64_t *event_ids, int32_t nevents, float *const *outs,
                                   wcsim_out out_kind, void *workspace, void *stream)
 {
-    wcsim_status st = check_batch_args(planes, depos, n, event_ids, nevents, outs, out_kind,
-                                       workspace);
-    if (st != WCSIM_OK)
-        return st;
-    hipStream_t s = (hipStream_t)stream;
-    char *ws = (char *)workspace;
-    for (const auto &g : schedule_groups(planes, nevents)) {
-        BatchLayout L = plan_batch(planes, n, g, out_kind);
-        fill_descriptors(L, g, ws, depos, n, event_ids, outs);
-        std::vector<char> host(L.off_raster);
-        pack_tables(L, host.data());
-        if ((st = stage_upload(host.data(), host.size(), ws, s)) != WCSIM_OK)
-            return st;
-        WCS_HIP(launch_batch_group(planes[g[0]], L, ws, s));
-    }
-    return WCSIM_OK;
+    return simulate_batch(planes, depos, n, event_ids, nevents, outs, out_kind, workspace, stream,
+                          nullptr);
+}
+
+wcsim_status wcsim_simulate_batch_profiled(const wcsim_plane *const *planes,
+                                           const wcsim_depo *const *depos, const int64_t *n,
+                                           const uint64_t *event_ids, int32_t nevents,
+                                           float *const *outs, wcsim_out out_kind,
+                                           void *workspace, void *stream, void *const *events,
+                                           int32_t nevents_events)
+{
+    if (!planes || !n || nevents <= 0)
+        return fail(WCSIM_E_INVALID, "bad batch arguments");
+    const int32_t nch = wcsim_batch_chunk_count(planes, n, nevents, out_kind);
+    if (!events || nevents_events != nch * WCSIM_BATCH_STAGE_EVENTS)
+        return fail(WCSIM_E_INVALID, "need WCSIM_BATCH_STAGE_EVENTS events per chunk");
+    for (int32_t i = 0; i < nevents_events; ++i)
+        if (!events[i])
+            return fail(WCSIM_E_INVALID, "NULL event in the event array");
+    return simulate_batch(planes, depos, n, event_ids, nevents, outs, out_kind, workspace, stream,
+                          (const hipEvent_t *)events);
 }
 
 wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t *capacity,
@@ -1201,35 +1365,44 @@ wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t 
     b->capacity.assign(capacity, capacity + nevents);
     b->kind = out_kind;
     b->ws = (char *)workspace;
-    b->groups = schedule_groups(planes, nevents);
-    size_t host_bytes = 0;
-    for (const auto &g : b->groups) {
-        b->layouts.push_back(plan_batch(planes, capacity, g, out_kind));
-        b->host_off.push_back(host_bytes);
-        host_bytes += align_up(b->layouts.back().off_raster);
-    }
+    b->plan = plan_batch(planes, capacity, nevents, out_kind);
     auto bail = [&](wcsim_status st) {
         destroy_batch(b);
         return st;
     };
     hipError_t e;
-    if ((e = hipHostMalloc(&b->pinned, std::max<size_t>(host_bytes, 256), hipHostMallocDefault)) !=
-        hipSuccess)
+    if ((e = hipHostMalloc(&b->pinned, std::max<size_t>(b->plan.tables_total, 256),
+                           hipHostMallocDefault)) != hipSuccess)
         return bail(check_hip(e, "hipHostMalloc(batch tables)"));
     if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess)
         return bail(check_hip(e, "hipEventCreate"));
-    hipStream_t cs = nullptr;
-    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
-        return bail(check_hip(e, "hipStreamCreate"));
+    // capture on two private streams (default priority), joined at the end
+    hipStream_t cs = nullptr, fs = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    auto release = [&]() {
+        for (hipEvent_t x : ev)
+            if (x)
+                (void)hipEventDestroy(x);
+        if (fs)
+            (void)hipStreamDestroy(fs);
+        if (cs)
+            (void)hipStreamDestroy(cs);
+    };
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&fs, hipStreamNonBlocking);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        release();
+        return bail(check_hip(e, "batch capture streams"));
+    }
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (size_t k = 0; e == hipSuccess && k < b->groups.size(); ++k) {
-        const BatchLayout &L = b->layouts[k];
-        e = hipMemcpyAsync(b->ws, (char *)b->pinned + b->host_off[k], L.off_raster,
-                           hipMemcpyHostToDevice, cs);
-        if (e == hipSuccess)
-            e = launch_batch_group(planes[b->groups[k][0]], L, b->ws, cs);
-    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws, b->pinned, b->plan.tables_total, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess)
+        e = launch_pipeline(b->plan, planes, b->ws, cs, fs, ev, ev + 2);
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess)
         e = e2;
@@ -1237,7 +1410,7 @@ wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t 
         e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
     if (graph)
         (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cs);
+    release();
     if (e != hipSuccess)
         return bail(check_hip(e, "batch graph capture"));
     *out = b;
@@ -1258,11 +1431,9 @@ wcsim_status wcsim_batch_run(wcsim_batch *b, const wcsim_depo *const *depos, con
         if (n[e] > b->capacity[(size_t)e])
             return fail(WCSIM_E_INVALID, "event " + std::to_string(e) + " exceeds its capacity");
     WCS_HIP(hipEventSynchronize(b->done));  // the previous run has read the tables
-    for (size_t k = 0; k < b->groups.size(); ++k) {
-        BatchLayout L = b->layouts[k];
-        fill_descriptors(L, b->groups[k], b->ws, depos, n, event_ids, outs);
-        pack_tables(L, (char *)b->pinned + b->host_off[k]);
-    }
+    BatchPlan bp = b->plan;
+    fill_descriptors(bp, b->ws, depos, n, event_ids, outs);
+    pack_tables(bp, (char *)b->pinned);
     WCS_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
     WCS_HIP(hipEventRecord(b->done, (hipStream_t)stream));
     return WCSIM_OK;

@@ -1073,14 +1073,19 @@ bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b)
 }
 
 hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
-                                 int nblk_p, int nblk_c, hipStream_t s)
+                                 int nblk_p, int nblk_c, hipStream_t s, const hipEvent_t *ev)
 {
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     hipError_t e;
-    if ((e = rows_r2c_any<true>(pl, R2CIo{}, bt, (unsigned)nblk_r, s)) != hipSuccess)
+    if ((e = rows_r2c_any<true>(pl, R2CIo{}, bt, (unsigned)nblk_r, s)) != hipSuccess ||
+        (e = mark(0)) != hipSuccess)
         return e;
-    if ((e = pitch_any<true>(pl, PitchIo{}, bt, (unsigned)nblk_p, 1.0f, s)) != hipSuccess)
+    if ((e = pitch_any<true>(pl, PitchIo{}, bt, (unsigned)nblk_p, 1.0f, s)) != hipSuccess ||
+        (e = mark(1)) != hipSuccess)
         return e;
-    return rows_c2r_any<true>(pl, C2RIo{}, bt, (unsigned)nblk_c, s);
+    if ((e = rows_c2r_any<true>(pl, C2RIo{}, bt, (unsigned)nblk_c, s)) != hipSuccess)
+        return e;
+    return mark(2);
 }
 
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind)

@@ -699,16 +699,31 @@ __global__ __launch_bounds__(kSchedThreads) void k_tile_sums(const int32_t *tile
         block_tot[blockIdx.x] = make_int2(tot_t, tot_c);
 }
 
+// Exclusive scan of the block totals in place (one workgroup), so that each
+// schedule block reads its two bases with one load.
+__global__ __launch_bounds__(kSchedThreads) void k_scan_block_tot(int2 *block_tot, int nb)
+{
+    __shared__ int sh[kSchedThreads / 64];
+    int carry_t = 0, carry_c = 0;
+    for (int b0 = 0; b0 < nb; b0 += kSchedThreads) {
+        const int i = b0 + threadIdx.x;
+        const int2 v = (i < nb) ? block_tot[i] : make_int2(0, 0);
+        int tot_t, tot_c;
+        const int ex_t = block_exclusive_scan<int>(v.x, sh, &tot_t);
+        const int ex_c = block_exclusive_scan<int>(v.y, sh, &tot_c);
+        if (i < nb)
+            block_tot[i] = make_int2(ex_t + carry_t, ex_c + carry_c);
+        carry_t += tot_t;
+        carry_c += tot_c;
+    }
+}
+
 __global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_count, int ntiles,
-                                                                const int2 *block_tot,
+                                                                const int2 *block_base,
                                                                 int4 *items, int32_t *counters)
 {
     __shared__ int sh[kSchedThreads / 64];
-    int base_t = 0, base_c = 0;
-    for (int b = 0; b < (int)blockIdx.x; ++b) {
-        base_t += block_tot[b].x;
-        base_c += block_tot[b].y;
-    }
+    const int base_t = block_base[blockIdx.x].x, base_c = block_base[blockIdx.x].y;
     const int first = blockIdx.x * kSchedTiles + threadIdx.x * kSchedPer;
     int cnt[kSchedPer];
     int st = 0, sc = 0;
@@ -1329,6 +1344,8 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
 // Blocks of the record kernel that clear the grid: two per CU keep HBM
 // writes busy while the other blocks build records.
 constexpr int kClearBlocks = 512;
+constexpr int kMaxClearBlocks = 4096;
+constexpr int64_t kClearPerBlock = 28125;  // float4 words: 512 blocks for 9600 x 6000 floats
 
 static size_t sched_blocks_of(int64_t ntiles)
 {
@@ -1425,9 +1442,17 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     const unsigned sched_blocks = (unsigned)sched_blocks_of(ntiles);
     hipLaunchKernelGGL(k_tile_sums, dim3(sched_blocks), dim3(kSchedThreads), 0, s, w.tile_count,
                        (int)ntiles, w.block_tot);
+    hipLaunchKernelGGL(k_scan_block_tot, dim3(1), dim3(kSchedThreads), 0, s, w.block_tot,
+                       (int)sched_blocks);
     hipLaunchKernelGGL(k_tile_schedule, dim3(sched_blocks), dim3(kSchedThreads), 0, s,
                        w.tile_count, (int)ntiles, w.block_tot, w.items, w.counters);
-    const int nclr = (int)std::min<int64_t>(kClearBlocks, std::max<int64_t>(n4 / 4096, 1));
+    // clearing blocks: kClearBlocks for a detector-scale plane (230 MB), more
+    // for the larger grid sets of batches, at most one per 64 KB
+    const int nclr = (int)std::min<int64_t>(
+        kMaxClearBlocks,
+        std::max<int64_t>(std::max<int64_t>(n4 / kClearPerBlock,
+                                            std::min<int64_t>(kClearBlocks, n4 / 4096)),
+                          1));
     hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64) + nclr), dim3(64), 0, s, e0, bt,
                        n, w.depo_tile, w.depo_slot, w.tile_count, w.records, (float4 *)grid, n4,
                        nclr);
@@ -1471,10 +1496,10 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
 
 hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
                                int64_t ntiles_total, const RasterWork &w, void *grids,
-                               size_t grid_bytes, hipStream_t s)
+                               size_t grid_bytes, hipStream_t s, const hipEvent_t *ev)
 {
     return raster_sequence<true>(pl, EventCtx{}, bt, n_total, ntiles_total, w, grids, grid_bytes,
-                                 s, nullptr);
+                                 s, ev);
 }
 
 }  // namespace wcs

@@ -215,9 +215,10 @@ RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n_total, int64
                                    void *base);
 // `grids` (grid_bytes, all events' grids, contiguous) are cleared by the
 // sequence itself.
+// `ev` (nullable): 3 stage marks as for launch_raster_fused.
 hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
                                int64_t ntiles_total, const RasterWork &w, void *grids,
-                               size_t grid_bytes, hipStream_t s);
+                               size_t grid_bytes, hipStream_t s, const hipEvent_t *ev = nullptr);
 
 // FFT convolution passes
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind);
@@ -230,8 +231,10 @@ hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void 
 size_t response_work_bytes(const wcsim_plane *pl);
 // Batched convolution: the three passes over every event of the tables;
 // nblk_* = total workgroups of each pass (the last entries of the bases).
+// `ev` (nullable): 3 events recorded after passes A, B and C.
 hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
-                                 int nblk_p, int nblk_c, hipStream_t s);
+                                 int nblk_p, int nblk_c, hipStream_t s,
+                                 const hipEvent_t *ev = nullptr);
 int rows_blocks(int nrows);                       // workgroups of a tick-axis pass
 int pitch_blocks_total(const wcsim_plane *pl);    // workgroups of the pitch pass
 bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b);

@@ -107,6 +107,8 @@ _SIGS = {
     "wcsim_workspace_invalid_count": (_st, [_P, _P, _P]),
     "wcsim_batch_workspace_bytes": (_sz, [_P, _P, _i32, _i32]),
     "wcsim_simulate_batch": (_st, [_P, _P, _P, _P, _i32, _P, _i32, _P, _P]),
+    "wcsim_batch_chunk_count": (_i32, [_P, _P, _i32, _i32]),
+    "wcsim_simulate_batch_profiled": (_st, [_P, _P, _P, _P, _i32, _P, _i32, _P, _P, _P, _i32]),
     "wcsim_batch_create": (_st, [_P, _P, _i32, _i32, _P, _P]),
     "wcsim_batch_run": (_st, [_P, _P, _P, _P, _P, _P]),
     "wcsim_batch_destroy": (None, [_P]),
@@ -266,13 +268,14 @@ class Patches:
         _check(_lib.wcsim_patches_count(handle, ctypes.byref(n), ctypes.byref(nv)))
         self.ndepos, self.nvalues = n.value, nv.value
 
-    def to_host(self):
+    def to_host(self, values: bool = True):
+        """(meta [n][4] int32, offsets [n + 1] int64, values float32 or None)."""
         meta = np.zeros((self.ndepos, 4), np.int32)
         offs = np.zeros(self.ndepos + 1, np.int64)
-        vals = np.zeros(max(self.nvalues, 1), np.float32)
+        vals = np.zeros(max(self.nvalues, 1), np.float32) if values else None
         _check(_lib.wcsim_patches_copy_to_host(self.handle, meta.ctypes.data, offs.ctypes.data,
-                                               vals.ctypes.data))
-        return meta, offs, vals[:self.nvalues]
+                                               vals.ctypes.data if values else None))
+        return meta, offs, (vals[:self.nvalues] if values else None)
 
     def destroy(self):
         if self.handle:
@@ -461,6 +464,39 @@ def simulate_batch(planes, depos_list, event_ids, outs, kind: int = OUT_WIRE,
                                     depos_list[0].device)
     _check(_lib.wcsim_simulate_batch(arr_p, arr_d, arr_n, arr_e, ne, arr_o, kind,
                                      _dev_ptr(workspace, what="workspace"), _stream(stream)))
+    return outs
+
+
+BATCH_STAGE_EVENTS = 8
+BATCH_STAGE_NAMES = ("bin_depos", "raster_tiles", "raster_large", None, "fft_ticks", "conv_pitch",
+                     "ifft_ticks")
+
+
+def batch_chunk_count(planes, ns, kind: int = OUT_WIRE) -> int:
+    arr_p = (ctypes.c_void_p * len(planes))(*[p.handle.value for p in planes])
+    arr_n = (ctypes.c_int64 * len(ns))(*[int(v) for v in ns])
+    return int(_lib.wcsim_batch_chunk_count(arr_p, arr_n, len(planes), kind))
+
+
+def simulate_batch_profiled(planes, depos_list, event_ids, outs, events, kind: int = OUT_WIRE,
+                            workspace: torch.Tensor | None = None, stream=None):
+    """simulate_batch recording BATCH_STAGE_EVENTS raw hipEvent_t handles per
+    chunk (see wcsim_simulate_batch_profiled)."""
+    ne = len(planes)
+    for d in depos_list:
+        _dev_ptr(d, torch.float64, "depos")
+    arr_p = (ctypes.c_void_p * ne)(*[p.handle.value for p in planes])
+    arr_d = (ctypes.c_void_p * ne)(*[d.data_ptr() for d in depos_list])
+    arr_n = (ctypes.c_int64 * ne)(*[d.shape[0] for d in depos_list])
+    arr_e = (ctypes.c_uint64 * ne)(*[int(e) & (2**64 - 1) for e in event_ids])
+    arr_o = (ctypes.c_void_p * ne)(*[_dev_ptr(o, torch.float32, "out") for o in outs])
+    arr_v = (ctypes.c_void_p * len(events))(*events)
+    if workspace is None:
+        workspace = batch_workspace(planes, [d.shape[0] for d in depos_list], kind,
+                                    depos_list[0].device)
+    _check(_lib.wcsim_simulate_batch_profiled(arr_p, arr_d, arr_n, arr_e, ne, arr_o, kind,
+                                              _dev_ptr(workspace, what="workspace"),
+                                              _stream(stream), arr_v, len(events)))
     return outs
 
 

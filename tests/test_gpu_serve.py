@@ -89,3 +89,47 @@ def test_serve_budget_serialises_and_rejects(mods):
     tiny = serve.Server(W.physics(True), hbm_budget=min(need) // 2)
     res = tiny.serve(reqs[:2])
     assert all(r.error is not None for r in res)
+
+
+def test_serve_isolates_invalid_requests_and_cancellations(mods):
+    """Failure injection: a request with a non-finite depo, one with a depo
+    behind its plane and one over the budget fail alone; a request cancelled
+    while queued and one cancelled while its group runs return no output; all
+    other requests equal their results alone."""
+    serve, wcsim = mods
+    print("case: serve failure injection", flush=True)
+    reqs = _requests(10, seed=21)
+    reqs[2]["depos"] = reqs[2]["depos"].copy()
+    reqs[2]["depos"][5, 1] = np.nan
+    reqs[6]["depos"] = reqs[6]["depos"].copy()
+    reqs[6]["depos"][0, 0] = -10.0
+    big = _requests(1, seed=5)[0]
+    rng = np.random.default_rng(3)
+    big["depos"] = W.clipped_track_depos(rng, 400_000, (W.BOX_X / 4, W.BOX_Y, 1500.0))
+    big["event_id"] = 99
+    reqs = [big] + reqs
+    srv = serve.Server(W.physics(True), slots=1, max_batch=1, depth=1)
+    # request 0 (large) runs first and is cancelled 1 ms in, while it runs;
+    # request 4 is cancelled while still queued behind it
+    res = srv.serve(reqs, None, cancel_at={0: 1e-3, 4: 0.0})
+    assert res[3].error is not None and "non-finite" in res[3].error
+    assert res[7].error is not None and "behind" in res[7].error
+    assert res[0].error == "cancelled" and not res[0].outputs
+    assert res[4].error == "cancelled" and not res[4].outputs
+    for k in (1, 2, 5, 6, 8, 9, 10):
+        assert res[k].error is None
+        for got, ref in zip(res[k].outputs, _alone(wcsim, srv, reqs[k])):
+            assert normwise(got, ref) <= 1e-5
+
+
+def test_serve_plain_baseline_matches(mods):
+    """The per-request baseline on the same stream gives the same results."""
+    serve, wcsim = mods
+    print("case: serve plain baseline", flush=True)
+    reqs = _requests(6, seed=31)
+    srv = serve.Server(W.physics(True), slots=2, max_batch=4)
+    res = srv.serve_plain(reqs)
+    for r, q in zip(res, reqs):
+        assert r.error is None
+        for got, ref in zip(r.outputs, _alone(wcsim, srv, q)):
+            assert normwise(got, ref) <= 1e-5
