@@ -114,3 +114,64 @@ def test_graph_batch_replays(ws):
     with pytest.raises(ws.WcsimError):
         b.run([torch.cat([d, d]) for d in deps], [0, 1, 2], outs)
     b.destroy()
+
+
+def _oracle_grid(O, dep, phys, pl, ev, threads=8):
+    """The oracle's grid of one event, its depos rasterized in contiguous parts
+    by several threads (each keyed by the depos' indices in the event, so the
+    sum is the event's grid), the patches scattered into one grid."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    parts = np.array_split(np.arange(dep.shape[0]), threads)
+    with ThreadPoolExecutor(threads) as pool:
+        res = list(pool.map(lambda p: O.rasterize(dep[p], phys, pl, ev, ids=p), parts))
+    shift = np.cumsum([0] + [v.size for _, v, _ in res[:-1]])
+    meta = np.concatenate([m + np.array([0, 0, 0, 0, s]) for (m, _, _), s in zip(res, shift)])
+    return O.scatter(meta, np.concatenate([v for _, v, _ in res]), pl)
+
+
+def test_batch_workload_full_size_against_oracle(ws):
+    """The 64-event batch workload itself, run by the captured batched form in
+    the benchmark's launch configuration (tuned 640 x 16 pitch schedule): the
+    largest 960-wire event (693,391 depos) and the largest 100-wire event
+    (553,172 depos) against the oracle over the whole wire output; the same
+    two events' grids, from a batch of planes with a delta response and pitch
+    output (whose output is the grid), against the oracle's grids."""
+    print("case: 64-event batch, full size, against the oracle", flush=True)
+    evs = W.batch_events(nevents=64)
+    phys = W.physics(True)
+    sched = {"fft_pitch": 640, "freq_chunk": 16}
+    planes = {nw: ws.Plane(W.plane(nw, 6000), phys, W.response("unipolar"), schedule=sched)
+              for nw in sorted({e["plane"]["nwires"] for e in evs})}
+    pl = [planes[e["plane"]["nwires"]] for e in evs]
+    deps = [torch.from_numpy(e["depos"]).cuda() for e in evs]
+    ids = [e["event_id"] for e in evs]
+    outs = [torch.empty((p.nwires, p.nticks), device="cuda") for p in pl]
+    b = ws.Batch(pl, [d.shape[0] for d in deps])
+    b.run(deps, ids, outs)
+    torch.cuda.synchronize()
+    picks = []
+    for nw in (960, 100):
+        mine = [k for k, e in enumerate(evs) if e["plane"]["nwires"] == nw]
+        picks.append(max(mine, key=lambda k: evs[k]["depos"].shape[0]))
+    assert all(evs[k]["depos"].shape[0] >= 500_000 for k in picks)
+    grids = {}
+    for k in picks:
+        e = evs[k]
+        print("  event %d: %d wires, %d depos" % (k, e["plane"]["nwires"], e["depos"].shape[0]),
+              flush=True)
+        G = _oracle_grid(O, e["depos"], phys, e["plane"], e["event_id"])
+        grids[k] = G
+        R = e["response"].astype(np.float64)
+        ref = O.wire_rows(O.convolve(G, R, R.shape[0] // 2, workers=8), 10)
+        assert normwise(outs[k].cpu().numpy(), ref) <= 1e-4
+    b.destroy()
+    # grids: the same two events through a batch with a delta response
+    delta = np.zeros((1, 1), np.float32)
+    delta[0, 0] = 1.0
+    dpl = [ws.Plane(evs[k]["plane"], phys, delta, r0=0) for k in picks]
+    gouts = [torch.empty((p.npitch, p.nticks), device="cuda") for p in dpl]
+    ws.simulate_batch(dpl, [deps[k] for k in picks], [ids[k] for k in picks], gouts,
+                      kind=ws.OUT_PITCH)
+    for k, g in zip(picks, gouts):
+        assert normwise(g.cpu().numpy(), grids[k]) <= 1e-5

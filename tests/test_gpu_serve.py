@@ -133,3 +133,48 @@ def test_serve_plain_baseline_matches(mods):
         assert r.error is None
         for got, ref in zip(r.outputs, _alone(wcsim, srv, q)):
             assert normwise(got, ref) <= 1e-5
+
+
+def test_served_requests_against_oracle(mods):
+    """Three requests of the serving workload's own mix (one of three planes),
+    served inside the whole 64-request mix: sampled wire waveforms of every
+    plane against the oracle.  For each sampled wire (the two strongest, two
+    at random) the oracle takes every depo whose window can reach that wire's
+    response reach (a superset by mean pitch bin), keyed by its index in the
+    request, and evaluates the defining convolution sum at every 7th tick."""
+    from oracle import oracle as O
+
+    serve, wcsim = mods
+    print("case: served requests against the oracle", flush=True)
+    reqs = W.serve_requests(nreq=64)
+    phys = W.physics(True)
+    srv = serve.Server(phys, slots=4, max_batch=8)
+    res = srv.serve(reqs)
+    assert all(r.error is None for r in res)
+    sizes = [r["depos"].shape[0] for r in reqs]
+    three = [k for k, r in enumerate(reqs) if len(r["planes"]) == 3 and sizes[k] < 600_000]
+    others = [k for k, r in enumerate(reqs) if len(r["planes"]) < 3 and sizes[k] < 600_000]
+    picks = [max(three, key=lambda k: sizes[k])] + sorted(others, key=lambda k: -sizes[k])[:2]
+    rng = np.random.default_rng(41)
+    for k in picks:
+        r = reqs[k]
+        dep = r["depos"]
+        print("  request %d: %d planes, %d depos" % (k, len(r["planes"]), dep.shape[0]),
+              flush=True)
+        for pl, R, out in zip(r["planes"], r["responses"], res[k].outputs):
+            Rp, r0, nimp = R.shape[0], R.shape[0] // 2, pl["nimpact"]
+            dp = pl["pitch"] / nimp
+            mu = ((dep[:, 1] * pl["dir_y"] + dep[:, 2] * pl["dir_z"]) - pl["pitch_origin"]) / dp
+            scale = np.abs(out).max()
+            assert scale > 0
+            wires = list(np.argsort(-np.abs(out).max(axis=1))[:2])
+            wires += list(rng.integers(0, pl["nwires"], 2))
+            ticks = np.arange(0, pl["nticks"], 7)
+            for wi in wires:
+                p = int(wi) * nimp + nimp // 2
+                lo, hi = p + r0 - (Rp - 1), p + r0
+                idx = np.nonzero((mu >= lo - 40) & (mu <= hi + 40))[0]
+                G = O.grid(dep[idx], phys, pl, r["event_id"], ids=idx)
+                pts = np.stack([np.full(ticks.shape, p), ticks], axis=1)
+                ref = O.convolve_points(G, R.astype(np.float64), r0, pts)
+                assert np.abs(out[int(wi), ticks] - ref).max() / scale <= 1e-4, (k, int(wi))
