@@ -34,6 +34,13 @@ constexpr double kSqrt2 = 1.41421356237309504880;  // sqrt(2), correctly rounded
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
 
+// a ^ b ^ c in one gfx950 three-input bitwise instruction (truth table 0x96:
+// the result bit is set when an odd number of input bits are)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -44,8 +51,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         }
         const uint64_t a = (uint64_t)kPhiloxM0 * c.x;
         const uint64_t b = (uint64_t)kPhiloxM1 * c.z;
-        c = make_uint4((uint32_t)(b >> 32) ^ c.y ^ k0, (uint32_t)b, (uint32_t)(a >> 32) ^ c.w ^ k1,
-                       (uint32_t)a);
+        c = make_uint4(xor3((uint32_t)(b >> 32), c.y, k0), (uint32_t)b,
+                       xor3((uint32_t)(a >> 32), c.w, k1), (uint32_t)a);
     }
     return c;
 }
@@ -173,60 +180,6 @@ __device__ __forceinline__ double seg_sum(double v)
     return v;
 }
 
-// DPP lane move within rows of 16 lanes (every source lane exists).
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
-// FP64 sum over the wavefront, the same value in every lane: quad swaps and
-// row mirrors (DPP) give every lane its 16-lane row's sum, then the rows are
-// combined by swapping row halves and wave halves between lanes (gfx950
-// permlane swaps), so no value passes through scalar registers.  Each 64-bit
-// value moves as two 32-bit halves.  The summation order is fixed, so the
-// result is reproducible, and a + b = b + a makes it identical in all lanes.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move_d(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)b >> 32), CTRL, 0xf,
-                                               0xf, false);
-    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-}
-
-// v + (the value of the lane `width` away, across a 16- or 32-lane boundary):
-// a permlane swap of a register with itself yields its own lane's value in one
-// result and the partner's in the other.
-template <int WIDTH>
-__device__ __forceinline__ double swap_add_d(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const uint32_t lo = (uint32_t)b, hi = (uint32_t)((uint64_t)b >> 32);
-    if (WIDTH == 16) {
-        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        return __longlong_as_double((long long)(((uint64_t)h[0] << 32) | l[0])) +
-               __longlong_as_double((long long)(((uint64_t)h[1] << 32) | l[1]));
-    } else {
-        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        return __longlong_as_double((long long)(((uint64_t)h[0] << 32) | l[0])) +
-               __longlong_as_double((long long)(((uint64_t)h[1] << 32) | l[1]));
-    }
-}
-
-__device__ __forceinline__ double wave_sum_uniform_d(double v)
-{
-    v += dpp_move_d<0xb1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_move_d<0x4e>(v);   // quad_perm [2,3,0,1]
-    v += dpp_move_d<0x141>(v);  // row_half_mirror
-    v += dpp_move_d<0x140>(v);  // row_mirror
-    v = swap_add_d<16>(v);      // rows 0+1 and 2+3
-    return swap_add_d<32>(v);   // all four rows
-}
-
 // q / S in FP64 for S > 0 of ordinary magnitude (a patch total): hardware
 // reciprocal refined by two Newton steps, then the product, within a few FP64
 // ulps of the quotient -- far below the float32 rounding the factor gets.
@@ -236,6 +189,39 @@ __device__ __forceinline__ double div_pos_d(double q, double S)
     r = fma(fma(-S, r, 1.0), r, r);
     r = fma(fma(-S, r, 1.0), r, r);
     return q * r;
+}
+
+// Inclusive prefix sum over the wavefront's lanes in FP64: within each row of
+// 16 lanes by shifts of 1, 2, 4 and 8 lanes, then each row adds the last lane
+// of the rows before it (row broadcasts of lanes 15 and 31).  Fixed order.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_shift_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)b >> 32), CTRL, ROWS,
+                                               0xf, true);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double wave_incl_scan_d(double v)
+{
+    v += dpp_shift_d<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_shift_d<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_shift_d<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_shift_d<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_shift_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_shift_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Electrons of a depo that survive the drift (electron lifetime tau; an
@@ -888,87 +874,26 @@ constexpr int region_cols()
     return TT + kHaloT;
 }
 
-// Header of one record, read from the lanes that hold its words (lane w holds
-// word w): window, depo, charge and the (row, tick quad) work items.
-struct PatchHdr {
-    int lo_p, lo_t, d, m, qlo, nq, items;
-    float q;   // charge, float32 (the bin values)
-    double qd; // charge, FP64 (the renormalisation)
-};
-
-__device__ __forceinline__ PatchHdr patch_header(float cur)
-{
-    const int w = __float_as_int(cur);
-    PatchHdr h;
-    h.lo_p = __builtin_amdgcn_readlane(w, kHLoP);
-    h.lo_t = __builtin_amdgcn_readlane(w, kHLoT);
-    const int n_p = __builtin_amdgcn_readlane(w, kHNp);
-    const int n_t = __builtin_amdgcn_readlane(w, kHNt);
-    h.d = __builtin_amdgcn_readlane(w, kHDepo);
-    const uint32_t qlo = (uint32_t)__builtin_amdgcn_readlane(w, kHQlo);
-    const uint32_t qhi = (uint32_t)__builtin_amdgcn_readlane(w, kHQhi);
-    h.qd = __longlong_as_double((long long)(((uint64_t)qhi << 32) | qlo));
-    h.q = (float)h.qd;
-    h.m = __builtin_amdgcn_readlane(w, kHMq);
-    h.qlo = quad_of(h.lo_t);
-    h.nq = quad_of(h.lo_t + n_t - 1) - h.qlo + 1;
-    h.items = n_p * h.nq;
-    return h;
-}
-
-// Word w of the record held by the wavefront (lane w holds word w).
-__device__ __forceinline__ float rec_word(int rec_bits, int w)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(w << 2, rec_bits));
-}
-
-// Work item it = (window row i, tick quad qlo + qq) of one patch: the four
-// bins' values (charge times weights, fluctuated if asked) and the float4
-// cell of the region they go to (-1: not deposited).  The weights are read
-// from the lanes that hold them (no LDS staging, no barrier per patch).
-template <int RP, int RT, bool FLUCT>
-__device__ __forceinline__ void patch_item(const PatchHdr &h, int it, int rec_bits, int p0,
-                                           int c0, uint32_t key0, uint32_t key1, uint32_t event,
-                                           float F[4], int &cell)
-{
-    const bool valid = it < h.items;
-    const int i = div_small(it, h.m);
-    const int qq = valid ? it - (int)__umul24(i, h.nq) : 0;
-    const int qd = h.qlo + qq;
-    const int r = h.lo_p + i - p0, c = 4 * qd - c0;
-    cell = (valid && (unsigned)r < (unsigned)RP && (unsigned)c <= (unsigned)(RT - 4))
-               ? (r * RT + c) >> 2
-               : -1;
-    // reads at in-range indexes, then a select: no branches
-    const float wp_raw = rec_word(rec_bits, kRecWp + (valid ? i : 0));
-    const float wp = valid ? wp_raw : 0.0f;
-    float wt[4];
-#pragma unroll
-    for (int mm = 0; mm < 4; ++mm)
-        wt[mm] = rec_word(rec_bits, kRecWt + 4 * qq + mm);
-    if (FLUCT) {
-        const uint4 rr = philox4x32_10(
-            make_uint4((uint32_t)qd, (uint32_t)(h.lo_p + i), (uint32_t)h.d, event), key0, key1);
-        float z[4];
-        box_muller(rr.x, rr.y, z[0], z[1]);
-        box_muller(rr.z, rr.w, z[2], z[3]);
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm)
-            F[mm] = fluct_value(h.q, wp * wt[mm], z[mm]);
-    } else {
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm)
-            F[mm] = h.q * (wp * wt[mm]);
-    }
-}
+// Patches per batch of items: consecutive patches of a work item whose (row,
+// tick quad) items number at most kBatchItems are drawn together, their
+// items laid out flat over kBatchItems / 64 passes of the wavefront, so that
+// the lanes of a pass serve several small patches instead of one.
+constexpr int kBatchItems = 64 * kFluctItems;
 
 // One wavefront per work item (tile, chunk of <= kChunk depos), rasterizing
-// one patch at a time into its own LDS copy of the tile region (tile + halo).
-// The bins of one patch are distinct, so the deposits are plain
-// read-add-write LDS accesses; no other wavefront touches the region.  The
-// region's non-zero cells are then added to the grid with float atomics.
-// (A wavefront that went on to further items would, before using their
-// loads, wait for its atomics: global loads and stores share one counter.)
+// its patches into its own LDS copy of the tile region (tile + halo).  The
+// patches are taken in batches of consecutive patches whose (row, tick quad)
+// items fit kFluctItems passes of 64 lanes; the items of a batch are laid out
+// flat (patch after patch), each lane finds its item's patch from the
+// patches' item offsets, reads the patch's header from the lane that holds it
+// (lane k holds patch k) and its weights from the depo record.  With
+// fluctuation every item's four values are added, in FP64, to its patch's
+// total in LDS; once the batch is drawn, each patch's factor q / S is formed
+// in FP64 by the lane holding it, and every value is rescaled and deposited.
+// The bins of one patch are distinct, so depositing the batch one patch at a
+// time makes every deposit a plain read-add-write LDS access (two patches of
+// a batch may cover the same cell).  No other wavefront touches the region.
+// The region's non-zero cells are then added to the grid with float atomics.
 template <int TP, int TT, bool B>
 __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
                                                      const int4 *__restrict__ items,
@@ -978,16 +903,20 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     constexpr int RP = TP + kHaloP, RT = region_cols<TT>();
     static_assert(RT % 4 == 0, "region rows must hold whole quads");
     __shared__ float4 acc4[RP * RT / 4];
+    __shared__ double xsum[kBatchItems];  // prefix sums of a batch's fluctuated item totals
     if ((int)blockIdx.x >= counters[2])
         return;
     const int4 item = items[blockIdx.x];
     const int tile = item.x, beg = item.y, end = item.z;
+    const int K = end - beg;  // patches of the work item (<= kChunk)
     const int lane = threadIdx.x;
-    float next = records[(int64_t)beg * kRecWords + lane];
-    // window of patch beg + lane (lanes past the chunk: empty)
-    int4 win = make_int4(INT_MAX, INT_MAX, 0, 0);
-    if (beg + lane < end)
-        win = *(const int4 *)(records + (int64_t)(beg + lane) * kRecWords);  // lo_p lo_t n_p n_t
+    // lane k < K holds the header of patch k: window, depo index, charge
+    int4 win = make_int4(INT_MAX, INT_MAX, 0, 0), hdr = make_int4(0, 0, 0, 0);
+    if (lane < K) {
+        const int4 *rec = (const int4 *)(records + (int64_t)(beg + lane) * kRecWords);
+        win = rec[0];  // lo_p lo_t n_p n_t
+        hdr = rec[1];  // depo, q low word, q high word, quad-count magic
+    }
     const EventCtx &E = B ? bt.ev[find_event(bt.tile_base, bt.nev, tile)] : e0;
     const PlaneParams P = E.kp;
     const int local = tile - E.tile_base;
@@ -1016,69 +945,147 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
         acc4[r * (RT / 4) + bq0 + br0 * (RT / 4) + (x - r * bnq)] =
             make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
+    // per-patch item counts and their inclusive prefix over the lanes
+    const int pqlo = quad_of(win.y);
+    const int pnq = (lane < K) ? quad_of(win.y + win.w - 1) - pqlo + 1 : 0;
+    const int pitems = (lane < K) ? win.z * pnq : 0;
+    int incl = pitems;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o)
+            incl += u;
+    }
+    const double pq = __longlong_as_double(
+        (long long)(((uint64_t)(uint32_t)hdr.z << 32) | (uint32_t)hdr.y));  // patch charge, FP64
+    const float pqf = (float)pq;
 
     wave_lds_sync();  // the cleared region is visible to every lane
 
-    for (int k = beg; k < end; ++k) {
-        const float cur = next;
-        const int cur_bits = __float_as_int(cur);
-        // the next record is loaded while this patch is rasterized
-        if (k + 1 < end)
-            next = records[(int64_t)(k + 1) * kRecWords + lane];
-        const PatchHdr h = patch_header(cur);
-
-        // nb = (row, quad) passes of this patch (uniform): passes b >= nb are
-        // skipped whole, with no zero-filled values to sum, scale or deposit
-        const int nb = (h.items + 63) >> 6;
+    int kb = 0;  // first patch of the batch (uniform)
+    while (kb < K) {
+        const int base = __builtin_amdgcn_readlane(incl - pitems, kb);
+        // the batch: patches kb .. ke, the longest run whose items fit
+        const uint64_t fits = __ballot(lane >= kb && lane < K && incl - base <= kBatchItems);
+        const int ke = 63 - __builtin_clzll(fits);
+        const int nitems = __builtin_amdgcn_readlane(incl, ke) - base;
+        const int npass = (nitems + 63) >> 6;
         float F[kFluctItems][4];
-        int cell[kFluctItems];
-        if (P.fluct) {
-            double acc = 0.0;
-#pragma unroll
-            for (int b = 0; b < kFluctItems; ++b)
-                if (b < nb) {
-                    patch_item<RP, RT, true>(h, lane + 64 * b, cur_bits, p0, c0, P.key0,
-                                             P.key1, E.event, F[b], cell[b]);
-                    acc += ((double)F[b][0] + (double)F[b][1]) +
-                           ((double)F[b][2] + (double)F[b][3]);
-                }
-            // renormalise the patch to its charge: the patch total and the
-            // factor q / S in FP64, the factor rounded once to float32
-            const double S = wave_sum_uniform_d(acc);
-            if (S > 0.0) {
-                const float scale = (float)div_pos_d(h.qd, S);
-#pragma unroll
-                for (int b = 0; b < kFluctItems; ++b)
-                    if (b < nb)
-#pragma unroll
-                        for (int mm = 0; mm < 4; ++mm)
-                            F[b][mm] *= scale;
-            } else {
-                // every fluctuated bin is zero: deposit the mean
-#pragma unroll
-                for (int b = 0; b < kFluctItems; ++b)
-                    if (b < nb)
-                        patch_item<RP, RT, false>(h, lane + 64 * b, cur_bits, p0, c0, 0, 0, 0,
-                                                  F[b], cell[b]);
-            }
-        } else {
-#pragma unroll
-            for (int b = 0; b < kFluctItems; ++b)
-                if (b < nb)
-                    patch_item<RP, RT, false>(h, lane + 64 * b, cur_bits, p0, c0, 0, 0, 0,
-                                              F[b], cell[b]);
-        }
+        int cell[kFluctItems], kk[kFluctItems];
+        double carry = 0.0;  // total of the batch's earlier passes (uniform)
 #pragma unroll
         for (int b = 0; b < kFluctItems; ++b) {
-            if (b < nb && cell[b] >= 0) {
-                float4 a4 = acc4[cell[b]];
-                a4.x += F[b][0];
-                a4.y += F[b][1];
-                a4.z += F[b][2];
-                a4.w += F[b][3];
-                acc4[cell[b]] = a4;
+            cell[b] = -1;
+            kk[b] = 0;
+            if (b < npass) {
+                const int g = 64 * b + lane;  // flat item index within the batch
+                const bool valid = g < nitems;
+                // the item's patch: kb plus the patch ends at or below g
+                int k = kb;
+                for (int j = kb; j < ke; ++j)
+                    k += (g >= __builtin_amdgcn_readlane(incl, j) - base) ? 1 : 0;
+                kk[b] = k;
+                // the patch's header, from the lane holding it
+                const int lo_p = __shfl(win.x, k, 64), lo_t = __shfl(win.y, k, 64);
+                const int d = __shfl(hdr.x, k, 64), m = __shfl(hdr.w, k, 64);
+                const int nq = __shfl(pnq, k, 64);
+                const int first = __shfl(incl - pitems, k, 64) - base;
+                const float q = __shfl(pqf, k, 64);
+                const int it = valid ? g - first : 0;
+                const int i = div_small(it, m);
+                const int qq = it - (int)__umul24(i, nq);
+                const int qd = quad_of(lo_t) + qq;
+                const int r = lo_p + i - p0, c = 4 * qd - c0;
+                cell[b] = (valid && (unsigned)r < (unsigned)RP && (unsigned)c <= (unsigned)(RT - 4))
+                              ? (r * RT + c) >> 2
+                              : -1;
+                const float *rec = records + (int64_t)(beg + k) * kRecWords;
+                const float wp = valid ? rec[kRecWp + i] : 0.0f;
+                const float4 wt = *(const float4 *)(rec + kRecWt + 4 * qq);
+                const float w4[4] = {wt.x, wt.y, wt.z, wt.w};
+                if (P.fluct) {
+                    const uint4 rr = philox4x32_10(
+                        make_uint4((uint32_t)qd, (uint32_t)(lo_p + i), (uint32_t)d, E.event),
+                        P.key0, P.key1);
+                    float z[4];
+                    box_muller(rr.x, rr.y, z[0], z[1]);
+                    box_muller(rr.z, rr.w, z[2], z[3]);
+#pragma unroll
+                    for (int mm = 0; mm < 4; ++mm)
+                        F[b][mm] = fluct_value(q, wp * w4[mm], z[mm]);
+                    // the item's total in FP64, and its prefix over the batch
+                    const double t = valid ? ((double)F[b][0] + (double)F[b][1]) +
+                                                 ((double)F[b][2] + (double)F[b][3])
+                                           : 0.0;
+                    const double x = wave_incl_scan_d(t) + carry;
+                    xsum[g] = x;
+                    carry = readlane_d(x, 63);
+                } else {
+#pragma unroll
+                    for (int mm = 0; mm < 4; ++mm)
+                        F[b][mm] = q * (wp * w4[mm]);
+                }
             }
         }
+        if (P.fluct) {
+            // the lane of each patch of the batch forms its total S as the
+            // difference of the prefix sums at its last item and before its
+            // first, and its factor q / S, in FP64 (negative when the clamped
+            // total is zero: the patch keeps its mean)
+            wave_lds_sync();
+            float scale = 0.0f;
+            if (lane >= kb && lane <= ke) {
+                const int s0 = incl - pitems - base, s1 = incl - base;
+                const double S = xsum[s1 - 1] - (s0 > 0 ? xsum[s0 - 1] : 0.0);
+                scale = (S > 0.0) ? (float)div_pos_d(pq, S) : -1.0f;
+            }
+            wave_lds_sync();  // the next batch may overwrite the prefix sums
+#pragma unroll
+            for (int b = 0; b < kFluctItems; ++b) {
+                const float sc = __shfl(scale, kk[b], 64);
+                if (b < npass && cell[b] >= 0) {
+                    if (sc >= 0.0f) {
+#pragma unroll
+                        for (int mm = 0; mm < 4; ++mm)
+                            F[b][mm] *= sc;
+                    } else {
+                        // rare: every fluctuated bin of the patch is zero
+                        const int k = kk[b];
+                        const int g = 64 * b + lane;
+                        const int first = __shfl(incl - pitems, k, 64) - base;
+                        const int it = g - first;
+                        const int i = div_small(it, __shfl(hdr.w, k, 64));
+                        const int qq = it - (int)__umul24(i, __shfl(pnq, k, 64));
+                        const float *rec = records + (int64_t)(beg + k) * kRecWords;
+                        const float wp = rec[kRecWp + i];
+                        const float4 wt = *(const float4 *)(rec + kRecWt + 4 * qq);
+                        const float q = __shfl(pqf, k, 64);
+                        F[b][0] = q * (wp * wt.x);
+                        F[b][1] = q * (wp * wt.y);
+                        F[b][2] = q * (wp * wt.z);
+                        F[b][3] = q * (wp * wt.w);
+                    }
+                }
+            }
+        }
+        // Deposit, one patch of the batch at a time: the bins of one patch are
+        // distinct, but two patches of a batch may share cells.  A wavefront's
+        // LDS accesses complete in program order, so each round reads what the
+        // previous one wrote.
+        for (int k = kb; k <= ke; ++k) {
+#pragma unroll
+            for (int b = 0; b < kFluctItems; ++b) {
+                if (b < npass && cell[b] >= 0 && kk[b] == k) {
+                    float4 a4 = acc4[cell[b]];
+                    a4.x += F[b][0];
+                    a4.y += F[b][1];
+                    a4.z += F[b][2];
+                    a4.w += F[b][3];
+                    acc4[cell[b]] = a4;
+                }
+            }
+        }
+        kb = ke + 1;
     }
     wave_lds_sync();  // every deposit lands before the flush reads the region
     // Flush: consecutive lanes take consecutive ticks of a row, so that one
