@@ -3,7 +3,7 @@
  *
  * The library computes the three steps the paper's DepoTransform holds
  * (arXiv:2304.01841, Sec. 2):
- *   1. Rasterization: every ionization-electron group ("depo") is drifted to
+ *   1. Rasterization: every group of ionization electrons (a depo) is drifted to
  *      the response plane, diffused into 2-D Gaussian widths and binned into a
  *      patch of (pitch-impact bin x time tick) weights, optionally with
  *      statistical fluctuation (Sec. 2 step 1; random numbers Sec. 4.1);
@@ -58,7 +58,7 @@ typedef enum {
     WCSIM_OUT_PITCH = 1 /* [nwires*nimpact][nticks]: every pitch-impact row */
 } wcsim_out;
 
-/* One depo (Sec. 2 step 1, "ionization electron group"): x is the drift
+/* One depo (Sec. 2 step 1: a group of ionization electrons): x is the drift
  * coordinate, (y, z) the transverse position, t the deposition time and q the
  * number of electrons (q >= 0).  Array of structures, 40 bytes per depo. */
 typedef struct {

@@ -15,7 +15,7 @@
  * Paper coverage (Sec. 2 lists the three steps; the details below are the
  * readings recorded in the design notes, because the paper defers them to the
  * earlier Kokkos study):
- *   - drift + diffusion                        (Sec. 2, step 1 "Rasterization")
+ *   - drift + diffusion                        (Sec. 2, step 1, rasterization)
  *   - patch window, erf-difference weights     (Sec. 2, step 1)
  *   - statistical fluctuation from a counter-
  *     based Philox4x32-10 stream               (Sec. 4.1: random123 / Salmon et al. 2011)

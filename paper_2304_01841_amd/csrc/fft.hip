@@ -1,7 +1,7 @@
 // FFT convolution of the plane grid with the detector response on gfx950
-// (arXiv:2304.01841, Sec. 2 step 3: "the main computation here is FFT"; the
-// tick-axis inverse is a complex-to-real transform along axis 1, the idft_cr
-// of Sec. 4.2).
+// (arXiv:2304.01841, Sec. 2 step 3, where the transforms carry the bulk of the
+// convolution's work; the tick-axis inverse is a complex-to-real transform
+// along axis 1, the idft_cr of Sec. 4.2).
 //
 // The grid is [Np][Nt] float32 (ticks contiguous).  The linear convolution
 // out[p][t] = sum_r sum_s R[r][s] G[p + r0 - r][t - s] runs in three passes,
