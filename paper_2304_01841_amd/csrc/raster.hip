@@ -1483,8 +1483,10 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess)
         return e;
     // Depos whose patch does not fit a tile region: one workgroup each, direct
-    // atomics.  The grid is persistent over the device-side count.
-    const unsigned lg = (unsigned)std::min<int64_t>(n, 512);
+    // atomics.  The grid is persistent over the device-side count, one
+    // workgroup per CU (most workloads have no such depo, and each workgroup
+    // holds 17 KB of LDS while it looks).
+    const unsigned lg = (unsigned)std::min<int64_t>(n, 256);
     hipLaunchKernelGGL((k_patch_generic<256, false, B>), dim3(lg), dim3(256), 0, s, e0, bt,
                        w.large, w.counters + 1, (int64_t)0, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess)
