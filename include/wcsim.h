@@ -297,8 +297,22 @@ wcsim_status wcsim_tune_schedules(const wcsim_plane_desc *desc, const wcsim_phys
                                   const wcsim_depo *depos, int64_t n, wcsim_out out_kind,
                                   int32_t reps, void *stream, float *ms);
 
-/* Device pointer to the [npitch][nticks] grid inside a simulate workspace. */
+/* Device pointer to the [npitch][nticks] grid inside a simulate workspace.
+ * After wcsim_simulate_event it holds the event's grid (Sec. 2 step 2) in
+ * every block of 32 pitch rows x 2^k ticks (the least k >= 6 with at most 64
+ * blocks per row) that a depo window reaches; the other blocks are neither
+ * cleared nor read by the event (the convolution takes them as zero) and
+ * keep whatever they held.  Call wcsim_workspace_grid_complete to zero them
+ * when the whole grid is wanted. */
 float *wcsim_workspace_grid(const wcsim_plane *plane, void *workspace, int64_t n);
+
+/* Zero, on `stream`, the blocks of the workspace grid that the last
+ * wcsim_simulate_event with this workspace, plane and depo count n did not
+ * reach, so that the whole grid (wcsim_workspace_grid) is that event's.
+ * Errors: WCSIM_E_STATE for a NULL plane, WCSIM_E_INVALID for a NULL or
+ * misaligned workspace or n < 0, WCSIM_E_DEVICE. */
+wcsim_status wcsim_workspace_grid_complete(const wcsim_plane *plane, void *workspace, int64_t n,
+                                           void *stream);
 
 /* Number of invalid depos dropped by the last wcsim_simulate_event that used
  * this workspace (synchronises `stream`). */
@@ -409,7 +423,7 @@ wcsim_status wcsim_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64
 
 const char *wcsim_last_error(void);
 
-/* Library version (major*10000 + minor*100 + patch): 10100. */
+/* Library version (major*10000 + minor*100 + patch): 10200. */
 int32_t wcsim_version(void);
 
 #ifdef __cplusplus

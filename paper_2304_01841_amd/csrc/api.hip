@@ -391,7 +391,7 @@ using namespace wcs;
 
 extern "C" {
 
-int32_t wcsim_version(void) { return 10100; }
+int32_t wcsim_version(void) { return 10200; }
 
 const char *wcsim_last_error(void) { return g_last_error.c_str(); }
 
@@ -683,6 +683,22 @@ float *wcsim_workspace_grid(const wcsim_plane *pl, void *workspace, int64_t n)
     return (float *)((char *)workspace + sim_grid_offset(pl, n));
 }
 
+wcsim_status wcsim_workspace_grid_complete(const wcsim_plane *pl, void *workspace, int64_t n,
+                                           void *stream)
+{
+    if (!pl)
+        return fail(WCSIM_E_STATE, "NULL plane");
+    if (!workspace || n < 0)
+        return fail(WCSIM_E_INVALID, "bad workspace arguments");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(WCSIM_E_INVALID, "workspace must be 256-byte aligned");
+    const RasterWork rw = raster_work_carve(pl, n, workspace);
+    WCS_HIP(launch_clear_unoccupied((float *)((char *)workspace + sim_grid_offset(pl, n)),
+                                    (int)pl->Np, (int)pl->Nt, rw.occ, occ_shift_of(pl->Nt),
+                                    (hipStream_t)stream));
+    return WCSIM_OK;
+}
+
 wcsim_status wcsim_workspace_invalid_count(const void *workspace, void *stream, int64_t *count)
 {
     if (!workspace || !count)
@@ -741,7 +757,7 @@ static wcsim_status simulate_event(const wcsim_plane *pl, const wcsim_depo *depo
     // Host output: the spectrum buffer of pass A is free once pass B has run
     // and is at least as large as the output.
     float *dst = (out_mem == WCSIM_MEM_HOST) ? (float *)conv : out;
-    WCS_HIP(launch_convolve(pl, grid, dst, out_kind, conv, s, ev ? ev + 5 : nullptr));
+    WCS_HIP(launch_convolve(pl, grid, dst, out_kind, conv, s, ev ? ev + 5 : nullptr, rw.occ));
     if (out_mem == WCSIM_MEM_HOST) {
         WCS_HIP(hipMemcpyAsync(out, dst, out_bytes, hipMemcpyDeviceToHost, s));
         WCS_HIP(hipStreamSynchronize(s));
@@ -923,12 +939,12 @@ constexpr int kChunkEvents = 8;  // events per chunk at most
 // Layout of one chunk: its tables (relative to the chunk's table offset) and
 // its data (relative to the base of the slot it runs in).
 struct ChunkLayout {
-    int64_t n_total = 0, ntiles_total = 0;
+    int64_t n_total = 0, ntiles_total = 0, nbands_total = 0;
     int nblk_r = 0, nblk_p = 0, nblk_c = 0;
     size_t off_bases = 0, tables_bytes = 0;
     size_t off_grid = 0, off_X = 0, off_Y = 0, grid_bytes = 0, data_bytes = 0;
     std::vector<EventCtx> ev;
-    std::vector<int32_t> bases;  // 5 arrays of nev + 1
+    std::vector<int32_t> bases;  // 6 arrays of nev + 1
 };
 
 struct BatchPlan {
@@ -946,9 +962,9 @@ ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
     ChunkLayout L;
     const int nev = (int)idx.size();
     L.ev.resize((size_t)nev);
-    L.bases.assign(5 * (size_t)(nev + 1), 0);
+    L.bases.assign(6 * (size_t)(nev + 1), 0);
     int32_t *bd = &L.bases[0], *bt = bd + (nev + 1), *br = bt + (nev + 1), *bp = br + (nev + 1),
-            *bc = bp + (nev + 1);
+            *bc = bp + (nev + 1), *bb = bc + (nev + 1);
     size_t grid_off = 0, x_off = 0, y_off = 0;
     for (int k = 0; k < nev; ++k) {
         const wcsim_plane *pl = planes[idx[(size_t)k]];
@@ -964,7 +980,10 @@ ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
         e.nout = (int32_t)nout;
         e.nblocks = pl->nblocks;
         e.mode = (kind == WCSIM_OUT_WIRE) ? 1 : 0;
-        // offsets within the chunk's data, turned into pointers per run
+        e.occ_shift = occ_shift_of(pl->Nt);
+        // offsets within the chunk's data (the map: within the chunk's maps),
+        // turned into pointers per run
+        e.occ = (uint8_t *)(uintptr_t)((size_t)kOccCols * (size_t)L.nbands_total);
         e.grid = (float *)(uintptr_t)grid_off;
         e.X = (float2 *)(uintptr_t)x_off;
         e.Y = (float2 *)(uintptr_t)y_off;
@@ -976,8 +995,10 @@ ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
         br[k] = L.nblk_r;
         bp[k] = L.nblk_p;
         bc[k] = L.nblk_c;
+        bb[k] = (int32_t)L.nbands_total;
         L.n_total += n[idx[(size_t)k]];
         L.ntiles_total += pl->ntiles;
+        L.nbands_total += occ_bands(pl->Np);
         L.nblk_r += rows_blocks((int)pl->Np);
         L.nblk_p += pitch_blocks_total(pl);
         L.nblk_c += rows_blocks((int)nout);
@@ -987,10 +1008,11 @@ ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
     br[nev] = L.nblk_r;
     bp[nev] = L.nblk_p;
     bc[nev] = L.nblk_c;
+    bb[nev] = (int32_t)L.nbands_total;
     L.off_bases = align_up(sizeof(EventCtx) * (size_t)nev);
     L.tables_bytes = L.off_bases + align_up(sizeof(int32_t) * L.bases.size());
     const wcsim_plane *pl0 = planes[idx[0]];
-    L.off_grid = raster_work_bytes_batch(pl0, L.n_total, L.ntiles_total);
+    L.off_grid = raster_work_bytes_batch(pl0, L.n_total, L.ntiles_total, L.nbands_total);
     L.grid_bytes = grid_off;
     L.off_X = L.off_grid + grid_off;
     L.off_Y = L.off_X + x_off;
@@ -1049,12 +1071,16 @@ void fill_descriptors(BatchPlan &bp, char *ws, const wcsim_depo *const *depos, c
         ChunkLayout &L = bp.layouts[c];
         const std::vector<int> &g = bp.chunks[c];
         char *data = ws + bp.slot_base((int)c);
+        const wcsim_plane *pl0 = nullptr;  // the carve does not depend on the plane
+        uint8_t *occ =
+            raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, L.nbands_total, data).occ;
         for (size_t k = 0; k < g.size(); ++k) {
             EventCtx &e = L.ev[k];
             e.depos = depos[g[k]];
             e.n = (int32_t)n[g[k]];
             e.event = (uint32_t)event_ids[g[k]];
             e.out = outs[g[k]];
+            e.occ = occ + (uintptr_t)e.occ;
             e.grid = (float *)(data + L.off_grid + (uintptr_t)e.grid);
             e.X = (float2 *)(data + L.off_X + (uintptr_t)e.X);
             e.Y = (float2 *)(data + L.off_Y + (uintptr_t)e.Y);
@@ -1085,6 +1111,7 @@ BatchTables tables_of(const BatchPlan &bp, int c, char *ws)
     bt.rblk_base = b0 + 2 * (nev + 1);
     bt.pblk_base = b0 + 3 * (nev + 1);
     bt.cblk_base = b0 + 4 * (nev + 1);
+    bt.band_base = b0 + 5 * (nev + 1);
     bt.nev = nev;
     return bt;
 }
@@ -1109,10 +1136,11 @@ hipError_t launch_pipeline(const BatchPlan &bp, const wcsim_plane *const *planes
         if (c >= bp.nslots && (e = hipStreamWaitEvent(sR, evF[slot], 0)) != hipSuccess)
             return e;
         const hipEvent_t *mk = marks ? marks + (size_t)c * WCSIM_BATCH_STAGE_EVENTS : nullptr;
-        const RasterWork rw = raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, data);
+        const RasterWork rw =
+            raster_work_carve_batch(pl0, L.n_total, L.ntiles_total, L.nbands_total, data);
         if ((mk && (e = hipEventRecord(mk[0], sR)) != hipSuccess) ||
-            (e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, rw, data + L.off_grid,
-                                     L.grid_bytes, sR, mk ? mk + 1 : nullptr)) != hipSuccess ||
+            (e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, L.nbands_total, rw, sR,
+                                     mk ? mk + 1 : nullptr)) != hipSuccess ||
             (e = hipEventRecord(evR[slot], sR)) != hipSuccess ||
             (e = hipStreamWaitEvent(sF, evR[slot], 0)) != hipSuccess ||
             (mk && (e = hipEventRecord(mk[4], sF)) != hipSuccess) ||

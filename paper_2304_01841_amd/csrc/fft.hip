@@ -449,7 +449,13 @@ struct R2CIo {
     int nrows, ncols;
     int64_t in_stride;
     float2 *X;
+    const uint8_t *occ;  // occupancy map of `in` (nullptr: every block is read)
+    int occ_shift;
 };
+
+// Loads of grid blocks that the occupancy map leaves unmarked read this pair
+// of zeros instead (one cached line for the whole launch).
+__device__ const float2 g_zero_pair[1] = {};
 
 template <class FFT, bool BATCH>
 __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTables bt, int N2,
@@ -466,6 +472,8 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
         io.ncols = E.kp.Nt;
         io.in_stride = E.kp.Nt;
         io.X = E.X;
+        io.occ = E.occ;
+        io.occ_shift = E.occ_shift;
         blk -= bt.rblk_base[e];
     }
     const float *__restrict__ in = io.in;
@@ -478,21 +486,37 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
     float2 *tabH = tabN2 + tw.na;
     load_tables(tw, tabN2, tabH);
     const int row0 = blk * RPW;
+    // Bit c of occ_m: ticks c 2^osh .. (c + 1) 2^osh - 1 of this workgroup's
+    // band of rows are occupied (every bit set without a map; a shift of 31
+    // sends every tick to bit 0).
+    uint64_t occ_m = ~0ull;
+    int osh = 31;
+    if (io.occ) {
+        occ_m = __ballot(io.occ[(row0 / kOccRows) * kOccCols + (threadIdx.x & 63)] != 0);
+        osh = io.occ_shift;
+    }
     // z_n of row s straight from global memory into the first pass.  Every
     // load is issued unconditionally from a clamped (valid) address and the
     // padding is selected afterwards, so the loads of a pass stay in flight
-    // together instead of waiting on each other across branches.
+    // together instead of waiting on each other across branches.  Loads in
+    // unoccupied blocks read the zero pair instead (the two ticks of a load
+    // share a block: blocks are at least 64 ticks and t is even).
     auto load2 = [&](int s, int n) {  // even ncols and stride: one 8-byte load
         const int row = row0 + s, t = 2 * n;
-        const float *src = in + (int64_t)min(row, nrows - 1) * in_stride;
-        const float2 v = *(const float2 *)(src + min(t, ncols - 2));
+        const int tc = min(t, ncols - 2);
+        const float *src = in + (int64_t)min(row, nrows - 1) * in_stride + tc;
+        const bool occ = (occ_m >> (tc >> osh)) & 1ull;
+        const float2 v = *(occ ? (const float2 *)src : g_zero_pair);
         const bool ok = row < nrows && t < ncols;
         return ok ? v : make_float2(0.0f, 0.0f);
     };
     auto load1 = [&](int s, int n) {
         const int row = row0 + s, t = 2 * n;
         const float *src = in + (int64_t)min(row, nrows - 1) * in_stride;
-        const float a = src[min(t, ncols - 1)], b = src[min(t + 1, ncols - 1)];
+        const int ta = min(t, ncols - 1), tb = min(t + 1, ncols - 1);
+        const bool occ = (occ_m >> (ta >> osh)) & 1ull;
+        const float *zf = (const float *)g_zero_pair;
+        const float a = *(occ ? src + ta : zf), b = *(occ ? src + tb : zf);
         const bool ok = row < nrows;
         return make_float2((ok && t < ncols) ? a : 0.0f, (ok && t + 1 < ncols) ? b : 0.0f);
     };
@@ -928,9 +952,10 @@ hipError_t rows_c2r_any(const wcsim_plane *pl, const C2RIo &io, const BatchTable
 }
 
 hipError_t rows_r2c(const wcsim_plane *pl, const float *in, int nrows, int ncols,
-                    int64_t in_stride, float2 *X, hipStream_t s)
+                    int64_t in_stride, float2 *X, hipStream_t s, const uint8_t *occ = nullptr)
 {
-    const R2CIo io = {in, nrows, ncols, in_stride, X};
+    static_assert(kOccRows % kRowsPerBlock == 0, "a tick-pass workgroup spans one map band");
+    const R2CIo io = {in, nrows, ncols, in_stride, X, occ, occ ? occ_shift_of(ncols) : 0};
     return rows_r2c_any<false>(pl, io, BatchTables{}, (unsigned)rows_blocks(nrows), s);
 }
 
@@ -1096,7 +1121,8 @@ size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind)
 }
 
 hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
-                           wcsim_out out_kind, void *work, hipStream_t s, const hipEvent_t *ev)
+                           wcsim_out out_kind, void *work, hipStream_t s, const hipEvent_t *ev,
+                           const uint8_t *occ)
 {
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     const int64_t nout = (out_kind == WCSIM_OUT_WIRE) ? pl->Nw : pl->Np;
@@ -1104,7 +1130,7 @@ hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
     float2 *Y = (float2 *)((char *)work +
                            align_up(sizeof(float2) * (size_t)pl->C * pl->F * (size_t)pl->Np));
     hipError_t e;
-    if ((e = rows_r2c(pl, grid, (int)pl->Np, (int)pl->Nt, pl->Nt, X, s)) != hipSuccess ||
+    if ((e = rows_r2c(pl, grid, (int)pl->Np, (int)pl->Nt, pl->Nt, X, s, occ)) != hipSuccess ||
         (e = mark(0)) != hipSuccess)
         return e;
     if ((e = pitch_pass(pl, X, (int)pl->Np, pl->K, Y, (int)nout, pl->nblocks,

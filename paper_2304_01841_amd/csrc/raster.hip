@@ -591,6 +591,18 @@ __device__ __forceinline__ bool fits_tile(const Win &w, int p0, int t0, const Ti
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
+// Mark the occupancy-map blocks that a window (status 0: it meets the grid)
+// reaches.  Every writer stores the same value, so no atomics are needed.
+__device__ __forceinline__ void mark_blocks(const Win &w, const PlaneParams &P, uint8_t *occ,
+                                            int shift)
+{
+    const int p0 = max(w.lo_p, 0), p1 = min(w.lo_p + w.n_p, P.Np) - 1;
+    const int t0 = max(w.lo_t, 0), t1 = min(w.lo_t + w.n_t, P.Nt) - 1;
+    for (int b = p0 / kOccRows; b <= p1 / kOccRows; ++b)
+        for (int c = t0 >> shift; c <= (t1 >> shift); ++c)
+            occ[b * kOccCols + c] = 1;
+}
+
 // Window and tile of every depo.  Slots in a tile's list come from one atomic
 // per distinct tile per wavefront (consecutive depos of a track share tiles).
 // Depos and tiles carry global indices: in a batch, depo gd belongs to the
@@ -615,6 +627,7 @@ __global__ __launch_bounds__(256) void k_prep_bin(EventCtx e0, BatchTables bt, i
         if (w.status == 1 || w.status == 3) {
             bad = true;
         } else if (w.status == 0) {
+            mark_blocks(w, P, E.occ, E.occ_shift);
             const int tp = min(max(w.lo_p, 0), P.Np - 1) / g.tp;
             const int tt = min(max(w.lo_t, 0), P.Nt - 1) / g.tt;
             if (fits_tile(w, tp * g.tp, tt * g.tt, g, P))
@@ -802,25 +815,56 @@ enum { kHLoP, kHLoT, kHNp, kHNt, kHDepo, kHQlo, kHQhi, kHMq, kHeaderWords };
 static_assert(kHeaderWords <= kRecWp, "record header overflow");
 constexpr int kStageStride = kRecWords + 1;  // odd: one LDS bank per lane
 
+// Zero the blocks of one band of kOccRows grid rows whose bits are set in
+// `m` (bit c: ticks c 2^shift .. (c + 1) 2^shift - 1), by one wavefront.
+__device__ __forceinline__ void clear_blocks(float *grid, int Np, int Nt, int band, uint64_t m,
+                                             int shift, int lane)
+{
+    const int r0 = band * kOccRows, nr = min(kOccRows, Np - r0);
+    while (m) {
+        const int c = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int c0 = c << shift, c1 = min(c0 + (1 << shift), Nt);
+        if ((Nt & 3) == 0) {  // rows of whole float4 words
+            const int nc = (c1 - c0) >> 2;
+            for (int i = lane; i < nr * nc; i += 64) {
+                const int r = i / nc;
+                *(float4 *)(grid + (int64_t)(r0 + r) * Nt + c0 + 4 * (i - r * nc)) =
+                    make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+        } else {
+            const int nc = c1 - c0;
+            for (int i = lane; i < nr * nc; i += 64) {
+                const int r = i / nc;
+                grid[(int64_t)(r0 + r) * Nt + c0 + (i - r * nc)] = 0.0f;
+            }
+        }
+    }
+}
+
 // One wavefront per block: each lane computes one record into LDS, then the
 // wavefront writes the records out one 256-byte row at a time.  The first
-// `nclr` blocks instead clear the plane grid (n4 float4 words): the clear is
-// bound by HBM writes and the records by FP64 arithmetic, so one launch runs
-// both side by side.
+// `nclr` blocks instead clear the occupied blocks of the grids, one band of
+// kOccRows rows at a time (nbands bands over all events): the clear is bound
+// by HBM writes and the records by FP64 arithmetic, so one launch runs both
+// side by side.
 template <bool B>
 __global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt, int64_t ntotal,
                                                      const int32_t *depo_tile,
                                                      const int32_t *depo_slot,
                                                      const int32_t *tile_off, float *records,
-                                                     float4 *clr, int64_t n4, int nclr)
+                                                     int nbands, int nclr)
 {
     __shared__ float stage[64 * kStageStride];
     const int lane = threadIdx.x;
     if ((int)blockIdx.x < nclr) {
-        const int64_t per = (n4 + nclr - 1) / nclr;
-        const int64_t b0 = blockIdx.x * per, b1 = min(b0 + per, n4);
-        for (int64_t i = b0 + lane; i < b1; i += 64)
-            clr[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int gb = blockIdx.x; gb < nbands; gb += nclr) {
+            const int e = B ? find_event(bt.band_base, bt.nev, gb) : 0;
+            const EventCtx &E = B ? bt.ev[e] : e0;
+            const int band = B ? gb - bt.band_base[e] : gb;
+            const uint64_t m = __ballot(E.occ[band * kOccCols + lane] != 0);
+            clear_blocks(E.grid, E.kp.Np, E.kp.Nt, band, m, E.occ_shift, lane);
+        }
         return;
     }
     const int64_t gd = (blockIdx.x - nclr) * (int64_t)64 + lane;
@@ -1115,12 +1159,14 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
 
 // Descriptor of a single event (kernel argument; no table lookups).
 EventCtx single_event(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
-                      uint64_t event_id, float *grid)
+                      uint64_t event_id, float *grid, uint8_t *occ = nullptr)
 {
     EventCtx e{};
     e.kp = pl->kp;
     e.depos = depos;
     e.grid = grid;
+    e.occ = occ;
+    e.occ_shift = occ_shift_of(pl->Nt);
     e.depo_base = 0;
     e.n = (int32_t)n;
     e.event = (uint32_t)event_id;
@@ -1348,11 +1394,9 @@ hipError_t launch_scatter_flat(const wcsim_plane *pl, int64_t n, const int32_t *
     return hipGetLastError();
 }
 
-// Blocks of the record kernel that clear the grid: two per CU keep HBM
-// writes busy while the other blocks build records.
-constexpr int kClearBlocks = 512;
+// Blocks of the record kernel that clear the occupied blocks of the grids:
+// one per band of grid rows (300 for a 9600-row plane), at most this many.
 constexpr int kMaxClearBlocks = 4096;
-constexpr int64_t kClearPerBlock = 28125;  // float4 words: 512 blocks for 9600 x 6000 floats
 
 static size_t sched_blocks_of(int64_t ntiles)
 {
@@ -1364,17 +1408,19 @@ static size_t items_cap(int64_t ntiles, int64_t n)
     return (size_t)ntiles + (size_t)(std::max<int64_t>(n, 1) / kChunk) + 1;
 }
 
-size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles)
+size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles, int64_t nbands)
 {
     (void)pl;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     return align_up(256) + align_up(sizeof(int32_t) * (size_t)(ntiles + 1)) +
+           align_up((size_t)kOccCols * (size_t)nbands) +
            align_up(sizeof(int2) * sched_blocks_of(ntiles)) +
            align_up(sizeof(int4) * items_cap(ntiles, n)) + 3 * align_up(sizeof(int32_t) * nn) +
            align_up(sizeof(float) * kRecWords * nn);
 }
 
-RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles, void *base)
+RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles,
+                                   int64_t nbands, void *base)
 {
     (void)pl;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
@@ -1384,6 +1430,8 @@ RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t nti
     p += align_up(256);
     w.tile_count = (int32_t *)p;
     p += align_up(sizeof(int32_t) * (size_t)(ntiles + 1));
+    w.occ = (uint8_t *)p;  // adjacent to the counters: cleared together
+    p += align_up((size_t)kOccCols * (size_t)nbands);
     w.block_tot = (int2 *)p;
     p += align_up(sizeof(int2) * sched_blocks_of(ntiles));
     w.items = (int4 *)p;
@@ -1400,12 +1448,12 @@ RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t nti
 
 size_t raster_work_bytes(const wcsim_plane *pl, int64_t n)
 {
-    return raster_work_bytes_batch(pl, n, pl->ntiles);
+    return raster_work_bytes_batch(pl, n, pl->ntiles, occ_bands(pl->Np));
 }
 
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
 {
-    return raster_work_carve_batch(pl, n, pl->ntiles, base);
+    return raster_work_carve_batch(pl, n, pl->ntiles, occ_bands(pl->Np), base);
 }
 
 // The launch sequence shared by single events and batches: clear counters,
@@ -1414,30 +1462,22 @@ RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
 template <bool B>
 static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
                                   const BatchTables &bt, int64_t n, int64_t ntiles,
-                                  const RasterWork &w, void *grid, size_t grid_bytes,
-                                  hipStream_t s, const hipEvent_t *ev)
+                                  int64_t nbands, const RasterWork &w, hipStream_t s,
+                                  const hipEvent_t *ev)
 {
     hipError_t e;
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
-    // counters and tile counts are adjacent: one clear
-    const size_t clear = (size_t)((char *)w.tile_count - (char *)w.counters) +
-                         sizeof(int32_t) * (size_t)(ntiles + 1);
+    // counters, tile counts and occupancy maps are adjacent: one clear
+    const size_t clear = (size_t)((char *)w.occ - (char *)w.counters) +
+                         (size_t)kOccCols * (size_t)nbands;
     if ((e = launch_fill_zero(w.counters, align_up(clear, 16), s)) != hipSuccess)
         return e;
-    if (n <= 0) {
-        if ((e = launch_fill_zero(grid, grid_bytes, s)) != hipSuccess)
-            return e;
+    if (n <= 0) {  // an empty map: nothing of the grid is read
         for (int i = 0; i < 3; ++i)
             if ((e = mark(i)) != hipSuccess)
                 return e;
         return hipSuccess;
     }
-    // the grid's float4 words are cleared by the record kernel's first blocks,
-    // any tail of fewer than four floats here
-    const int64_t n4 = (int64_t)(grid_bytes / 16);
-    if (grid_bytes % 16 &&
-        (e = launch_fill_zero((char *)grid + n4 * 16, grid_bytes % 16, s)) != hipSuccess)
-        return e;
     TileGeom g;
     g.tp = pl->ts.tp;
     g.tt = pl->ts.tt;
@@ -1453,16 +1493,10 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
                        (int)sched_blocks);
     hipLaunchKernelGGL(k_tile_schedule, dim3(sched_blocks), dim3(kSchedThreads), 0, s,
                        w.tile_count, (int)ntiles, w.block_tot, w.items, w.counters);
-    // clearing blocks: kClearBlocks for a detector-scale plane (230 MB), more
-    // for the larger grid sets of batches, at most one per 64 KB
-    const int nclr = (int)std::min<int64_t>(
-        kMaxClearBlocks,
-        std::max<int64_t>(std::max<int64_t>(n4 / kClearPerBlock,
-                                            std::min<int64_t>(kClearBlocks, n4 / 4096)),
-                          1));
+    // clearing blocks: one per band of grid rows, at most kMaxClearBlocks
+    const int nclr = (int)std::min<int64_t>(kMaxClearBlocks, nbands);
     hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64) + nclr), dim3(64), 0, s, e0, bt,
-                       n, w.depo_tile, w.depo_slot, w.tile_count, w.records, (float4 *)grid, n4,
-                       nclr);
+                       n, w.depo_tile, w.depo_slot, w.tile_count, w.records, (int)nbands, nclr);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
     const unsigned grid_items = (unsigned)items_cap(ntiles, n);
@@ -1498,17 +1532,39 @@ hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, i
                                uint64_t event_id, const RasterWork &w, float *grid, hipStream_t s,
                                const hipEvent_t *ev)
 {
-    const EventCtx e0 = single_event(pl, depos, n, event_id, grid);
-    return raster_sequence<false>(pl, e0, BatchTables{}, n, pl->ntiles, w, grid,
-                                  sizeof(float) * (size_t)pl->Np * (size_t)pl->Nt, s, ev);
+    const EventCtx e0 = single_event(pl, depos, n, event_id, grid, w.occ);
+    return raster_sequence<false>(pl, e0, BatchTables{}, n, pl->ntiles, occ_bands(pl->Np), w, s,
+                                  ev);
 }
 
 hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
-                               int64_t ntiles_total, const RasterWork &w, void *grids,
-                               size_t grid_bytes, hipStream_t s, const hipEvent_t *ev)
+                               int64_t ntiles_total, int64_t nbands_total, const RasterWork &w,
+                               hipStream_t s, const hipEvent_t *ev)
 {
-    return raster_sequence<true>(pl, EventCtx{}, bt, n_total, ntiles_total, w, grids, grid_bytes,
-                                 s, ev);
+    return raster_sequence<true>(pl, EventCtx{}, bt, n_total, ntiles_total, nbands_total, w, s,
+                                 ev);
+}
+
+// Zero the blocks that the occupancy map leaves unmarked (one wavefront per
+// band of rows), so that the whole grid holds the event.
+__global__ __launch_bounds__(64) void k_clear_unoccupied(float *grid, int Np, int Nt,
+                                                         const uint8_t *occ, int shift)
+{
+    const int band = blockIdx.x, lane = threadIdx.x;
+    const int nb = (Nt + (1 << shift) - 1) >> shift;
+    const uint64_t valid = (nb >= 64) ? ~0ull : ((1ull << nb) - 1ull);
+    const uint64_t m = __ballot(occ[band * kOccCols + lane] != 0);
+    clear_blocks(grid, Np, Nt, band, ~m & valid, shift, lane);
+}
+
+hipError_t launch_clear_unoccupied(float *grid, int Np, int Nt, const uint8_t *occ, int shift,
+                                   hipStream_t s)
+{
+    if (Np <= 0 || Nt <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_clear_unoccupied, dim3((unsigned)occ_bands(Np)), dim3(64), 0, s, grid,
+                       Np, Nt, occ, shift);
+    return hipGetLastError();
 }
 
 }  // namespace wcs

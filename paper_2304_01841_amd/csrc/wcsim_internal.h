@@ -47,6 +47,21 @@ struct PlaneParams {
 // Maximum window length per axis handled anywhere in the library.
 constexpr int kMaxWindow = 1024;
 
+// Occupancy map of a plane grid: one byte per block of kOccRows pitch rows x
+// 2^shift ticks, kOccCols bytes per band of kOccRows rows (at most 64 tick
+// blocks per band: shift >= 6 is the least with ceil(Nt / 2^shift) <= 64).  A
+// byte is non-zero when some depo window reaches the block; blocks never
+// reached are neither cleared nor read (the tick-axis pass takes them as zero).
+constexpr int kOccRows = 32, kOccCols = 64;
+inline int occ_shift_of(int64_t Nt)
+{
+    int s = 6;
+    while (((Nt + (1LL << s) - 1) >> s) > kOccCols)
+        ++s;
+    return s;
+}
+inline int64_t occ_bands(int64_t Np) { return (Np + kOccRows - 1) / kOccRows; }
+
 // ---------------------------------------------------------------------------
 // Batched execution: one descriptor per event in device memory, and prefix
 // bases (nev + 1 entries each) that map a global index of each kind of work
@@ -60,12 +75,13 @@ struct EventCtx {
     float2 *X;         // [C][Np][F]
     float2 *Y;         // [C][nout][F]
     float *out;        // [nout][Nt]
+    uint8_t *occ;      // occupancy map of the grid (occ_bands(Np) x kOccCols bytes)
     int64_t depo_base;
     int32_t n;
     uint32_t event;
     int32_t tile_base, ntt;
     int32_t nout, nblocks, mode;
-    int32_t pad_;
+    int32_t occ_shift;  // tick blocks of the map are 2^occ_shift ticks
 };
 
 struct BatchTables {
@@ -75,6 +91,7 @@ struct BatchTables {
     const int32_t *rblk_base;  // tick-axis forward pass workgroups
     const int32_t *pblk_base;  // pitch-axis pass workgroups
     const int32_t *cblk_base;  // tick-axis inverse pass workgroups
+    const int32_t *band_base;  // bands of kOccRows grid rows (occupancy map)
     int32_t nev;
 };
 
@@ -199,33 +216,41 @@ struct RasterWork {
     int32_t *depo_slot;   // [n] position in its tile's list
     int32_t *large;       // [n] depos of the large-patch path
     float *records;       // [n][64] depo records in tile-list order
+    uint8_t *occ;         // occupancy maps of the grids (bands x kOccCols bytes)
 };
 size_t raster_work_bytes(const wcsim_plane *pl, int64_t n);
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base);
 // `ev` (nullable): 3 events recorded after binning, after the LDS-tiled
 // raster kernel and after the large-patch kernel.
-// The grid (npitch x nticks floats) is cleared by the sequence itself.
+// The sequence clears the occupancy map w.occ and the grid's occupied blocks;
+// the others keep whatever they held.
 hipError_t launch_raster_fused(const wcsim_plane *pl, const wcsim_depo *depos, int64_t n,
                                uint64_t event_id, const RasterWork &w, float *grid,
                                hipStream_t s, const hipEvent_t *ev = nullptr);
 // Batched: events of planes sharing one schedule class (pl = any of them);
-// n_total depos, ntiles_total tiles over all events.
-size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n_total, int64_t ntiles_total);
+// n_total depos, ntiles_total tiles and nbands_total map bands over all events.
+size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n_total, int64_t ntiles_total,
+                               int64_t nbands_total);
 RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n_total, int64_t ntiles_total,
-                                   void *base);
-// `grids` (grid_bytes, all events' grids, contiguous) are cleared by the
-// sequence itself.
+                                   int64_t nbands_total, void *base);
+// Each event's map (EventCtx::occ, inside w.occ) and the occupied blocks of
+// its grid are cleared by the sequence itself.
 // `ev` (nullable): 3 stage marks as for launch_raster_fused.
 hipError_t launch_raster_batch(const wcsim_plane *pl, const BatchTables &bt, int64_t n_total,
-                               int64_t ntiles_total, const RasterWork &w, void *grids,
-                               size_t grid_bytes, hipStream_t s, const hipEvent_t *ev = nullptr);
+                               int64_t ntiles_total, int64_t nbands_total, const RasterWork &w,
+                               hipStream_t s, const hipEvent_t *ev = nullptr);
+// Zero the blocks of a grid that its occupancy map marks as not reached.
+hipError_t launch_clear_unoccupied(float *grid, int Np, int Nt, const uint8_t *occ, int shift,
+                                   hipStream_t s);
 
 // FFT convolution passes
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind);
-// `ev` (nullable): 3 events recorded after passes A, B and C.
+// `ev` (nullable): 3 events recorded after passes A, B and C.  `occ`
+// (nullable): the grid's occupancy map; blocks it does not mark are read as
+// zero.
 hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
                            wcsim_out out_kind, void *work, hipStream_t s,
-                           const hipEvent_t *ev = nullptr);
+                           const hipEvent_t *ev = nullptr, const uint8_t *occ = nullptr);
 hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void *work,
                                    hipStream_t s);
 size_t response_work_bytes(const wcsim_plane *pl);

@@ -104,6 +104,7 @@ _SIGS = {
     "wcsim_simulate_event_noalloc": (_st, [_P, _P, _i64, _u64, _P, _i32, _P]),
     "wcsim_tune_schedules": (_st, [_P, _P, _P, _i32, _P, _i64, _i32, _i32, _P, _P]),
     "wcsim_workspace_grid": (_P, [_P, _P, _i64]),
+    "wcsim_workspace_grid_complete": (_st, [_P, _P, _i64, _P]),
     "wcsim_workspace_invalid_count": (_st, [_P, _P, _P]),
     "wcsim_batch_workspace_bytes": (_sz, [_P, _P, _i32, _i32]),
     "wcsim_simulate_batch": (_st, [_P, _P, _P, _P, _i32, _P, _i32, _P, _P]),
@@ -336,8 +337,14 @@ def simulate_workspace(plane: Plane, n: int, kind: int = OUT_WIRE, device="cuda"
     return _workspace(_lib.wcsim_simulate_workspace_bytes(plane.handle, int(n), kind), device)
 
 
-def workspace_grid(plane: Plane, workspace: torch.Tensor, n: int) -> torch.Tensor:
-    """View of the plane grid left in a simulate workspace."""
+def workspace_grid(plane: Plane, workspace: torch.Tensor, n: int, complete: bool = True,
+                   stream=None) -> torch.Tensor:
+    """View of the plane grid left in a simulate workspace by the last event of
+    n depos; with `complete` the blocks no depo window reached are zeroed
+    first (wcsim_workspace_grid_complete), otherwise they hold stale values."""
+    if complete:
+        _check(_lib.wcsim_workspace_grid_complete(plane.handle, workspace.data_ptr(), int(n),
+                                                  _stream(stream)))
     off = _lib.wcsim_workspace_grid(plane.handle, workspace.data_ptr(), int(n)) - \
         workspace.data_ptr()
     nb = plane.npitch * plane.nticks * 4

@@ -47,7 +47,10 @@ def test_batch_equals_single_and_oracle(ws, kind, tau):
     planes = [ws.Plane(e["plane"], phys, R, r0=20) for e in evs]
     deps = [torch.from_numpy(np.ascontiguousarray(e["depos"])).cuda() for e in evs]
     outs = [torch.full((p.out_rows(kind), p.nticks), 3.0, device="cuda") for p in planes]
-    ws.simulate_batch(planes, deps, [e["event_id"] for e in evs], outs, kind=kind)
+    # a workspace full of NaN: grid blocks no depo reaches are neither cleared nor read
+    wsp = ws.batch_workspace(planes, [d.shape[0] for d in deps], kind)
+    wsp.fill_(0xFF)
+    ws.simulate_batch(planes, deps, [e["event_id"] for e in evs], outs, kind=kind, workspace=wsp)
     torch.cuda.synchronize()
     for p, d, e, o in zip(planes, deps, evs, outs):
         single = ws.simulate_event(p, d, e["event_id"], kind=kind).cpu().numpy()

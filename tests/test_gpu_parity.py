@@ -257,6 +257,38 @@ def test_simulate_small_every_tile_shape(ws):
     _sim_and_compare(ws, edges, kinds=(ws.OUT_PITCH,), schedules=shapes)
 
 
+def test_unreached_grid_blocks_are_neither_cleared_nor_read(ws):
+    """Only the grid blocks (32 pitch rows x 2^k ticks) that some depo window
+    reaches are cleared and read: on a workspace full of NaN (all-one bytes),
+    and then after a dense event left its data behind, a sparse event gives
+    the oracle's output; its grid keeps the stale contents outside the reached
+    blocks until completed, and then equals the oracle's grid."""
+    log("case: unreached grid blocks")
+    w = W.small()
+    pl, R = w["planes"][0], w["responses"][0]
+    phys = W.physics(True)
+    P = ws.Plane(pl, phys, R)
+    dense = w["depos"]
+    sparse = np.ascontiguousarray(dense[:25])
+    nmax = dense.shape[0]
+    wsp = ws.simulate_workspace(P, nmax, ws.OUT_PITCH)
+    wsp.fill_(0xFF)
+    for dep, ev in ((sparse, 3), (dense, 4), (sparse, 5)):
+        G = O.grid(dep, phys, pl, ev)
+        ref = O.convolve(G, R.astype(np.float64), R.shape[0] // 2)
+        out = ws.simulate_event(P, torch.from_numpy(dep).cuda(), ev, kind=ws.OUT_PITCH,
+                                workspace=wsp).cpu().numpy()
+        assert np.isfinite(out).all()
+        assert normwise(out, ref) <= CONV_TOL, ev
+        n = dep.shape[0]
+        if ev == 3:  # NaN left wherever no window reached, values wherever charge landed
+            stale = ws.workspace_grid(P, wsp, n, complete=False).cpu().numpy()
+            assert np.isnan(stale).any()
+            assert np.isfinite(stale[G != 0.0]).all()
+        grid = ws.workspace_grid(P, wsp, n).cpu().numpy()
+        assert normwise(grid, G) <= GRID_TOL, ev
+
+
 def test_simulate_collection_full_size(ws):
     """Detector-scale collection plane (960 wires x 10 impact x 6000 ticks,
     500,000 track depos, fluctuation) in every launch configuration the
