@@ -494,6 +494,14 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
     if (io.occ) {
         occ_m = __ballot(io.occ[(row0 / kOccRows) * kOccCols + (threadIdx.x & 63)] != 0);
         osh = io.occ_shift;
+        if (occ_m == 0) {  // no depo reaches this band of rows: zero spectra
+            const int fmask = (1 << F_shift) - 1, cf = C << F_shift;
+            for (int s = 0; s < RPW && row0 + s < nrows; ++s)
+                for (int k = threadIdx.x; k < cf; k += blockDim.x)
+                    X[(((int64_t)(k >> F_shift) * nrows + row0 + s) << F_shift) + (k & fmask)] =
+                        make_float2(0.0f, 0.0f);
+            return;
+        }
     }
     // z_n of row s straight from global memory into the first pass.  Every
     // load is issued unconditionally from a clamped (valid) address and the

@@ -939,18 +939,12 @@ constexpr int kBatchItems = 64 * kFluctItems;
 // a batch may cover the same cell).  No other wavefront touches the region.
 // The region's non-zero cells are then added to the grid with float atomics.
 template <int TP, int TT, bool B>
-__global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
-                                                     const int4 *__restrict__ items,
-                                                     const int32_t *__restrict__ counters,
-                                                     EventCtx e0, BatchTables bt)
+__device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const int4 item,
+                                            const float *__restrict__ records,
+                                            const EventCtx &e0, const BatchTables &bt)
 {
-    constexpr int RP = TP + kHaloP, RT = region_cols<TT>();
-    static_assert(RT % 4 == 0, "region rows must hold whole quads");
-    __shared__ float4 acc4[RP * RT / 4];
-    __shared__ double xsum[kBatchItems];  // prefix sums of a batch's fluctuated item totals
-    if ((int)blockIdx.x >= counters[2])
-        return;
-    const int4 item = items[blockIdx.x];
+    constexpr int RT = region_cols<TT>();
+    constexpr int RP = TP + kHaloP;
     const int tile = item.x, beg = item.y, end = item.z;
     const int K = end - beg;  // patches of the work item (<= kChunk)
     const int lane = threadIdx.x;
@@ -1155,6 +1149,24 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
             for (int col = lane; col < W; col += 64)
                 flush_one(r, col);
     }
+}
+
+template <int TP, int TT, bool B>
+__global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
+                                                     const int4 *__restrict__ items,
+                                                     const int32_t *__restrict__ counters,
+                                                     EventCtx e0, BatchTables bt)
+{
+    constexpr int RP = TP + kHaloP, RT = region_cols<TT>();
+    static_assert(RT % 4 == 0, "region rows must hold whole quads");
+    __shared__ float4 acc4[RP * RT / 4];
+    __shared__ double xsum[kBatchItems];  // prefix sums of a batch's fluctuated item totals
+    // The launch has at most as many wavefronts as a typical work list has
+    // items (the count is known only on the device); a wavefront takes items
+    // blockIdx.x, + gridDim.x, ... so that every item is drawn.
+    const int nitems_all = counters[2];
+    for (int itm = blockIdx.x; itm < nitems_all; itm += gridDim.x)
+        raster_item<TP, TT, B>(acc4, xsum, items[itm], records, e0, bt);
 }
 
 // Descriptor of a single event (kernel argument; no table lookups).
@@ -1408,6 +1420,15 @@ static size_t items_cap(int64_t ntiles, int64_t n)
     return (size_t)ntiles + (size_t)(std::max<int64_t>(n, 1) / kChunk) + 1;
 }
 
+// Wavefronts of the raster launch: enough for the work lists of track-like
+// and uniform depo sets (a work item holds up to kChunk depos of one tile;
+// the collection plane's 500,000 depos make 29,129 items), never more than
+// the worst case; any further items are taken by a second round.
+static unsigned raster_grid(int64_t ntiles, int64_t n)
+{
+    return (unsigned)std::min<size_t>(items_cap(ntiles, n), (size_t)(n / 8) + 4096);
+}
+
 size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles, int64_t nbands)
 {
     (void)pl;
@@ -1499,7 +1520,7 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
                        n, w.depo_tile, w.depo_slot, w.tile_count, w.records, (int)nbands, nclr);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
-    const unsigned grid_items = (unsigned)items_cap(ntiles, n);
+    const unsigned grid_items = raster_grid(ntiles, n);
     switch (pl->tile) {
     case 1:
         hipLaunchKernelGGL((k_raster_tiles<32, 32, B>), dim3(grid_items), dim3(64), 0, s,
