@@ -134,6 +134,48 @@ __device__ __forceinline__ void dft<5>(float2 *x)
     x[3] = csub(e2, mul_mi(o2));
 }
 
+// 16 points as 4 x 4: t = 4 t1 + t2, m = m1 + 4 m2; 4-point DFTs over t1,
+// the factors exp(-2 pi i t2 m1 / 16), then 4-point DFTs over t2.
+template <>
+__device__ __forceinline__ void dft<16>(float2 *x)
+{
+    constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
+    constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+    constexpr float h = 0.70710678118654752440f;   // cos(pi/4)
+    float2 a[4][4];
+#pragma unroll
+    for (int t2 = 0; t2 < 4; ++t2) {
+        a[t2][0] = x[t2];
+        a[t2][1] = x[4 + t2];
+        a[t2][2] = x[8 + t2];
+        a[t2][3] = x[12 + t2];
+        dft<4>(a[t2]);
+    }
+    // a[t2][m1] *= W^(t2 m1), W = exp(-2 pi i / 16)
+    auto w1 = [&](float2 v) { return make_float2(c1 * v.x + s1 * v.y, c1 * v.y - s1 * v.x); };
+    auto w2 = [&](float2 v) { return make_float2(h * (v.x + v.y), h * (v.y - v.x)); };
+    auto w3 = [&](float2 v) { return make_float2(s1 * v.x + c1 * v.y, s1 * v.y - c1 * v.x); };
+    auto w6 = [&](float2 v) { return make_float2(h * (v.y - v.x), -h * (v.x + v.y)); };
+    auto w9 = [&](float2 v) { return make_float2(-c1 * v.x - s1 * v.y, s1 * v.x - c1 * v.y); };
+    a[1][1] = w1(a[1][1]);
+    a[1][2] = w2(a[1][2]);
+    a[1][3] = w3(a[1][3]);
+    a[2][1] = w2(a[2][1]);
+    a[2][2] = mul_mi(a[2][2]);  // W^4 = -i
+    a[2][3] = w6(a[2][3]);
+    a[3][1] = w3(a[3][1]);
+    a[3][2] = w6(a[3][2]);
+    a[3][3] = w9(a[3][3]);
+#pragma unroll
+    for (int m1 = 0; m1 < 4; ++m1) {
+        float2 b[4] = {a[0][m1], a[1][m1], a[2][m1], a[3][m1]};
+        dft<4>(b);
+#pragma unroll
+        for (int m2 = 0; m2 < 4; ++m2)
+            x[m1 + 4 * m2] = b[m2];
+    }
+}
+
 // Multiply x_t by w^t, t = 1..R-1 (powers by repeated products: a few ulp,
 // far below the float32 transform error).
 template <int R>
@@ -863,11 +905,11 @@ constexpr int kRowsPerBlock = 1 << kRowsShift;
 //   workgroups; they get 512 threads to keep enough waves.
 using TickCt3125 = FftCt<3125, kRowsShift, 3126, 1, 320, 5, 5, 5, 5, 5>;
 using TickCt600 = FftCt<600, kRowsShift, 601, 1, 128, 8, 5, 5, 3>;
-using PitchCt1024x8 = FftCt<1024, 3, 1, 8, 512, 8, 8, 4, 4>;
+using PitchCt1024x8 = FftCt<1024, 3, 1, 8, 512, 16, 16, 4>;
 using PitchCt512x16 = FftCt<512, 4, 1, 16, 512, 8, 8, 8>;
 // Blocks a multiple of 10 rows long for the folded wire-output inverse, with
 // the folded transforms of length L / 10.
-using PitchCt640x8 = FftCt<640, 3, 1, 8, 512, 8, 4, 4, 5>;
+using PitchCt640x8 = FftCt<640, 3, 1, 8, 512, 16, 8, 5>;
 using PitchCt960x8 = FftCt<960, 3, 1, 8, 512, 8, 8, 5, 3>;
 using FoldCt64x8 = FftCt<64, 3, 1, 8, 512, 8, 8>;
 using FoldCt96x8 = FftCt<96, 3, 1, 8, 512, 8, 4, 3>;
@@ -994,7 +1036,7 @@ hipError_t pitch_any(const wcsim_plane *pl, const PitchIo &io, const BatchTables
                      unsigned blocks, float scale, hipStream_t s)
 {
     const bool fold10 = pl->fold && pl->kp.nimpact == 10;
-    if (pl->L == 1024 && pl->Fb == 8 && !pl->fold && plan_is(pl->planL, {8, 8, 4, 4}))
+    if (pl->L == 1024 && pl->Fb == 8 && !pl->fold)
         launch_pitch<PitchCt1024x8, PitchCt1024x8, B>(pl, PitchCt1024x8(), PitchCt1024x8(),
                                                       PitchCt1024x8::kThreads, io, bt, blocks,
                                                       scale, s);
@@ -1002,8 +1044,7 @@ hipError_t pitch_any(const wcsim_plane *pl, const PitchIo &io, const BatchTables
         launch_pitch<PitchCt512x16, PitchCt512x16, B>(pl, PitchCt512x16(), PitchCt512x16(),
                                                       PitchCt512x16::kThreads, io, bt, blocks,
                                                       scale, s);
-    else if (pl->L == 640 && pl->Fb == 8 && fold10 && plan_is(pl->planL, {8, 4, 4, 5}) &&
-             plan_is(pl->planF, {8, 8}))
+    else if (pl->L == 640 && pl->Fb == 8 && fold10 && plan_is(pl->planF, {8, 8}))
         launch_pitch<PitchCt640x8, FoldCt64x8, B>(pl, PitchCt640x8(), FoldCt64x8(),
                                                   PitchCt640x8::kThreads, io, bt, blocks, scale, s);
     else if (pl->L == 960 && pl->Fb == 8 && fold10 && plan_is(pl->planL, {8, 8, 5, 3}) &&
