@@ -762,11 +762,41 @@ __global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_c
 // values near 1, so tail bins keep their full relative precision), a bin
 // holding the centre is 2 - c_a - c_b.  The window total is the same
 // difference taken between the window's outer edges.
+// erfc(x) for x >= 0 in FP64 without branches: exp(-x^2) erfcx(x), with
+// erfcx(x) = exp(x^2) erfc(x) from its Chebyshev expansion of degree 18 in
+// u = 9 / (3 + x) - 2 (the interval [0, 6] of x mapped onto [-1, 1]), fitted by
+// weighted least squares at 300 Chebyshev nodes in 40-digit arithmetic: at
+// most 1.6e-15 relative to the library erfc on [0, 6].  Beyond x = 6 erfcx is
+// held at its value at 6 (erfc(6) = 2.2e-17: the absolute error stays below
+// 1e-17).  The library erfc branches over three ranges of x here, and the
+// lanes of a wavefront take all three.
+__constant__ const double kErfcxCheb[19] = {
+    0.43106340548200280783,     0.4317768845374619746,      0.11240012030838863907,
+    0.021602701119412269399,    0.0029235483262740457863,   0.00023395398679905218146,
+    1.3120228285000756815e-06,  -1.8388769572666935182e-06, -1.036155682341427026e-07,
+    1.5512144298939361581e-08,  1.3916389949762914822e-09,  -1.8185219119865354685e-10,
+    -1.5415890937672703625e-11, 2.7673211570784812338e-12,  1.1975973105657121435e-13,
+    -4.5294816534347390793e-14, 6.1173784776326125931e-16,  6.7176043883895186765e-16,
+    -4.7338253409245980876e-17};
+
+__device__ __forceinline__ double erfc_tail(double x)
+{
+    const double u = 9.0 / (3.0 + fmin(x, 6.0)) - 2.0;
+    double b1 = 0.0, b2 = 0.0;  // Clenshaw recurrence
+#pragma unroll
+    for (int k = 18; k >= 1; --k) {
+        const double t = fma(2.0 * u, b1, kErfcxCheb[k] - b2);
+        b2 = b1;
+        b1 = t;
+    }
+    return exp(-x * x) * fma(u, b1, kErfcxCheb[0] - b2);
+}
+
 __device__ __forceinline__ double edge_tail(int lo, int k, double mu, double inv, bool &neg)
 {
     const double x = ((double)(lo + k) - mu) * inv;
     neg = x < 0.0;
-    return erfc(fabs(x));
+    return erfc_tail(fabs(x));
 }
 
 __device__ __forceinline__ double bin_integral(double ca, bool na, double cb, bool nb)
@@ -791,13 +821,14 @@ __device__ __forceinline__ void thread_axis_weights(int lo, int n, double mu, do
     const double c_n = edge_tail(lo, n, mu, inv, nn);
     const double rtot = 1.0 / bin_integral(c_lo, n0, c_n, nn);
     bool n_lo = n0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i + 1 < n; ++i) {
         bool n_hi;
         const double c_hi = edge_tail(lo, i + 1, mu, inv, n_hi);
         W[i] = (float)(bin_integral(c_lo, n_lo, c_hi, n_hi) * rtot);
         c_lo = c_hi;
         n_lo = n_hi;
     }
+    W[n - 1] = (float)(bin_integral(c_lo, n_lo, c_n, nn) * rtot);  // the last edge is c_n
 }
 
 // floor(a / b) for 0 <= a < 4096 and 1 <= b <= 64 by a multiply-shift with
