@@ -262,31 +262,35 @@ def test_unreached_grid_blocks_are_neither_cleared_nor_read(ws):
     reaches are cleared and read: on a workspace full of NaN (all-one bytes),
     and then after a dense event left its data behind, a sparse event gives
     the oracle's output; its grid keeps the stale contents outside the reached
-    blocks until completed, and then equals the oracle's grid."""
+    blocks until completed, and then equals the oracle's grid.  Also on a
+    ragged plane (130 pitch rows: a partial last band; 997 ticks: rows of an
+    odd length, cleared and read float by float)."""
     log("case: unreached grid blocks")
     w = W.small()
-    pl, R = w["planes"][0], w["responses"][0]
-    phys = W.physics(True)
-    P = ws.Plane(pl, phys, R)
-    dense = w["depos"]
-    sparse = np.ascontiguousarray(dense[:25])
-    nmax = dense.shape[0]
-    wsp = ws.simulate_workspace(P, nmax, ws.OUT_PITCH)
-    wsp.fill_(0xFF)
-    for dep, ev in ((sparse, 3), (dense, 4), (sparse, 5)):
-        G = O.grid(dep, phys, pl, ev)
-        ref = O.convolve(G, R.astype(np.float64), R.shape[0] // 2)
-        out = ws.simulate_event(P, torch.from_numpy(dep).cuda(), ev, kind=ws.OUT_PITCH,
-                                workspace=wsp).cpu().numpy()
-        assert np.isfinite(out).all()
-        assert normwise(out, ref) <= CONV_TOL, ev
-        n = dep.shape[0]
-        if ev == 3:  # NaN left wherever no window reached, values wherever charge landed
-            stale = ws.workspace_grid(P, wsp, n, complete=False).cpu().numpy()
-            assert np.isnan(stale).any()
-            assert np.isfinite(stale[G != 0.0]).all()
-        grid = ws.workspace_grid(P, wsp, n).cpu().numpy()
-        assert normwise(grid, G) <= GRID_TOL, ev
+    rng = np.random.default_rng(41)
+    ragged = (W.plane(13, 997), W.uniform_depos(rng, 400, (0.0, 65.0), (0.0, 480.0)))
+    for pl, dense in ((w["planes"][0], w["depos"]), ragged):
+        R = w["responses"][0]
+        phys = W.physics(True)
+        P = ws.Plane(pl, phys, R)
+        sparse = np.ascontiguousarray(dense[:25])
+        wsp = ws.simulate_workspace(P, dense.shape[0], ws.OUT_PITCH)
+        wsp.fill_(0xFF)
+        for dep, ev in ((sparse, 3), (dense, 4), (sparse, 5)):
+            log("  plane %d x %d, %d depos" % (P.npitch, P.nticks, dep.shape[0]))
+            G = O.grid(dep, phys, pl, ev)
+            ref = O.convolve(G, R.astype(np.float64), R.shape[0] // 2)
+            out = ws.simulate_event(P, torch.from_numpy(dep).cuda(), ev, kind=ws.OUT_PITCH,
+                                    workspace=wsp).cpu().numpy()
+            assert np.isfinite(out).all()
+            assert normwise(out, ref) <= CONV_TOL, ev
+            n = dep.shape[0]
+            if ev == 3:  # NaN where no window reached, values wherever charge landed
+                stale = ws.workspace_grid(P, wsp, n, complete=False).cpu().numpy()
+                assert np.isnan(stale).any()
+                assert np.isfinite(stale[G != 0.0]).all()
+            grid = ws.workspace_grid(P, wsp, n).cpu().numpy()
+            assert normwise(grid, G) <= GRID_TOL, ev
 
 
 def test_simulate_collection_full_size(ws):
