@@ -91,11 +91,16 @@ def algorithmic_bytes(P, nout: int, n_depos: int) -> dict:
     Np, Nt = P.npitch, P.nticks
     Rt = P._resp.shape[1]
     H = (Nt + Rt - 1) // 2 + 1
-    L = P.info["fft_pitch"]
+    # resident response spectrum read by the pitch pass: L rows per column for
+    # the overlap-save blocks, nimpact phases of 128 for the polyphase wire pass
+    if P.info["wire_polyphase"] and nout == P.nwires and nout != Np:
+        spectrum_rows = P.info["nimpact"] * 128
+    else:
+        spectrum_rows = P.info["fft_pitch"]
     return {
         "raster_tiles": 40 * n_depos + 4 * Np * Nt,
         "fft_ticks": 4 * Np * Nt + 8 * Np * H,
-        "conv_pitch": 8 * Np * H + 8 * L * H + 8 * nout * H,
+        "conv_pitch": 8 * Np * H + 8 * spectrum_rows * H + 8 * nout * H,
         "ifft_ticks": 8 * nout * H + 4 * nout * Nt,
     }
 

@@ -124,6 +124,13 @@ typedef struct {
     int32_t tile;       /* raster tile shape id, pitch bins x ticks of a tile: 0 = 32 x 8
                          * (default), 1 = 32 x 32, 2 = 64 x 8; each wavefront's LDS
                          * region adds a 32-bin x 16-tick halo */
+    int32_t wire_mode;  /* pitch pass of wire output (Sec. 2 step 3): 1 = polyphase
+                         * (per tick frequency, the nimpact phases of the grid rows at
+                         * wire rate, each convolved with its ceil(resp_npitch /
+                         * nimpact)-tap slice of the response through 128-point
+                         * transforms and summed; needs nimpact > 1 and at most 64
+                         * taps), 2 = overlap-save blocks of fft_pitch rows; 0 =
+                         * polyphase where it applies, else blocks */
 } wcsim_schedule;
 
 /* Derived sizes of a plane (read-only). */
@@ -137,6 +144,8 @@ typedef struct {
     int64_t spectrum_bytes; /* resident response spectrum */
     int32_t pitch_cols;     /* spectrum columns per pitch-pass workgroup (divides freq_chunk) */
     int32_t wire_fold;      /* 1: wire output folds the pitch inverse to fft_pitch / nimpact */
+    int32_t wire_polyphase; /* 1: wire output uses the polyphase pitch pass */
+    int32_t wire_blocks;    /* polyphase blocks along the wires (0 without) */
 } wcsim_plane_info;
 
 typedef struct wcsim_plane wcsim_plane;
@@ -423,7 +432,7 @@ wcsim_status wcsim_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64
 
 const char *wcsim_last_error(void);
 
-/* Library version (major*10000 + minor*100 + patch): 10200. */
+/* Library version (major*10000 + minor*100 + patch): 10300. */
 int32_t wcsim_version(void);
 
 #ifdef __cplusplus

@@ -22,12 +22,17 @@ import torch
 
 from . import wcsim
 
-# Candidate schedules: the library default first, then the compiled pitch-pass
+# Candidate schedules: the library default first, then the polyphase wire
+# pass over 16- and 8-column chunks, then the compiled overlap-save block
 # variants (block length x chunk width; 640 and 960 allow the folded
-# wire-output inverse) crossed with the raster tile shapes.
-PITCH_CHOICES = ({}, {"fft_pitch": 512, "freq_chunk": 16}, {"fft_pitch": 1024, "freq_chunk": 16},
-                 {"fft_pitch": 1024, "freq_chunk": 8}, {"fft_pitch": 640, "freq_chunk": 16},
-                 {"fft_pitch": 960, "freq_chunk": 16})
+# wire-output inverse), crossed with the raster tile shapes.  The block
+# length also sets the pitch-output pass of every candidate.
+PITCH_CHOICES = ({}, {"freq_chunk": 16}, {"freq_chunk": 8},
+                 {"fft_pitch": 512, "freq_chunk": 16, "wire_mode": 2},
+                 {"fft_pitch": 1024, "freq_chunk": 16, "wire_mode": 2},
+                 {"fft_pitch": 1024, "freq_chunk": 8, "wire_mode": 2},
+                 {"fft_pitch": 640, "freq_chunk": 16, "wire_mode": 2},
+                 {"fft_pitch": 960, "freq_chunk": 16, "wire_mode": 2})
 TILE_CHOICES = (0, 1, 2)
 TIE = 0.02  # relative timing difference treated as a tie
 

@@ -17,10 +17,14 @@
 // host response they were built from (to recognise a compatible donor).
 struct wcs_spectrum {
     float2 *K = nullptr, *twT = nullptr, *twHalf = nullptr, *twL = nullptr, *twF = nullptr;
+    float2 *H = nullptr, *twP = nullptr;  // polyphase spectra and table (poly planes)
     std::vector<float> response, elec;
     int Rp = 0, Rt = 0, r0 = 0, Nfft = 0, L = 0, F = 0, device = -1;
+    bool poly = false;
     ~wcs_spectrum()
     {
+        (void)hipFree(H);
+        (void)hipFree(twP);
         (void)hipFree(K);
         (void)hipFree(twT);
         (void)hipFree(twHalf);
@@ -196,6 +200,22 @@ wcsim_status choose_schedule(wcsim_plane *pl, const wcsim_schedule *sc)
     pl->L = L;
     pl->V = L - pl->Rp + 1;
     pl->nblocks = (int)((pl->Np + pl->V - 1) / pl->V);
+    // Wire output: the polyphase pitch pass when each of the nimpact phase
+    // filters has at most poly_max_taps() taps (wire_mode 0 or 1), else the
+    // overlap-save blocks of L rows (wire_mode 2, or 0 when it does not apply).
+    const int wm = sc ? sc->wire_mode : 0;
+    if (wm < 0 || wm > 2)
+        return fail(WCSIM_E_INVALID, "wire_mode must be 0, 1 or 2");
+    const int taps = (int)((pl->Rp + D - 1) / D);
+    const bool poly_ok = D > 1 && taps <= poly_max_taps();
+    if (wm == 1 && !poly_ok)
+        return fail(WCSIM_E_INVALID,
+                    "polyphase wire output needs nimpact > 1 and ceil(resp_npitch / nimpact) <= 64");
+    pl->poly = poly_ok && wm != 2;
+    pl->polyA = taps;
+    pl->polyV = poly_block_rows() - taps + 1;
+    pl->polyBlocks = (int)((pl->Nw + pl->polyV - 1) / pl->polyV);
+    pl->polyCw = D / 2 + pl->r0;
     pl->H = pl->N2 + 1;
     pl->C = (pl->H + pl->F - 1) / pl->F;
     pl->tile = (sc && sc->tile) ? sc->tile : 0;
@@ -277,6 +297,7 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
         const wcs_spectrum &d = *donor->spectrum;
         if (d.Rp == pl->Rp && d.Rt == pl->Rt && d.r0 == pl->r0 && d.Nfft == pl->Nfft &&
             d.L == pl->L && d.F == pl->F && d.device == pl->device && (d.twF != nullptr) == pl->fold &&
+            d.poly == pl->poly && (!pl->poly || pl->kp.nimpact == donor->kp.nimpact) &&
             d.response.size() == nresp0 && d.elec.size() == nelec &&
             memcmp(d.response.data(), desc->response, sizeof(float) * nresp0) == 0 &&
             (nelec == 0 || memcmp(d.elec.data(), desc->elec_response, sizeof(float) * nelec) == 0)) {
@@ -286,6 +307,8 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
             pl->twHalf = d.twHalf;
             pl->twL = d.twL;
             pl->twF = d.twF;
+            pl->KP = d.H;
+            pl->twP = d.twP;
             *out = pl;
             return WCSIM_OK;
         }
@@ -311,20 +334,31 @@ wcsim_status plane_create(const wcsim_plane_desc *desc, const wcsim_physics *phy
     spec->L = pl->L;
     spec->F = pl->F;
     spec->device = pl->device;
+    spec->poly = pl->poly;
     if ((st = upload(&spec->twT, twiddles(pl->N2, pl->N2), s)) != WCSIM_OK ||
         (st = upload(&spec->twHalf, twiddles(pl->Nfft, pl->N2 + 1), s)) != WCSIM_OK ||
         (st = upload(&spec->twL, twiddles(pl->L, pl->L), s)) != WCSIM_OK ||
-        (pl->fold && (st = upload(&spec->twF, twiddles(pl->L10, pl->L10), s)) != WCSIM_OK))
+        (pl->fold && (st = upload(&spec->twF, twiddles(pl->L10, pl->L10), s)) != WCSIM_OK) ||
+        (pl->poly && (st = upload(&spec->twP, twiddles(poly_block_rows(), poly_block_rows()), s)) !=
+                         WCSIM_OK))
         return cleanup(st);
     pl->twT = spec->twT;
     pl->twHalf = spec->twHalf;
     pl->twL = spec->twL;
     pl->twF = spec->twF;
+    pl->twP = spec->twP;
     hipError_t e;
     const size_t kbytes = sizeof(float2) * (size_t)pl->C * pl->L * pl->F;
     if ((e = hipMalloc((void **)&spec->K, kbytes)) != hipSuccess)
         return cleanup(check_hip(e, "hipMalloc(response spectrum)"));
     pl->K = spec->K;
+    if (pl->poly) {
+        const size_t hbytes =
+            sizeof(float2) * (size_t)pl->C * pl->kp.nimpact * poly_block_rows() * pl->F;
+        if ((e = hipMalloc((void **)&spec->H, hbytes)) != hipSuccess)
+            return cleanup(check_hip(e, "hipMalloc(polyphase response spectra)"));
+        pl->KP = spec->H;
+    }
     // device copies: [combined Rp x Rt | caller's Rp x Rt0 | electronics]
     const size_t rbytes = sizeof(float) * (nresp + nresp0 + nelec);
     if ((e = hipMalloc((void **)&resp, rbytes)) != hipSuccess)
@@ -391,7 +425,7 @@ using namespace wcs;
 
 extern "C" {
 
-int32_t wcsim_version(void) { return 10200; }
+int32_t wcsim_version(void) { return 10300; }
 
 const char *wcsim_last_error(void) { return g_last_error.c_str(); }
 
@@ -414,11 +448,12 @@ wcsim_status wcsim_plane_create_sharing(const wcsim_plane_desc *desc, const wcsi
 {
     if (!donor)
         return fail(WCSIM_E_INVALID, "NULL spectrum donor");
-    wcsim_schedule sc;
+    wcsim_schedule sc{};
     sc.fft_ticks = donor->Nfft;
     sc.fft_pitch = donor->L;
     sc.freq_chunk = donor->F;
     sc.tile = donor->tile;
+    sc.wire_mode = donor->poly ? 0 : 2;
     // the donor's transform may be too short for a longer readout
     if (desc && donor->Nfft < desc->nticks + effective_resp_nticks(desc) - 1)
         return plane_create(desc, phys, nullptr, nullptr, stream, out);
@@ -450,9 +485,14 @@ wcsim_status wcsim_plane_get_info(const wcsim_plane *pl, wcsim_plane_info *info)
     info->tile_pitch = pl->ts.tp;
     info->tile_ticks = pl->ts.tt;
     info->ntiles = pl->ntiles;
-    info->spectrum_bytes = (int64_t)sizeof(float2) * pl->C * pl->L * pl->F;
+    info->spectrum_bytes = (int64_t)sizeof(float2) * pl->C * pl->L * pl->F +
+                           (pl->poly ? (int64_t)sizeof(float2) * pl->C * pl->kp.nimpact *
+                                           poly_block_rows() * pl->F
+                                     : 0);
     info->pitch_cols = pl->Fb;
     info->wire_fold = pl->fold ? 1 : 0;
+    info->wire_polyphase = pl->poly ? 1 : 0;
+    info->wire_blocks = pl->poly ? pl->polyBlocks : 0;
     return WCSIM_OK;
 }
 
@@ -940,6 +980,7 @@ constexpr int kChunkEvents = 8;  // events per chunk at most
 // its data (relative to the base of the slot it runs in).
 struct ChunkLayout {
     int64_t n_total = 0, ntiles_total = 0, nbands_total = 0;
+    bool poly = false;  // wire output through the polyphase pitch pass
     int nblk_r = 0, nblk_p = 0, nblk_c = 0;
     size_t off_bases = 0, tables_bytes = 0;
     size_t off_grid = 0, off_X = 0, off_Y = 0, grid_bytes = 0, data_bytes = 0;
@@ -962,6 +1003,7 @@ ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
     ChunkLayout L;
     const int nev = (int)idx.size();
     L.ev.resize((size_t)nev);
+    L.poly = kind == WCSIM_OUT_WIRE && planes[idx[0]]->poly;
     L.bases.assign(6 * (size_t)(nev + 1), 0);
     int32_t *bd = &L.bases[0], *bt = bd + (nev + 1), *br = bt + (nev + 1), *bp = br + (nev + 1),
             *bc = bp + (nev + 1), *bb = bc + (nev + 1);
@@ -972,13 +1014,13 @@ ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
         EventCtx &e = L.ev[(size_t)k];
         e = EventCtx{};
         e.kp = pl->kp;
-        e.K = pl->K;
+        e.K = L.poly ? pl->KP : pl->K;
         e.depo_base = L.n_total;
         e.n = (int32_t)n[idx[(size_t)k]];
         e.tile_base = (int32_t)L.ntiles_total;
         e.ntt = pl->ntt;
         e.nout = (int32_t)nout;
-        e.nblocks = pl->nblocks;
+        e.nblocks = L.poly ? pl->polyBlocks : pl->nblocks;
         e.mode = (kind == WCSIM_OUT_WIRE) ? 1 : 0;
         e.occ_shift = occ_shift_of(pl->Nt);
         // offsets within the chunk's data (the map: within the chunk's maps),
@@ -1000,7 +1042,7 @@ ChunkLayout plan_chunk(const wcsim_plane *const *planes, const int64_t *n,
         L.ntiles_total += pl->ntiles;
         L.nbands_total += occ_bands(pl->Np);
         L.nblk_r += rows_blocks((int)pl->Np);
-        L.nblk_p += pitch_blocks_total(pl);
+        L.nblk_p += L.poly ? poly_blocks_total(pl) : pitch_blocks_total(pl);
         L.nblk_c += rows_blocks((int)nout);
     }
     bd[nev] = (int32_t)L.n_total;
@@ -1144,7 +1186,7 @@ hipError_t launch_pipeline(const BatchPlan &bp, const wcsim_plane *const *planes
             (e = hipEventRecord(evR[slot], sR)) != hipSuccess ||
             (e = hipStreamWaitEvent(sF, evR[slot], 0)) != hipSuccess ||
             (mk && (e = hipEventRecord(mk[4], sF)) != hipSuccess) ||
-            (e = launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, sF,
+            (e = launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, L.poly, sF,
                                        mk ? mk + 5 : nullptr)) != hipSuccess ||
             (e = hipEventRecord(evF[slot], sF)) != hipSuccess)
             return e;

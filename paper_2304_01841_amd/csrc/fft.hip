@@ -863,6 +863,140 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_pitch_conv(PitchIo io, Bat
     });
 }
 
+// ---------------------------------------------------------------------------
+// Pass B for wire output, polyphase form.  With D = nimpact, wire w keeps grid
+// row p = w D + D/2, and per tick frequency out[w] = sum_r K[r] X[p + r0 - r]
+// (K: the response's tick spectrum, X: the grid's).  Split r = D a + b: with
+// cw = D/2 + r0 and cw - b = D s_b + phi_b (0 <= phi_b < D),
+//   out[w] = sum_b sum_a h_b[a] G_{phi_b}[w + s_b - a],
+//   h_b[a] = K[D a + b] (A = ceil(Rp / D) taps), G_phi[m] = X[D m + phi]:
+// D convolutions of wire-rate phase sequences with A-tap filters, summed.
+// Overlap-save along wires with blocks of M = 128: block w0 takes
+// x_b[j] = G_{phi_b}[w0 + s_b - (A - 1) + j] (j < M), forms
+// Y(f) = sum_b H_b(f) DFT_M(x_b)(f) with H_b = DFT_M(h_b) / (M N') resident,
+// and keeps y[j] = IDFT_M(Y)[j], j >= A - 1, as out[w0 + j - (A - 1)].
+// A workgroup takes one block of V = M - A + 1 wires for all F columns of a
+// chunk.  Per phase: a radix-8 pass from global memory into LDS, then a
+// radix-16 pass whose outputs (frequencies i + 8 t of column s: the same for
+// every phase) are multiplied by H_b and summed in registers; then the inverse
+// (a forward transform of the conjugate).  Workgroups are mapped XCD-major as
+// in k_pitch_conv.
+// ---------------------------------------------------------------------------
+constexpr int kPolyM = 128;
+constexpr int kPolyMaxTaps = 64;  // A <= 64: at least 65 wires per block
+struct PolyIo {
+    const float2 *X;  // [C][Np][F]
+    int Np;
+    const float2 *H;  // [C][D][M][F]
+    float2 *Y;        // [C][Nw][F]
+    int Nw, nblocks;
+};
+
+template <int F, bool BATCH>
+__global__ __launch_bounds__(8 * F) void k_pitch_poly(PolyIo io, BatchTables bt, int C, int D,
+                                                      int A, int cw, const float2 *twM)
+{
+    constexpr int NT = 8 * F, M = kPolyM, NSS = (F == 16) ? 4 : 3;
+    constexpr int NTAB = kTwLo + M / kTwLo + 1;  // two-level table of exp(-2 pi i j / M)
+    __shared__ float2 buf[M * F];
+    __shared__ float2 tab[NTAB];
+    int gblk = blockIdx.x;
+    if (BATCH) {
+        const int e = find_event(bt.pblk_base, bt.nev, gblk);
+        const EventCtx &E = bt.ev[e];
+        io.X = E.X;
+        io.Np = E.kp.Np;
+        io.H = E.K;
+        io.Y = E.Y;
+        io.Nw = E.nout;
+        io.nblocks = E.nblocks;
+        gblk -= bt.pblk_base[e];
+    }
+    const int xcd = gblk & 7, slot = gblk >> 3;
+    const int lc = slot / io.nblocks, blk = slot - lc * io.nblocks;
+    const int c = lc * 8 + xcd;
+    if (c >= C)
+        return;
+    for (int t = threadIdx.x; t < NTAB; t += NT)
+        tab[t] = twM[t];
+    const int V = M - A + 1, w0 = blk * V;
+    const int tid = threadIdx.x, s = tid % F, i = tid / F;  // radix-16 butterfly i < 8 of column s
+    const float2 *Xc = io.X + (int64_t)c * io.Np * F;
+    const float2 *Hc = io.H + (int64_t)c * D * M * F;
+    float2 acc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+        acc[t] = make_float2(0.0f, 0.0f);
+    InLds none;
+    for (int b = 0; b < D; ++b) {
+        const int phi = ((cw - b) % D + D) % D;
+        const int m0 = w0 + (cw - b - phi) / D - (A - 1);
+        // x_b[j] from global memory (zero outside the grid), from a clamped row
+        auto load = [&](int col, int j) {
+            const int q = (m0 + j) * D + phi;
+            const int qc = min(max(q, 0), io.Np - 1);
+            const float2 v = Xc[(int64_t)qc * F + col];
+            return (q == qc) ? v : make_float2(0.0f, 0.0f);
+        };
+        ct_pass<M, 8, 1, NSS, 1, F, NT, true, false>(buf, tab, load, none);
+        // radix-16 pass (p = 8) into registers, then times H_b, summed over b
+        const float2 *Hb = Hc + (int64_t)b * M * F;
+        float2 h[16], v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            h[t] = Hb[(i + 8 * t) * F + s];
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            v[t] = buf[(i + 8 * t) * F + s];
+        twiddle_powers<16>(v, tw_at(tab, i));
+        dft<16>(v);
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            acc[t] = cadd(acc[t], cmul(v[t], h[t]));
+        __syncthreads();  // every read of this phase precedes the next phase's writes
+    }
+    // inverse: the forward transform of the conjugate, conjugated
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+        buf[(i + 8 * t) * F + s] = conjf2(acc[t]);
+    __syncthreads();
+    float2 *Yc = io.Y + (int64_t)c * io.Nw * F;
+    const int nw = io.Nw;
+    auto store = [&](int col, int j, float2 val) {
+        const int w = w0 + j - (A - 1);
+        if (j < A - 1 || w >= nw)
+            return;
+        Yc[(int64_t)w * F + col] = conjf2(val);
+    };
+    ct_fft<M, NSS, 1, F, NT, 1, InLds, decltype(store), 8, 16>(buf, tab, none, store);
+}
+
+// Response spectra of the polyphase pass: H[c][b][f][s] = sum_{a < A, D a + b < Rp}
+// XR[c][D a + b][s] exp(-2 pi i a f / M) / (M N'), from the tick spectra XR of
+// the response rows (FP64 sums, once per plane).
+__global__ void k_poly_spectrum(const float2 *XR, int Rp, int C, int F, int D, int A,
+                                double scale, float2 *H)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)C * D * kPolyM * F;
+    if (idx >= total)
+        return;
+    const int sc = (int)(idx % F);
+    int64_t r = idx / F;
+    const int f = (int)(r % kPolyM);
+    r /= kPolyM;
+    const int b = (int)(r % D), c = (int)(r / D);
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < A && D * a + b < Rp; ++a) {
+        const float2 x = XR[((int64_t)c * Rp + D * a + b) * F + sc];
+        double sn, cs;
+        sincospi(-2.0 * (double)((a * f) % kPolyM) / (double)kPolyM, &sn, &cs);
+        re += (double)x.x * cs - (double)x.y * sn;
+        im += (double)x.x * sn + (double)x.y * cs;
+    }
+    H[idx] = make_float2((float)(re * scale), (float)(im * scale));
+}
+
 int ilog2(int v)
 {
     int s = 0;
@@ -1141,20 +1275,42 @@ int pitch_blocks_total(const wcsim_plane *pl)
 bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b)
 {
     return a->Nfft == b->Nfft && a->L == b->L && a->F == b->F && a->Fb == b->Fb &&
+           a->poly == b->poly &&
            a->fold == b->fold && a->Rp == b->Rp &&
            a->Rt == b->Rt && a->r0 == b->r0 && a->tile == b->tile && a->Nt == b->Nt &&
            a->kp.nimpact == b->kp.nimpact && a->device == b->device;
 }
 
+int poly_blocks_total(const wcsim_plane *pl)
+{
+    return 8 * ((pl->C + 7) / 8) * pl->polyBlocks;
+}
+
+// The polyphase pitch pass of one plane (io set) or of a batch (tables).
+template <bool B>
+hipError_t poly_any(const wcsim_plane *pl, const PolyIo &io, const BatchTables &bt,
+                    unsigned blocks, hipStream_t s)
+{
+    if (pl->F == 16)
+        hipLaunchKernelGGL((k_pitch_poly<16, B>), dim3(blocks), dim3(128), 0, s, io, bt, pl->C,
+                           (int)pl->kp.nimpact, pl->polyA, pl->polyCw, pl->twP);
+    else
+        hipLaunchKernelGGL((k_pitch_poly<8, B>), dim3(blocks), dim3(64), 0, s, io, bt, pl->C,
+                           (int)pl->kp.nimpact, pl->polyA, pl->polyCw, pl->twP);
+    return hipGetLastError();
+}
+
 hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
-                                 int nblk_p, int nblk_c, hipStream_t s, const hipEvent_t *ev)
+                                 int nblk_p, int nblk_c, bool poly, hipStream_t s,
+                                 const hipEvent_t *ev)
 {
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     hipError_t e;
     if ((e = rows_r2c_any<true>(pl, R2CIo{}, bt, (unsigned)nblk_r, s)) != hipSuccess ||
         (e = mark(0)) != hipSuccess)
         return e;
-    if ((e = pitch_any<true>(pl, PitchIo{}, bt, (unsigned)nblk_p, 1.0f, s)) != hipSuccess ||
+    if ((e = poly ? poly_any<true>(pl, PolyIo{}, bt, (unsigned)nblk_p, s)
+                  : pitch_any<true>(pl, PitchIo{}, bt, (unsigned)nblk_p, 1.0f, s)) != hipSuccess ||
         (e = mark(1)) != hipSuccess)
         return e;
     if ((e = rows_c2r_any<true>(pl, C2RIo{}, bt, (unsigned)nblk_c, s)) != hipSuccess)
@@ -1182,9 +1338,14 @@ hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
     if ((e = rows_r2c(pl, grid, (int)pl->Np, (int)pl->Nt, pl->Nt, X, s, occ)) != hipSuccess ||
         (e = mark(0)) != hipSuccess)
         return e;
-    if ((e = pitch_pass(pl, X, (int)pl->Np, pl->K, Y, (int)nout, pl->nblocks,
-                        out_kind == WCSIM_OUT_WIRE ? 1 : 0, 1.0f, s)) != hipSuccess ||
-        (e = mark(1)) != hipSuccess)
+    if (out_kind == WCSIM_OUT_WIRE && pl->poly) {
+        const PolyIo io = {X, (int)pl->Np, pl->KP, Y, (int)pl->Nw, pl->polyBlocks};
+        e = poly_any<false>(pl, io, BatchTables{}, (unsigned)poly_blocks_total(pl), s);
+    } else {
+        e = pitch_pass(pl, X, (int)pl->Np, pl->K, Y, (int)nout, pl->nblocks,
+                       out_kind == WCSIM_OUT_WIRE ? 1 : 0, 1.0f, s);
+    }
+    if (e != hipSuccess || (e = mark(1)) != hipSuccess)
         return e;
     if ((e = rows_c2r(pl, Y, (int)nout, out, (int)pl->Nt, pl->Nt, s)) != hipSuccess)
         return e;
@@ -1232,7 +1393,18 @@ hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void 
     if ((e = rows_r2c(pl, resp_dev, pl->Rp, pl->Rt, pl->Rt, XR, s)) != hipSuccess)
         return e;
     const float scale = (float)(1.0 / ((double)pl->L * (double)pl->Nfft));
-    return pitch_pass(pl, XR, pl->Rp, nullptr, pl->K, pl->L, 1, 2, scale, s);
+    if ((e = pitch_pass(pl, XR, pl->Rp, nullptr, pl->K, pl->L, 1, 2, scale, s)) != hipSuccess)
+        return e;
+    if (!pl->poly)
+        return hipSuccess;
+    const int64_t total = (int64_t)pl->C * pl->kp.nimpact * kPolyM * pl->F;
+    hipLaunchKernelGGL(k_poly_spectrum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, XR,
+                       pl->Rp, pl->C, pl->F, (int)pl->kp.nimpact, pl->polyA,
+                       1.0 / ((double)kPolyM * (double)pl->Nfft), pl->KP);
+    return hipGetLastError();
 }
+
+int poly_block_rows() { return kPolyM; }
+int poly_max_taps() { return kPolyMaxTaps; }
 
 }  // namespace wcs

@@ -155,6 +155,13 @@ struct wcsim_plane {
     float2 *twL;     // two-level table of exp(-2 pi i j / L), j < L
     float2 *twF;     // two-level table of exp(-2 pi i j / L10), j < L10 (fold only)
     float2 *K;       // response spectrum [C][L][F], scaled by 1/(L N')
+    // polyphase wire-output pitch pass (poly): response spectra KP[C][D][M][F]
+    // of the D phase filters of polyA = ceil(Rp / D) taps, scaled by
+    // 1/(M N'); blocks of polyV = M - polyA + 1 wires; polyCw = D/2 + r0
+    bool poly;
+    int polyA, polyV, polyBlocks, polyCw;
+    float2 *KP;
+    float2 *twP;     // two-level table of exp(-2 pi i j / M), j < M
     // owner of K and the twiddle tables; planes with the same response and
     // transform sizes share one
     std::shared_ptr<struct wcs_spectrum> spectrum;
@@ -257,11 +264,16 @@ size_t response_work_bytes(const wcsim_plane *pl);
 // Batched convolution: the three passes over every event of the tables;
 // nblk_* = total workgroups of each pass (the last entries of the bases).
 // `ev` (nullable): 3 events recorded after passes A, B and C.
+// `poly`: wire output through the polyphase pitch pass (pl->poly), whose
+// workgroup counts are in the tables' pblk_base.
 hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
-                                 int nblk_p, int nblk_c, hipStream_t s,
+                                 int nblk_p, int nblk_c, bool poly, hipStream_t s,
                                  const hipEvent_t *ev = nullptr);
 int rows_blocks(int nrows);                       // workgroups of a tick-axis pass
 int pitch_blocks_total(const wcsim_plane *pl);    // workgroups of the pitch pass
+int poly_blocks_total(const wcsim_plane *pl);     // workgroups of the polyphase pitch pass
+int poly_block_rows();                            // M, the polyphase block transform length
+int poly_max_taps();                              // longest phase filter of the polyphase pass
 bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b);
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }

@@ -16,7 +16,7 @@ def test_candidates_start_with_the_default_and_are_distinct():
     keys = {json.dumps(x, sort_keys=True) for x in c}
     assert len(keys) == len(c)
     for x in c:
-        assert set(x) <= {"fft_ticks", "fft_pitch", "freq_chunk", "tile"}
+        assert set(x) <= {"fft_ticks", "fft_pitch", "freq_chunk", "tile", "wire_mode"}
 
 
 def test_cache_key_separates_shapes_and_depo_scales():

@@ -167,9 +167,10 @@ def test_convolve_random_response(ws, nw, nimp, nt, Rp, Rt, r0):
 
 def test_convolve_schedules_agree(ws):
     """The result does not depend on the FFT schedule (padded sizes, chunk
-    width, pitch block length, column split of the pitch pass, and the
-    folded wire-output inverse when the block length is a multiple of the
-    impact count): pitch and wire output against the oracle."""
+    width, pitch block length, column split of the pitch pass, the folded
+    wire-output inverse when the block length is a multiple of the impact
+    count, and the polyphase wire pass against the overlap-save blocks):
+    pitch and wire output against the oracle."""
     log("case: convolve schedules")
     rng = np.random.default_rng(5)
     pl = W.plane(40, 900)
@@ -185,11 +186,21 @@ def test_convolve_schedules_agree(ws):
                {"fft_pitch": 1024, "freq_chunk": 16}, {"fft_ticks": 6250}, {"fft_ticks": 1200},
                {"fft_pitch": 640, "freq_chunk": 16}, {"fft_pitch": 960, "freq_chunk": 16},
                {"fft_pitch": 640, "freq_chunk": 8}, {"fft_pitch": 100}, {"fft_pitch": 320}):
-        P = ws.Plane(pl, W.physics(False), R, r0=25, schedule=sc)
-        out = ws.convolve(P, g, kind=ws.OUT_PITCH)
-        assert normwise(out.cpu().numpy(), ref) <= CONV_TOL, sc
-        outw = ws.convolve(P, g, kind=ws.OUT_WIRE)
-        assert normwise(outw.cpu().numpy(), refw) <= CONV_TOL, ("wire", sc)
+        for wm in (0, 2):
+            P = ws.Plane(pl, W.physics(False), R, r0=25, schedule=dict(sc, wire_mode=wm))
+            assert P.info["wire_polyphase"] == (1 if wm == 0 else 0)
+            out = ws.convolve(P, g, kind=ws.OUT_PITCH)
+            assert normwise(out.cpu().numpy(), ref) <= CONV_TOL, sc
+            outw = ws.convolve(P, g, kind=ws.OUT_WIRE)
+            assert normwise(outw.cpu().numpy(), refw) <= CONV_TOL, ("wire", sc, wm)
+    # the polyphase pass asked for where it cannot apply
+    with pytest.raises(ws.WcsimError):
+        ws.Plane(W.plane(40, 900, nimpact=1), W.physics(False), R, r0=25,
+                 schedule={"wire_mode": 1})
+    Rlong = W.random_response(rng, 700, 20)  # ceil(700 / 10) = 70 taps per phase
+    with pytest.raises(ws.WcsimError):
+        ws.Plane(pl, W.physics(False), Rlong, r0=350, schedule={"wire_mode": 1})
+    assert ws.Plane(pl, W.physics(False), Rlong, r0=350).info["wire_polyphase"] == 0
 
 
 def test_convolve_delta_response_identity(ws):
