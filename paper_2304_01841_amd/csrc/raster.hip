@@ -969,7 +969,7 @@ constexpr int kBatchItems = 64 * kFluctItems;
 // time makes every deposit a plain read-add-write LDS access (two patches of
 // a batch may cover the same cell).  No other wavefront touches the region.
 // The region's non-zero cells are then added to the grid with float atomics.
-template <int TP, int TT, bool B>
+template <int TP, int TT, bool B, bool FLUCT>
 __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const int4 item,
                                             const float *__restrict__ records,
                                             const EventCtx &e0, const BatchTables &bt)
@@ -1072,7 +1072,7 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
                 const float wp = valid ? rec[kRecWp + i] : 0.0f;
                 const float4 wt = *(const float4 *)(rec + kRecWt + 4 * qq);
                 const float w4[4] = {wt.x, wt.y, wt.z, wt.w};
-                if (P.fluct) {
+                if constexpr (FLUCT) {
                     const uint4 rr = philox4x32_10(
                         make_uint4((uint32_t)qd, (uint32_t)(lo_p + i), (uint32_t)d, E.event),
                         P.key0, P.key1);
@@ -1096,7 +1096,7 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
                 }
             }
         }
-        if (P.fluct) {
+        if constexpr (FLUCT) {
             // the lane of each patch of the batch forms its total S as the
             // difference of the prefix sums at its last item and before its
             // first, and its factor q / S, in FP64 (negative when the clamped
@@ -1182,7 +1182,9 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
     }
 }
 
-template <int TP, int TT, bool B>
+// FLUCT: the planes fluctuate (a template argument, so that no branch on it
+// separates a pass's weight loads from the Philox rounds that need no weight).
+template <int TP, int TT, bool B, bool FLUCT>
 __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ records,
                                                      const int4 *__restrict__ items,
                                                      const int32_t *__restrict__ counters,
@@ -1197,7 +1199,7 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     // blockIdx.x, + gridDim.x, ... so that every item is drawn.
     const int nitems_all = counters[2];
     for (int itm = blockIdx.x; itm < nitems_all; itm += gridDim.x)
-        raster_item<TP, TT, B>(acc4, xsum, items[itm], records, e0, bt);
+        raster_item<TP, TT, B, FLUCT>(acc4, xsum, items[itm], records, e0, bt);
 }
 
 // Descriptor of a single event (kernel argument; no table lookups).
@@ -1508,6 +1510,26 @@ RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
     return raster_work_carve_batch(pl, n, pl->ntiles, occ_bands(pl->Np), base);
 }
 
+template <bool B, bool FLUCT>
+static void launch_raster_tiles(int tile, unsigned grid, const RasterWork &w, const EventCtx &e0,
+                                const BatchTables &bt, hipStream_t s)
+{
+    switch (tile) {
+    case 1:
+        hipLaunchKernelGGL((k_raster_tiles<32, 32, B, FLUCT>), dim3(grid), dim3(64), 0, s,
+                           w.records, w.items, w.counters, e0, bt);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_raster_tiles<64, 8, B, FLUCT>), dim3(grid), dim3(64), 0, s,
+                           w.records, w.items, w.counters, e0, bt);
+        break;
+    default:
+        hipLaunchKernelGGL((k_raster_tiles<32, 8, B, FLUCT>), dim3(grid), dim3(64), 0, s,
+                           w.records, w.items, w.counters, e0, bt);
+        break;
+    }
+}
+
 // The launch sequence shared by single events and batches: clear counters,
 // window + tile per depo, tile schedule, depo records, LDS-tiled raster,
 // large-patch raster.  `ev` (single events only) receives three stage marks.
@@ -1552,20 +1574,10 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
     const unsigned grid_items = raster_grid(ntiles, n);
-    switch (pl->tile) {
-    case 1:
-        hipLaunchKernelGGL((k_raster_tiles<32, 32, B>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.counters, e0, bt);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_raster_tiles<64, 8, B>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.counters, e0, bt);
-        break;
-    default:
-        hipLaunchKernelGGL((k_raster_tiles<32, 8, B>), dim3(grid_items), dim3(64), 0, s,
-                           w.records, w.items, w.counters, e0, bt);
-        break;
-    }
+    if (pl->kp.fluct)
+        launch_raster_tiles<B, true>(pl->tile, grid_items, w, e0, bt, s);
+    else
+        launch_raster_tiles<B, false>(pl->tile, grid_items, w, e0, bt, s);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(1)) != hipSuccess)
         return e;
     // Depos whose patch does not fit a tile region: one workgroup each, direct
