@@ -518,10 +518,10 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
         io.occ_shift = E.occ_shift;
         blk -= bt.rblk_base[e];
     }
-    const float *__restrict__ in = io.in;
+    const gptr<const float> in = glb(io.in);
     const int nrows = io.nrows, ncols = io.ncols;
     const int64_t in_stride = io.in_stride;
-    float2 *__restrict__ X = io.X;
+    const gptr<float2> X = glb(io.X);
     const int RPW = 1 << rpw_shift;
     const int S = N2 + 1;
     float2 *tabN2 = lds + RPW * S;
@@ -554,18 +554,18 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_r2c(R2CIo io, BatchTa
     auto load2 = [&](int s, int n) {  // even ncols and stride: one 8-byte load
         const int row = row0 + s, t = 2 * n;
         const int tc = min(t, ncols - 2);
-        const float *src = in + (int64_t)min(row, nrows - 1) * in_stride + tc;
+        const gptr<const float> src = in + (int64_t)min(row, nrows - 1) * in_stride + tc;
         const bool occ = (occ_m >> (tc >> osh)) & 1ull;
-        const float2 v = *(occ ? (const float2 *)src : g_zero_pair);
+        const float2 v = *(occ ? (gptr<const float2>)src : glb(g_zero_pair));
         const bool ok = row < nrows && t < ncols;
         return ok ? v : make_float2(0.0f, 0.0f);
     };
     auto load1 = [&](int s, int n) {
         const int row = row0 + s, t = 2 * n;
-        const float *src = in + (int64_t)min(row, nrows - 1) * in_stride;
+        const gptr<const float> src = in + (int64_t)min(row, nrows - 1) * in_stride;
         const int ta = min(t, ncols - 1), tb = min(t + 1, ncols - 1);
         const bool occ = (occ_m >> (ta >> osh)) & 1ull;
-        const float *zf = (const float *)g_zero_pair;
+        const gptr<const float> zf = (gptr<const float>)glb(g_zero_pair);
         const float a = *(occ ? src + ta : zf), b = *(occ ? src + tb : zf);
         const bool ok = row < nrows;
         return make_float2((ok && t < ncols) ? a : 0.0f, (ok && t + 1 < ncols) ? b : 0.0f);
@@ -633,9 +633,9 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(C2RIo io, BatchTa
         io.out_stride = E.kp.Nt;
         blk -= bt.cblk_base[e];
     }
-    const float2 *__restrict__ Y = io.Y;
+    const gptr<const float2> Y = glb(io.Y);
     const int nrows = io.nrows, ncols = io.ncols;
-    float *__restrict__ out = io.out;
+    const gptr<float> out = glb(io.out);
     const int64_t out_stride = io.out_stride;
     const int RPW = 1 << rpw_shift;
     const int S = N2 + 1;
@@ -652,8 +652,10 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(C2RIo io, BatchTa
             const int s = (g >> F_shift) & (RPW - 1);
             const int c = g >> (F_shift + rpw_shift);
             const int row = row0 + s;
-            return (row < nrows) ? Y[(((int64_t)c * nrows + row) << F_shift) + f]
-                                 : make_float2(0.0f, 0.0f);
+            if (row >= nrows)
+                return make_float2(0.0f, 0.0f);
+            const float2 v = Y[(((int64_t)c * nrows + row) << F_shift) + f];
+            return v;
         },
         [&](int g, float2 v) {
             const int f = g & (F - 1);
@@ -684,9 +686,9 @@ __global__ __launch_bounds__(FFT::kMaxThreads) void k_rows_c2r(C2RIo io, BatchTa
         const int row = row0 + s, t = 2 * n;
         if (row >= nrows || t >= ncols)
             return;
-        float *dst = out + (int64_t)row * out_stride;
+        const gptr<float> dst = out + (int64_t)row * out_stride;
         if (vec2) {
-            *(float2 *)(dst + t) = make_float2(z.x, -z.y);
+            *(gptr<float2>)(dst + t) = make_float2(z.x, -z.y);
         } else {
             dst[t] = z.x;
             if (t + 1 < ncols)
@@ -921,8 +923,8 @@ __global__ __launch_bounds__(8 * F) void k_pitch_poly(PolyIo io, BatchTables bt,
         tab[t] = twM[t];
     const int V = M - A + 1, w0 = blk * V;
     const int tid = threadIdx.x, s = tid % F, i = tid / F;  // radix-16 butterfly i < 8 of column s
-    const float2 *Xc = io.X + (int64_t)c * io.Np * F;
-    const float2 *Hc = io.H + (int64_t)c * D * M * F;
+    const gptr<const float2> Xc = glb(io.X) + (int64_t)c * io.Np * F;
+    const gptr<const float2> Hc = glb(io.H) + (int64_t)c * D * M * F;
     float2 acc[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t)
@@ -940,7 +942,7 @@ __global__ __launch_bounds__(8 * F) void k_pitch_poly(PolyIo io, BatchTables bt,
         };
         ct_pass<M, 8, 1, NSS, 1, F, NT, true, false>(buf, tab, load, none);
         // radix-16 pass (p = 8) into registers, then times H_b, summed over b
-        const float2 *Hb = Hc + (int64_t)b * M * F;
+        const gptr<const float2> Hb = Hc + (int64_t)b * M * F;
         float2 h[16], v[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t)
@@ -960,7 +962,7 @@ __global__ __launch_bounds__(8 * F) void k_pitch_poly(PolyIo io, BatchTables bt,
     for (int t = 0; t < 16; ++t)
         buf[(i + 8 * t) * F + s] = conjf2(acc[t]);
     __syncthreads();
-    float2 *Yc = io.Y + (int64_t)c * io.Nw * F;
+    const gptr<float2> Yc = glb(io.Y) + (int64_t)c * io.Nw * F;
     const int nw = io.Nw;
     auto store = [&](int col, int j, float2 val) {
         const int w = w0 + j - (A - 1);

@@ -452,9 +452,10 @@ __global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables b
         const EventCtx &Ev = B ? bt.ev[find_event(bt.depo_base, bt.nev, gd)] : e0;
         const PlaneParams &P = Ev.kp;
         const uint32_t event = Ev.event;
-        float *grid = Ev.grid;
+        const gptr<float> grid = glb(Ev.grid);
         const int d = gd - (int)Ev.depo_base;  // index in the event's own depo array
-        const Win w = depo_window(Ev.depos[d], P);
+        const wcsim_depo dep = glb(Ev.depos)[d];
+        const Win w = depo_window(dep, P);
         if (w.status != 0)
             continue;
         block_axis_weights<NT>(w.lo_p, w.n_p, w.mu_p, w.s_p, Wp, E, red);
@@ -593,7 +594,7 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane
 
 // Mark the occupancy-map blocks that a window (status 0: it meets the grid)
 // reaches.  Every writer stores the same value, so no atomics are needed.
-__device__ __forceinline__ void mark_blocks(const Win &w, const PlaneParams &P, uint8_t *occ,
+__device__ __forceinline__ void mark_blocks(const Win &w, const PlaneParams &P, gptr<uint8_t> occ,
                                             int shift)
 {
     const int p0 = max(w.lo_p, 0), p1 = min(w.lo_p + w.n_p, P.Np) - 1;
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(256) void k_prep_bin(EventCtx e0, BatchTables bt, i
         if (w.status == 1 || w.status == 3) {
             bad = true;
         } else if (w.status == 0) {
-            mark_blocks(w, P, E.occ, E.occ_shift);
+            mark_blocks(w, P, glb(E.occ), E.occ_shift);
             const int tp = min(max(w.lo_p, 0), P.Np - 1) / g.tp;
             const int tt = min(max(w.lo_t, 0), P.Nt - 1) / g.tt;
             if (fits_tile(w, tp * g.tp, tt * g.tt, g, P))
@@ -848,8 +849,8 @@ constexpr int kStageStride = kRecWords + 1;  // odd: one LDS bank per lane
 
 // Zero the blocks of one band of kOccRows grid rows whose bits are set in
 // `m` (bit c: ticks c 2^shift .. (c + 1) 2^shift - 1), by one wavefront.
-__device__ __forceinline__ void clear_blocks(float *grid, int Np, int Nt, int band, uint64_t m,
-                                             int shift, int lane)
+__device__ __forceinline__ void clear_blocks(gptr<float> grid, int Np, int Nt, int band,
+                                             uint64_t m, int shift, int lane)
 {
     const int r0 = band * kOccRows, nr = min(kOccRows, Np - r0);
     while (m) {
@@ -860,7 +861,7 @@ __device__ __forceinline__ void clear_blocks(float *grid, int Np, int Nt, int ba
             const int nc = (c1 - c0) >> 2;
             for (int i = lane; i < nr * nc; i += 64) {
                 const int r = i / nc;
-                *(float4 *)(grid + (int64_t)(r0 + r) * Nt + c0 + 4 * (i - r * nc)) =
+                *(gptr<float4>)(grid + (int64_t)(r0 + r) * Nt + c0 + 4 * (i - r * nc)) =
                     make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         } else {
@@ -893,8 +894,8 @@ __global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt
             const int e = B ? find_event(bt.band_base, bt.nev, gb) : 0;
             const EventCtx &E = B ? bt.ev[e] : e0;
             const int band = B ? gb - bt.band_base[e] : gb;
-            const uint64_t m = __ballot(E.occ[band * kOccCols + lane] != 0);
-            clear_blocks(E.grid, E.kp.Np, E.kp.Nt, band, m, E.occ_shift, lane);
+            const uint64_t m = __ballot(glb(E.occ)[band * kOccCols + lane] != 0);
+            clear_blocks(glb(E.grid), E.kp.Np, E.kp.Nt, band, m, E.occ_shift, lane);
         }
         return;
     }
@@ -1160,7 +1161,7 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
     // Flush: consecutive lanes take consecutive ticks of a row, so that one
     // atomic instruction covers 256 contiguous bytes (few L2 lines) rather
     // than 16-byte pieces of many lines.
-    float *grid = E.grid;
+    const gptr<float> grid = glb(E.grid);
     const float *acc = (const float *)acc4;
     const int W = 4 * bnq;  // floats per bounding-box row
     const int nrows = max(br1 - br0, 0);
@@ -1618,7 +1619,7 @@ __global__ __launch_bounds__(64) void k_clear_unoccupied(float *grid, int Np, in
     const int nb = (Nt + (1 << shift) - 1) >> shift;
     const uint64_t valid = (nb >= 64) ? ~0ull : ((1ull << nb) - 1ull);
     const uint64_t m = __ballot(occ[band * kOccCols + lane] != 0);
-    clear_blocks(grid, Np, Nt, band, ~m & valid, shift, lane);
+    clear_blocks(glb(grid), Np, Nt, band, ~m & valid, shift, lane);
 }
 
 hipError_t launch_clear_unoccupied(float *grid, int Np, int Nt, const uint8_t *occ, int shift,

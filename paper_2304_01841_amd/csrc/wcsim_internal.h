@@ -95,6 +95,19 @@ struct BatchTables {
     int32_t nev;
 };
 
+// A pointer read from memory (an event's table entry) has no address space
+// for the compiler, which then emits flat instructions for its accesses; those
+// count against the LDS wait counter too, so each LDS wait in the kernel also
+// waits for the HBM loads and atomics in flight.  Every pointer the kernels
+// take addresses device memory: this cast lets the compiler emit global ones.
+// (The host pass, which only checks the kernels' bodies, has no such space.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> using gptr = __attribute__((address_space(1))) T *;
+#else
+template <class T> using gptr = T *;
+#endif
+template <class T> __device__ __forceinline__ gptr<T> glb(T *p) { return (gptr<T>)p; }
+
 // Largest e with base[e] <= key (base ascending, base[0] = 0).
 __device__ __forceinline__ int find_event(const int32_t *base, int nev, int key)
 {
