@@ -131,6 +131,15 @@ typedef struct {
                          * transforms and summed; needs nimpact > 1 and at most 64
                          * taps), 2 = overlap-save blocks of fft_pitch rows; 0 =
                          * polyphase where it applies, else blocks */
+    int32_t deterministic; /* 1: the simulated grid and output are reproducible bit for
+                         * bit (Sec. 2 step 2 sums in a fixed order): depos are
+                         * listed per tile in index order, tiles are flushed in
+                         * colour phases whose LDS regions are disjoint with plain
+                         * read-add-writes, and depos too large for a tile are
+                         * added one after another in index order; 0 (default) =
+                         * float atomics, whose order of addition varies from run
+                         * to run.  Applies to the fused simulate entry points
+                         * (single events and batches). */
 } wcsim_schedule;
 
 /* Derived sizes of a plane (read-only). */
@@ -146,6 +155,7 @@ typedef struct {
     int32_t wire_fold;      /* 1: wire output folds the pitch inverse to fft_pitch / nimpact */
     int32_t wire_polyphase; /* 1: wire output uses the polyphase pitch pass */
     int32_t wire_blocks;    /* polyphase blocks along the wires (0 without) */
+    int32_t deterministic;  /* 1: reproducible sums (wcsim_schedule.deterministic) */
 } wcsim_plane_info;
 
 typedef struct wcsim_plane wcsim_plane;
@@ -432,7 +442,7 @@ wcsim_status wcsim_philox4x32_10(const uint32_t *ctr, const uint32_t *key, int64
 
 const char *wcsim_last_error(void);
 
-/* Library version (major*10000 + minor*100 + patch): 10300. */
+/* Library version (major*10000 + minor*100 + patch): 10400. */
 int32_t wcsim_version(void);
 
 #ifdef __cplusplus

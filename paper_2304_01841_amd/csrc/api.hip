@@ -218,6 +218,10 @@ wcsim_status choose_schedule(wcsim_plane *pl, const wcsim_schedule *sc)
     pl->polyCw = D / 2 + pl->r0;
     pl->H = pl->N2 + 1;
     pl->C = (pl->H + pl->F - 1) / pl->F;
+    const int det = sc ? sc->deterministic : 0;
+    if (det < 0 || det > 1)
+        return fail(WCSIM_E_INVALID, "deterministic must be 0 or 1");
+    pl->det = det == 1;
     pl->tile = (sc && sc->tile) ? sc->tile : 0;
     if (pl->tile < 0 || pl->tile >= kNumTileShapes)
         return fail(WCSIM_E_INVALID, "unknown tile shape");
@@ -425,7 +429,7 @@ using namespace wcs;
 
 extern "C" {
 
-int32_t wcsim_version(void) { return 10300; }
+int32_t wcsim_version(void) { return 10400; }
 
 const char *wcsim_last_error(void) { return g_last_error.c_str(); }
 
@@ -454,6 +458,7 @@ wcsim_status wcsim_plane_create_sharing(const wcsim_plane_desc *desc, const wcsi
     sc.freq_chunk = donor->F;
     sc.tile = donor->tile;
     sc.wire_mode = donor->poly ? 0 : 2;
+    sc.deterministic = donor->det ? 1 : 0;
     // the donor's transform may be too short for a longer readout
     if (desc && donor->Nfft < desc->nticks + effective_resp_nticks(desc) - 1)
         return plane_create(desc, phys, nullptr, nullptr, stream, out);
@@ -493,6 +498,7 @@ wcsim_status wcsim_plane_get_info(const wcsim_plane *pl, wcsim_plane_info *info)
     info->wire_fold = pl->fold ? 1 : 0;
     info->wire_polyphase = pl->poly ? 1 : 0;
     info->wire_blocks = pl->poly ? pl->polyBlocks : 0;
+    info->deterministic = pl->det ? 1 : 0;
     return WCSIM_OK;
 }
 

@@ -1279,7 +1279,8 @@ bool same_schedule_class(const wcsim_plane *a, const wcsim_plane *b)
     return a->Nfft == b->Nfft && a->L == b->L && a->F == b->F && a->Fb == b->Fb &&
            a->poly == b->poly && a->kp.fluct == b->kp.fluct &&
            a->fold == b->fold && a->Rp == b->Rp &&
-           a->Rt == b->Rt && a->r0 == b->r0 && a->tile == b->tile && a->Nt == b->Nt &&
+           a->Rt == b->Rt && a->r0 == b->r0 && a->tile == b->tile && a->det == b->det &&
+           a->Nt == b->Nt &&
            a->kp.nimpact == b->kp.nimpact && a->device == b->device;
 }
 

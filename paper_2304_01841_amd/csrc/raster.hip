@@ -23,6 +23,8 @@
 
 #include <limits.h>
 
+#include <atomic>
+
 #include "wcsim_internal.h"
 
 namespace wcs {
@@ -531,6 +533,8 @@ __global__ __launch_bounds__(NT) void k_patch_generic(EventCtx e0, BatchTables b
                 }
             }
         }
+        if (gridDim.x == 1)
+            __threadfence();  // one workgroup: this patch's adds complete before the next's
         __syncthreads();
     }
 }
@@ -604,6 +608,10 @@ __device__ __forceinline__ void mark_blocks(const Win &w, const PlaneParams &P, 
             occ[b * kOccCols + c] = 1;
 }
 
+// depo_tile of a depo whose patch does not fit a tile region (-1: no tile and
+// no patch).
+constexpr int32_t kTileLarge = -2;
+
 // Window and tile of every depo.  Slots in a tile's list come from one atomic
 // per distinct tile per wavefront (consecutive depos of a track share tiles).
 // Depos and tiles carry global indices: in a batch, depo gd belongs to the
@@ -665,7 +673,7 @@ __global__ __launch_bounds__(256) void k_prep_bin(EventCtx e0, BatchTables bt, i
         active &= ~same;
     }
     if (d < ntotal) {
-        depo_tile[d] = tile;
+        depo_tile[d] = big ? kTileLarge : tile;
         depo_slot[d] = slot;
     }
 }
@@ -752,6 +760,155 @@ __global__ __launch_bounds__(kSchedThreads) void k_tile_schedule(int32_t *tile_c
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kSchedThreads - 1)
         counters[2] = off_c;
+}
+
+// ---------------------------------------------------------------------------
+// Tile lists in depo order (reproducible sums).  The slots that binning takes
+// by atomics order a tile's depos as the wavefronts happened to run; a stable
+// least-significant-digit radix sort of the keys (tile; kTileLarge depos after
+// the last tile; depos without a patch last) over the depo indices gives every
+// depo its rank in its tile's list by index, and the large-patch list in index
+// order.  Blocks of kSortBlock keys; 8-bit digits, one count / offsets /
+// scatter triple per digit.
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256, kSortPer = 16, kSortBlock = kSortThreads * kSortPer;
+static_assert(kSortThreads == kScanThreads, "the sort uses the block scan");
+
+__global__ __launch_bounds__(256) void k_sort_keys(const int32_t *depo_tile, int64_t n,
+                                                   uint32_t ntiles, uint32_t *keys,
+                                                   int32_t *vals)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int t = depo_tile[i];
+    keys[i] = (t >= 0) ? (uint32_t)t : (t == kTileLarge ? ntiles : ntiles + 1u);
+    vals[i] = (int32_t)i;
+}
+
+// counts[b][d]: keys of block b with digit d; totals[d] += the block's count.
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint32_t *keys, int64_t n,
+                                                            int shift, int32_t *counts,
+                                                            int32_t *totals)
+{
+    __shared__ int hist[256];
+    const int tid = threadIdx.x;
+    hist[tid] = 0;
+    __syncthreads();
+    const int64_t b0 = blockIdx.x * (int64_t)kSortBlock;
+#pragma unroll 4
+    for (int k = 0; k < kSortPer; ++k) {
+        const int64_t i = b0 + k * kSortThreads + tid;
+        if (i < n)
+            atomicAdd(&hist[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    const int c = hist[tid];
+    counts[(int64_t)blockIdx.x * 256 + tid] = c;
+    if (c)
+        atomicAdd(&totals[tid], c);
+}
+
+// One workgroup, thread d: the first output position of digit d in each block
+// (the keys of smaller digits plus those of digit d in earlier blocks), in
+// place; the totals are cleared for the next digit.
+__global__ __launch_bounds__(kSortThreads) void k_sort_offsets(int32_t *counts, int nblk,
+                                                              int32_t *totals)
+{
+    __shared__ int sh[kSortThreads / 64];
+    const int d = threadIdx.x;
+    int all;
+    int run = block_exclusive_scan<int>(totals[d], sh, &all);
+    totals[d] = 0;
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+        int c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            c[u] = counts[(int64_t)(b + u) * 256 + d];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            counts[(int64_t)(b + u) * 256 + d] = run;
+            run += c[u];
+        }
+    }
+    for (; b < nblk; ++b) {
+        const int c = counts[(int64_t)b * 256 + d];
+        counts[(int64_t)b * 256 + d] = run;
+        run += c;
+    }
+}
+
+// Stable scatter of one block: its keys are taken in rounds of kSortThreads
+// consecutive keys; a key's position is its digit's next free slot plus the
+// keys of the same digit before it in the round (earlier wavefronts, then
+// lower lanes of its own).
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t *kin,
+                                                              const int32_t *vin, int64_t n,
+                                                              int shift, const int32_t *offsets,
+                                                              uint32_t *kout, int32_t *vout)
+{
+    constexpr int NW = kSortThreads / 64;
+    __shared__ int next[256];
+    __shared__ int wcnt[NW][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    next[tid] = offsets[(int64_t)blockIdx.x * 256 + tid];
+#pragma unroll
+    for (int u = 0; u < NW; ++u)
+        wcnt[u][tid] = 0;
+    __syncthreads();
+    const int64_t b0 = blockIdx.x * (int64_t)kSortBlock;
+    for (int k = 0; k < kSortPer; ++k) {
+        const int64_t i = b0 + k * kSortThreads + tid;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const int32_t val = valid ? vin[i] : 0;
+        const int dg = (int)((key >> shift) & 255u);
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t m = __ballot((dg >> bit) & 1);
+            same &= ((dg >> bit) & 1) ? m : ~m;
+        }
+        const int rank = __popcll(same & lanemask_lt(lane));
+        if (valid && rank == 0)
+            wcnt[w][dg] = __popcll(same);
+        __syncthreads();
+        if (valid) {
+            int pos = next[dg] + rank;
+            for (int u = 0; u < w; ++u)
+                pos += wcnt[u][dg];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();  // every position is formed before the counts move on
+        int add = 0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            add += wcnt[u][tid];
+            wcnt[u][tid] = 0;
+        }
+        next[tid] += add;
+        __syncthreads();
+    }
+}
+
+// From the sorted keys: each tile-listed depo's slot (its rank in the tile's
+// list) and the large-patch list in depo order.  tile_off: the tiles'
+// exclusive list offsets, ntiles + 1 entries.
+__global__ __launch_bounds__(256) void k_sort_slots(const uint32_t *keys, const int32_t *vals,
+                                                    int64_t n, uint32_t ntiles,
+                                                    const int32_t *tile_off, int32_t *depo_slot,
+                                                    int32_t *large)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t key = keys[i];
+    if (key < ntiles)
+        depo_slot[vals[i]] = (int32_t)(i - tile_off[key]);
+    else if (key == ntiles)
+        large[i - tile_off[ntiles]] = vals[i];
 }
 
 // Weights of one axis computed by one thread into a record, in FP64: the
@@ -970,7 +1127,10 @@ constexpr int kBatchItems = 64 * kFluctItems;
 // time makes every deposit a plain read-add-write LDS access (two patches of
 // a batch may cover the same cell).  No other wavefront touches the region.
 // The region's non-zero cells are then added to the grid with float atomics.
-template <int TP, int TT, bool B, bool FLUCT>
+// OWN: the caller clears the whole region before the tile's first item and
+// flushes it after the last (the owner flush); the item neither clears nor
+// flushes.
+template <int TP, int TT, bool B, bool FLUCT, bool OWN = false>
 __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const int4 item,
                                             const float *__restrict__ records,
                                             const EventCtx &e0, const BatchTables &bt)
@@ -979,7 +1139,7 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
     constexpr int RP = TP + kHaloP;
     const int tile = item.x, beg = item.y, end = item.z;
     const int K = end - beg;  // patches of the work item (<= kChunk)
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;  // the item's wavefront (one of OWN's workgroup)
     // lane k < K holds the header of patch k: window, depo index, charge
     int4 win = make_int4(INT_MAX, INT_MAX, 0, 0), hdr = make_int4(0, 0, 0, 0);
     if (lane < K) {
@@ -1010,7 +1170,7 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
     const int bq1 = min(4 * min(qhi, quad_of((int)P.Nt - 1) + 1) - c0, RT) >> 2;
     const int bnq = max(bq1 - bq0, 0), bcells = max(br1 - br0, 0) * bnq;
     const int bmagic = magic_small(max(bnq, 1));
-    for (int x = lane; x < bcells; x += 64) {
+    for (int x = lane; x < (OWN ? 0 : bcells); x += 64) {
         const int r = div_small(x, bmagic);
         acc4[r * (RT / 4) + bq0 + br0 * (RT / 4) + (x - r * bnq)] =
             make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -1158,6 +1318,8 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
         kb = ke + 1;
     }
     wave_lds_sync();  // every deposit lands before the flush reads the region
+    if constexpr (OWN)
+        return;
     // Flush: consecutive lanes take consecutive ticks of a row, so that one
     // atomic instruction covers 256 contiguous bytes (few L2 lines) rather
     // than 16-byte pieces of many lines.
@@ -1201,6 +1363,173 @@ __global__ __launch_bounds__(64) void k_raster_tiles(const float *__restrict__ r
     const int nitems_all = counters[2];
     for (int itm = blockIdx.x; itm < nitems_all; itm += gridDim.x)
         raster_item<TP, TT, B, FLUCT>(acc4, xsum, items[itm], records, e0, bt);
+}
+
+// Owner flush (reproducible sums).  Tiles are coloured by (tile row mod CP,
+// tile column mod CT), with CP TP >= RP and CT TT >= RT, so that the LDS
+// regions of two tiles of one colour never share a grid cell; one launch per
+// colour, in a fixed order.  In a launch each tile of the colour is owned by
+// one workgroup of kOwnerWaves wavefronts: wavefront w draws the tile's work
+// items w, w + kOwnerWaves, ... (in list order) into its own copy of the
+// region, and the workgroup adds the sum of the copies to the grid with plain
+// read-add-writes.  Every cell receives its sums in the same order on every
+// run.  The launch is persistent over the colour's list of tiles (the items
+// that open them), one workgroup per resident slot.
+constexpr int kOwnerWaves = 2;
+constexpr int kColourCount = 3, kColourNext = 9;  // counters: tiles per colour, places handed out
+
+template <int TP, int TT>
+constexpr int owner_colours_p()
+{
+    return (TP + kHaloP + TP - 1) / TP;
+}
+template <int TT>
+constexpr int owner_colours_t()
+{
+    return (region_cols<TT>() + TT - 1) / TT;
+}
+
+// Add a complete region to the grid (one workgroup of NT threads, exclusive
+// owner of the region's cells): quads wholly inside the grid as 16-byte
+// read-add-writes when rows are whole float4 words, the others cell by cell.
+// The region is the sum of the NW wavefronts' copies, taken in wavefront
+// order.  Each thread's grid values are all loaded before any is stored, so
+// that the loads are in flight together.
+template <int RP, int RT, int NW, int NT>
+__device__ __forceinline__ void owner_flush(const float4 *acc4, gptr<float> grid, int Np, int Nt,
+                                            int p0, int c0)
+{
+    constexpr int RQ = RT / 4, NQ = (RP * RQ + NT - 1) / NT;
+    const bool vec = (Nt & 3) == 0;
+    float4 a[NQ], g[NQ];
+    int64_t off[NQ];
+    bool whole[NQ], any[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int x = threadIdx.x + NT * u;
+        const int r = x / RQ, q = x - r * RQ;
+        const int I = p0 + r, J = c0 + 4 * q;
+        const bool in = x < RP * RQ && I < Np && J < Nt;
+        a[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (in) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const float4 v = acc4[w * RP * RQ + x];
+                a[u] = make_float4(a[u].x + v.x, a[u].y + v.y, a[u].z + v.z, a[u].w + v.w);
+            }
+        }
+        any[u] = in && (a[u].x != 0.0f || a[u].y != 0.0f || a[u].z != 0.0f || a[u].w != 0.0f);
+        whole[u] = vec && J + 3 < Nt;
+        off[u] = (int64_t)I * Nt + J;
+        g[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (any[u] && whole[u])
+            g[u] = *(const gptr<float4>)(grid + off[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        if (!any[u])
+            continue;
+        if (whole[u]) {
+            *(gptr<float4>)(grid + off[u]) =
+                make_float4(g[u].x + a[u].x, g[u].y + a[u].y, g[u].z + a[u].z, g[u].w + a[u].w);
+        } else {
+            const int J = (int)(off[u] % Nt);
+            const float v[4] = {a[u].x, a[u].y, a[u].z, a[u].w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (v[m] != 0.0f && J + m < Nt)
+                    grid[off[u] + m] = grid[off[u] + m] + v[m];
+        }
+    }
+}
+
+// Lists of the items that open a tile, by colour: counts (counters[kColourCount
+// + c]), then each item's place behind the counts of the smaller colours
+// (counters[kColourNext + c] hands out places; the order within a colour does
+// not matter: its tiles are independent).
+template <int TP, int TT, bool B, bool SCATTER>
+__global__ __launch_bounds__(256) void k_owner_lists(const int4 *__restrict__ items,
+                                                     int32_t *counters,
+                                                     const int32_t *__restrict__ tile_off,
+                                                     EventCtx e0, BatchTables bt,
+                                                     int32_t *colour_list)
+{
+    constexpr int CP = owner_colours_p<TP, TT>(), CT = owner_colours_t<TT>();
+    const int nitems_all = counters[2];
+    const int lane = threadIdx.x & 63;
+    const int stride = gridDim.x * blockDim.x;
+    // whole wavefronts iterate together: one atomic per colour per wavefront
+    for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < nitems_all; i0 += stride) {
+        const int itm = i0 + lane;
+        int c = -1;
+        if (itm < nitems_all) {
+            const int4 it = items[itm];
+            if (it.y == tile_off[it.x]) {  // the tile's first item
+                const EventCtx &E = B ? bt.ev[find_event(bt.tile_base, bt.nev, it.x)] : e0;
+                const int local = it.x - E.tile_base;
+                const int tp = local / E.ntt, tt = local - tp * E.ntt;
+                c = (tp % CP) * CT + tt % CT;
+            }
+        }
+        int base = 0;
+        if (SCATTER)
+            for (int u = 0; u < CP * CT; ++u)
+                base += (u < c) ? counters[kColourCount + u] : 0;
+        for (int u = 0; u < CP * CT; ++u) {
+            const uint64_t m = __ballot(c == u);
+            if (!m)
+                continue;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            int first = 0;
+            if (lane == leader)
+                first = atomicAdd(&counters[(SCATTER ? kColourNext : kColourCount) + u],
+                                  __popcll(m));
+            first = __shfl(first, leader);
+            if (SCATTER && c == u)
+                colour_list[base + first + __popcll(m & lanemask_lt(lane))] = itm;
+        }
+    }
+}
+
+template <int TP, int TT, bool B, bool FLUCT>
+__global__ __launch_bounds__(64 * kOwnerWaves) void k_raster_owner(
+    const float *__restrict__ records, const int4 *__restrict__ items,
+    const int32_t *__restrict__ counters, const int32_t *__restrict__ colour_list, EventCtx e0,
+    BatchTables bt, int colour_p, int colour_t)
+{
+    constexpr int RP = TP + kHaloP, RT = region_cols<TT>(), NW = kOwnerWaves;
+    constexpr int CP = owner_colours_p<TP, TT>(), CT = owner_colours_t<TT>();
+    static_assert(CP * TP >= RP && CT * TT >= RT, "regions of one colour must be disjoint");
+    constexpr int RQ4 = RP * RT / 4;
+    __shared__ float4 acc4[NW * RQ4];
+    __shared__ double xsum[NW * kBatchItems];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nitems_all = counters[2];
+    const int colour = colour_p * CT + colour_t;
+    int base = 0;
+    for (int c = 0; c < colour; ++c)
+        base += counters[kColourCount + c];
+    const int ntiles_c = counters[kColourCount + colour];
+    for (int k = blockIdx.x; k < ntiles_c; k += gridDim.x) {
+        const int itm = colour_list[base + k];
+        const int tile = items[itm].x;
+        const EventCtx &E = B ? bt.ev[find_event(bt.tile_base, bt.nev, tile)] : e0;
+        const int local = tile - E.tile_base;
+        const int tp = local / E.ntt, tt = local - tp * E.ntt;
+        float4 *mine = acc4 + w * RQ4;
+        for (int x = lane; x < RQ4; x += 64)
+            mine[x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        wave_lds_sync();
+        for (int j = itm + w; j < nitems_all; j += NW) {
+            const int4 it = items[j];
+            if (it.x != tile)
+                break;
+            raster_item<TP, TT, B, FLUCT, true>(mine, xsum + w * kBatchItems, it, records, e0, bt);
+        }
+        __syncthreads();  // every copy of the region is complete
+        owner_flush<RP, RT, NW, 64 * NW>(acc4, glb(E.grid), E.kp.Np, E.kp.Nt, tp * TP, tt * TT);
+        __syncthreads();  // the copies are read before the next tile clears them
+    }
 }
 
 // Descriptor of a single event (kernel argument; no table lookups).
@@ -1463,15 +1792,27 @@ static unsigned raster_grid(int64_t ntiles, int64_t n)
     return (unsigned)std::min<size_t>(items_cap(ntiles, n), (size_t)(n / 8) + 4096);
 }
 
+// Counters: [0..2] as RasterWork states, then the sort's digit totals.
+constexpr int kCounterWords = 64;
+constexpr size_t kCounterBytes = sizeof(int32_t) * (kCounterWords + 256);
+
+// The tile-list sort works in the record area before the records are written:
+// keys and depo indices twice (ping-pong) and the per-block digit counts.
+static size_t sort_blocks_of(size_t n) { return (n + kSortBlock - 1) / kSortBlock; }
+static size_t sort_bytes(size_t n)
+{
+    return 4 * align_up(sizeof(int32_t) * n) + align_up(sizeof(int32_t) * 256 * sort_blocks_of(n));
+}
+
 size_t raster_work_bytes_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles, int64_t nbands)
 {
     (void)pl;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
-    return align_up(256) + align_up(sizeof(int32_t) * (size_t)(ntiles + 1)) +
+    return align_up(kCounterBytes) + align_up(sizeof(int32_t) * (size_t)(ntiles + 1)) +
            align_up((size_t)kOccCols * (size_t)nbands) +
            align_up(sizeof(int2) * sched_blocks_of(ntiles)) +
            align_up(sizeof(int4) * items_cap(ntiles, n)) + 3 * align_up(sizeof(int32_t) * nn) +
-           align_up(sizeof(float) * kRecWords * nn);
+           align_up(std::max(sizeof(float) * kRecWords * nn, sort_bytes(nn)));
 }
 
 RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t ntiles,
@@ -1482,7 +1823,8 @@ RasterWork raster_work_carve_batch(const wcsim_plane *pl, int64_t n, int64_t nti
     char *p = (char *)base;
     RasterWork w;
     w.counters = (int32_t *)p;
-    p += align_up(256);
+    w.sort_tot = w.counters + kCounterWords;
+    p += align_up(kCounterBytes);
     w.tile_count = (int32_t *)p;
     p += align_up(sizeof(int32_t) * (size_t)(ntiles + 1));
     w.occ = (uint8_t *)p;  // adjacent to the counters: cleared together
@@ -1509,6 +1851,99 @@ size_t raster_work_bytes(const wcsim_plane *pl, int64_t n)
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base)
 {
     return raster_work_carve_batch(pl, n, pl->ntiles, occ_bands(pl->Np), base);
+}
+
+// Compute units of the current device (cached per device).
+static int device_cus()
+{
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    int v = cus[dev].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cus[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+// The colour lists (in depo_tile, free once the records are written: a tile
+// list has at most n items), then one launch per colour of the owner flush,
+// colours in row-major order, each with as many workgroups as the device
+// holds at once (LDS-bound).
+template <int TP, int TT, bool B, bool FLUCT>
+static void launch_owner_phases(unsigned items_grid, const RasterWork &w, const EventCtx &e0,
+                                const BatchTables &bt, hipStream_t s)
+{
+    const unsigned lg = std::max(1u, std::min(items_grid / 4, 2048u));
+    hipLaunchKernelGGL((k_owner_lists<TP, TT, B, false>), dim3(lg), dim3(256), 0, s, w.items,
+                       w.counters, w.tile_count, e0, bt, w.depo_tile);
+    hipLaunchKernelGGL((k_owner_lists<TP, TT, B, true>), dim3(lg), dim3(256), 0, s, w.items,
+                       w.counters, w.tile_count, e0, bt, w.depo_tile);
+    constexpr size_t lds = sizeof(float4) * kOwnerWaves * (TP + kHaloP) * region_cols<TT>() / 4 +
+                           sizeof(double) * kOwnerWaves * kBatchItems;
+    const unsigned per_cu = (unsigned)std::max<size_t>(1, (160 * 1024) / lds);
+    const unsigned grid = (unsigned)device_cus() * per_cu;
+    for (int cp = 0; cp < owner_colours_p<TP, TT>(); ++cp)
+        for (int ct = 0; ct < owner_colours_t<TT>(); ++ct)
+            hipLaunchKernelGGL((k_raster_owner<TP, TT, B, FLUCT>), dim3(grid),
+                               dim3(64 * kOwnerWaves), 0, s, w.records, w.items, w.counters,
+                               w.depo_tile, e0, bt, cp, ct);
+}
+
+template <bool B, bool FLUCT>
+static void launch_raster_owner(int tile, unsigned grid, const RasterWork &w, const EventCtx &e0,
+                                const BatchTables &bt, hipStream_t s)
+{
+    switch (tile) {
+    case 1:
+        launch_owner_phases<32, 32, B, FLUCT>(grid, w, e0, bt, s);
+        break;
+    case 2:
+        launch_owner_phases<64, 8, B, FLUCT>(grid, w, e0, bt, s);
+        break;
+    default:
+        launch_owner_phases<32, 8, B, FLUCT>(grid, w, e0, bt, s);
+        break;
+    }
+}
+
+// Tile lists in depo order: sort, then slots and the ordered large-patch list.
+static void launch_tile_list_sort(int64_t n, int64_t ntiles, const RasterWork &w, hipStream_t s)
+{
+    const size_t nn = (size_t)n;
+    char *p = (char *)w.records;
+    uint32_t *kA = (uint32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    uint32_t *kB = (uint32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    int32_t *vA = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    int32_t *vB = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * nn);
+    int32_t *counts = (int32_t *)p;
+    const unsigned nblk = (unsigned)sort_blocks_of(nn);
+    const uint32_t nt = (uint32_t)ntiles;
+    int bits = 1;
+    while (bits < 32 && ((uint64_t)nt + 1) >> bits)
+        ++bits;
+    hipLaunchKernelGGL(k_sort_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, w.depo_tile, n, nt,
+                       kA, vA);
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_sort_count, dim3(nblk), dim3(kSortThreads), 0, s, kA, n, shift,
+                           counts, w.sort_tot);
+        hipLaunchKernelGGL(k_sort_offsets, dim3(1), dim3(kSortThreads), 0, s, counts, (int)nblk,
+                           w.sort_tot);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortThreads), 0, s, kA, vA, n, shift,
+                           counts, kB, vB);
+        std::swap(kA, kB);
+        std::swap(vA, vB);
+    }
+    hipLaunchKernelGGL(k_sort_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, kA, vA, n, nt,
+                       w.tile_count, w.depo_slot, w.large);
 }
 
 template <bool B, bool FLUCT>
@@ -1568,6 +2003,8 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
                        (int)sched_blocks);
     hipLaunchKernelGGL(k_tile_schedule, dim3(sched_blocks), dim3(kSchedThreads), 0, s,
                        w.tile_count, (int)ntiles, w.block_tot, w.items, w.counters);
+    if (pl->det)
+        launch_tile_list_sort(n, ntiles, w, s);
     // clearing blocks: one per band of grid rows, at most kMaxClearBlocks
     const int nclr = (int)std::min<int64_t>(kMaxClearBlocks, nbands);
     hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64) + nclr), dim3(64), 0, s, e0, bt,
@@ -1575,7 +2012,11 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
     const unsigned grid_items = raster_grid(ntiles, n);
-    if (pl->kp.fluct)
+    if (pl->det && pl->kp.fluct)
+        launch_raster_owner<B, true>(pl->tile, grid_items, w, e0, bt, s);
+    else if (pl->det)
+        launch_raster_owner<B, false>(pl->tile, grid_items, w, e0, bt, s);
+    else if (pl->kp.fluct)
         launch_raster_tiles<B, true>(pl->tile, grid_items, w, e0, bt, s);
     else
         launch_raster_tiles<B, false>(pl->tile, grid_items, w, e0, bt, s);
@@ -1584,8 +2025,10 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
     // Depos whose patch does not fit a tile region: one workgroup each, direct
     // atomics.  The grid is persistent over the device-side count, one
     // workgroup per CU (most workloads have no such depo, and each workgroup
-    // holds 17 KB of LDS while it looks).
-    const unsigned lg = (unsigned)std::min<int64_t>(n, 256);
+    // holds 17 KB of LDS while it looks).  With reproducible sums one
+    // workgroup adds the patches one after another in depo order (a patch's
+    // bins are distinct; its atomics complete before the next patch's).
+    const unsigned lg = pl->det ? 1u : (unsigned)std::min<int64_t>(n, 256);
     hipLaunchKernelGGL((k_patch_generic<256, false, B>), dim3(lg), dim3(256), 0, s, e0, bt,
                        w.large, w.counters + 1, (int64_t)0, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess)

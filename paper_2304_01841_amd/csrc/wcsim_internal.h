@@ -179,6 +179,7 @@ struct wcsim_plane {
     // transform sizes share one
     std::shared_ptr<struct wcs_spectrum> spectrum;
     int tile;
+    bool det;  // reproducible sums: sorted tile lists, owner flush, ordered large patches
     wcs::TileShape ts;
     int ntp, ntt;
     int64_t ntiles;
@@ -237,6 +238,7 @@ struct RasterWork {
     int32_t *large;       // [n] depos of the large-patch path
     float *records;       // [n][64] depo records in tile-list order
     uint8_t *occ;         // occupancy maps of the grids (bands x kOccCols bytes)
+    int32_t *sort_tot;    // [256] digit totals of the tile-list sort (zero between passes)
 };
 size_t raster_work_bytes(const wcsim_plane *pl, int64_t n);
 RasterWork raster_work_carve(const wcsim_plane *pl, int64_t n, void *base);

@@ -63,7 +63,7 @@ class PlaneDesc(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("fft_ticks", ctypes.c_int32), ("fft_pitch", ctypes.c_int32),
                 ("freq_chunk", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("wire_mode", ctypes.c_int32)]
+                ("wire_mode", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class PlaneInfo(ctypes.Structure):
@@ -75,7 +75,8 @@ class PlaneInfo(ctypes.Structure):
                 ("tile_pitch", ctypes.c_int32), ("tile_ticks", ctypes.c_int32),
                 ("ntiles", ctypes.c_int64), ("spectrum_bytes", ctypes.c_int64),
                 ("pitch_cols", ctypes.c_int32), ("wire_fold", ctypes.c_int32),
-                ("wire_polyphase", ctypes.c_int32), ("wire_blocks", ctypes.c_int32)]
+                ("wire_polyphase", ctypes.c_int32), ("wire_blocks", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -186,7 +187,7 @@ def schedule_struct(schedule: dict | None) -> Schedule:
     schedule = schedule or {}
     return Schedule(int(schedule.get("fft_ticks", 0)), int(schedule.get("fft_pitch", 0)),
                     int(schedule.get("freq_chunk", 0)), int(schedule.get("tile", 0)),
-                    int(schedule.get("wire_mode", 0)))
+                    int(schedule.get("wire_mode", 0)), int(schedule.get("deterministic", 0)))
 
 
 class Plane:

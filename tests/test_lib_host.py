@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(ws):
 
 
 def test_version_and_error_string(ws):
-    assert ws.version() == 10300
+    assert ws.version() == 10400
     assert isinstance(ws._lib.wcsim_last_error(), bytes)
 
 
