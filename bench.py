@@ -210,7 +210,7 @@ def measure_batched(wcsim, pl, deps, ids, outs, steps, warmup):
     wall = time.perf_counter() - t0
     # stage durations summed over chunks, averaged over steps
     names = {"bin_depos": (0, 1), "raster_tiles": (1, 2), "raster_large": (2, 3),
-             "fft_ticks": (4, 5), "conv_pitch": (5, 6), "ifft_ticks": (6, 7)}
+             "fft_ticks": (4, 5), "conv_pitch": (5, 6), "ifft_ticks": (8, 7)}
     stage = {k: 0.0 for k in names}
     step_ms = []
     for s in range(steps):

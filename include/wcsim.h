@@ -365,13 +365,15 @@ int32_t wcsim_batch_chunk_count(const wcsim_plane *const *planes, const int64_t 
 /* wcsim_simulate_batch with stage timing (the paper's per-kernel timers,
  * Sec. 5.2): `events` holds WCSIM_BATCH_STAGE_EVENTS hipEvent_t handles per
  * chunk (nevents_events = chunks * WCSIM_BATCH_STAGE_EVENTS), recorded for
- * chunk c at [8c + 0] start of its rasterization, [8c + 1] depos binned and
- * records built, [8c + 2] LDS-tiled raster done, [8c + 3] large-patch raster
- * done (all on `stream`), [8c + 4] start of its passes, [8c + 5] tick-axis
- * FFT done, [8c + 6] pitch-axis convolution done, [8c + 7] inverse tick-axis
- * FFT done (on the library's second stream).  WCSIM_E_INVALID when the count
- * does not match or an entry is NULL. */
-#define WCSIM_BATCH_STAGE_EVENTS 8
+ * chunk c (base b = 9c) at [b + 0] start of its rasterization, [b + 1] depos
+ * binned and records built, [b + 2] LDS-tiled raster done, [b + 3]
+ * large-patch raster done (on `stream`), [b + 4] start of its tick-axis and
+ * pitch-axis passes, [b + 5] tick-axis FFT done, [b + 6] pitch-axis
+ * convolution done (on the library's second stream), [b + 8] start and
+ * [b + 7] end of its inverse tick-axis FFT (on `stream`, after the next
+ * chunk's rasterization).  WCSIM_E_INVALID when the count does not match or
+ * an entry is NULL. */
+#define WCSIM_BATCH_STAGE_EVENTS 9
 wcsim_status wcsim_simulate_batch_profiled(const wcsim_plane *const *planes,
                                            const wcsim_depo *const *depos, const int64_t *n,
                                            const uint64_t *event_ids, int32_t nevents,

@@ -1164,24 +1164,48 @@ BatchTables tables_of(const BatchPlan &bp, int c, char *ws)
     return bt;
 }
 
-// Launches of a whole batch whose tables are already in the workspace:
-// rasters on sR, convolutions on sF, ordered by the four events (two per
-// slot); sR finally waits for the last convolution, so the batch is complete
-// in sR's order.  `marks` (nullable): WCSIM_BATCH_STAGE_EVENTS timing events
-// per chunk (see wcsim_simulate_batch_profiled).
+// Launches of a whole batch whose tables are already in the workspace.  The
+// stream sR runs each chunk's rasterization and then the inverse tick-axis
+// pass (pass C) of the chunk before it; sF runs each chunk's passes A and B.
+// The raster side has the shorter work, so it takes pass C.  Per workspace
+// slot, `ev` holds kPipeEvents / 2 events: raster done (pass A may read the
+// grid), pass A done (the next raster of the slot may overwrite grid and
+// records), pass B done (pass C may read Y) and pass C done (the next pass B
+// of the slot may overwrite Y).  The batch is complete in sR's order (its
+// last pass C waits for the last pass B).  `marks` (nullable):
+// WCSIM_BATCH_STAGE_EVENTS timing events per chunk (see
+// wcsim_simulate_batch_profiled).
+constexpr int kPipeEvents = 8;
+
 hipError_t launch_pipeline(const BatchPlan &bp, const wcsim_plane *const *planes, char *ws,
-                           hipStream_t sR, hipStream_t sF, const hipEvent_t *evR,
-                           const hipEvent_t *evF, const hipEvent_t *marks = nullptr)
+                           hipStream_t sR, hipStream_t sF, const hipEvent_t *ev,
+                           const hipEvent_t *marks = nullptr)
 {
     hipError_t e;
+    const hipEvent_t *evR = ev, *evA = ev + 2, *evB = ev + 4, *evC = ev + 6;
     const int nch = (int)bp.chunks.size();
+    auto pass_c = [&](int c) -> hipError_t {
+        const ChunkLayout &L = bp.layouts[(size_t)c];
+        const wcsim_plane *pl0 = planes[bp.chunks[(size_t)c][0]];
+        const int slot = c % bp.nslots;
+        const hipEvent_t *mk = marks ? marks + (size_t)c * WCSIM_BATCH_STAGE_EVENTS : nullptr;
+        hipError_t r;
+        if ((r = hipStreamWaitEvent(sR, evB[slot], 0)) != hipSuccess ||
+            (mk && (r = hipEventRecord(mk[8], sR)) != hipSuccess) ||
+            (r = launch_convolve_batch_c(pl0, tables_of(bp, c, ws), L.nblk_c, sR)) !=
+                hipSuccess ||
+            (mk && (r = hipEventRecord(mk[7], sR)) != hipSuccess))
+            return r;
+        return hipEventRecord(evC[slot], sR);
+    };
     for (int c = 0; c < nch; ++c) {
         const ChunkLayout &L = bp.layouts[(size_t)c];
         const wcsim_plane *pl0 = planes[bp.chunks[(size_t)c][0]];
         const BatchTables bt = tables_of(bp, c, ws);
         const int slot = c % bp.nslots;
         char *data = ws + bp.slot_base(c);
-        if (c >= bp.nslots && (e = hipStreamWaitEvent(sR, evF[slot], 0)) != hipSuccess)
+        const bool reuse = c >= bp.nslots;  // the slot held chunk c - nslots
+        if (reuse && (e = hipStreamWaitEvent(sR, evA[slot], 0)) != hipSuccess)
             return e;
         const hipEvent_t *mk = marks ? marks + (size_t)c * WCSIM_BATCH_STAGE_EVENTS : nullptr;
         const RasterWork rw =
@@ -1189,16 +1213,20 @@ hipError_t launch_pipeline(const BatchPlan &bp, const wcsim_plane *const *planes
         if ((mk && (e = hipEventRecord(mk[0], sR)) != hipSuccess) ||
             (e = launch_raster_batch(pl0, bt, L.n_total, L.ntiles_total, L.nbands_total, rw, sR,
                                      mk ? mk + 1 : nullptr)) != hipSuccess ||
-            (e = hipEventRecord(evR[slot], sR)) != hipSuccess ||
-            (e = hipStreamWaitEvent(sF, evR[slot], 0)) != hipSuccess ||
+            (e = hipEventRecord(evR[slot], sR)) != hipSuccess)
+            return e;
+        if (c > 0 && (e = pass_c(c - 1)) != hipSuccess)
+            return e;
+        if ((e = hipStreamWaitEvent(sF, evR[slot], 0)) != hipSuccess ||
             (mk && (e = hipEventRecord(mk[4], sF)) != hipSuccess) ||
-            (e = launch_convolve_batch(pl0, bt, L.nblk_r, L.nblk_p, L.nblk_c, L.poly, sF,
-                                       mk ? mk + 5 : nullptr)) != hipSuccess ||
-            (e = hipEventRecord(evF[slot], sF)) != hipSuccess)
+            (e = launch_convolve_batch_ab(pl0, bt, L.nblk_r, L.nblk_p, L.poly, sF,
+                                          mk ? mk + 5 : nullptr, evA[slot],
+                                          reuse ? evC[slot] : nullptr)) != hipSuccess ||
+            (e = hipEventRecord(evB[slot], sF)) != hipSuccess)
             return e;
     }
     if (nch > 0)
-        return hipStreamWaitEvent(sR, evF[(nch - 1) % bp.nslots], 0);
+        return pass_c(nch - 1);
     return hipSuccess;
 }
 
@@ -1263,12 +1291,12 @@ wcsim_status stage_upload(const void *src, size_t bytes, void *dst, hipStream_t 
     return WCSIM_OK;
 }
 
-// The second stream and the four ordering events of this thread's direct
-// batch calls, one set per device (default priority, non-blocking).
+// The second stream and the ordering events of this thread's direct batch
+// calls, one set per device (default priority, non-blocking).
 struct PipeStreams {
     int device = -1;
     hipStream_t sF = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[kPipeEvents] = {};
     ~PipeStreams()
     {
         if (sF) {
@@ -1381,7 +1409,7 @@ static wcsim_status simulate_batch(const wcsim_plane *const *planes,
     pack_tables(bp, host.data());
     if ((st = stage_upload(host.data(), host.size(), ws, s)) != WCSIM_OK)
         return st;
-    WCS_HIP(launch_pipeline(bp, planes, ws, s, ps->sF, ps->ev, ps->ev + 2, marks));
+    WCS_HIP(launch_pipeline(bp, planes, ws, s, ps->sF, ps->ev, marks));
     return WCSIM_OK;
 }
 
@@ -1454,7 +1482,7 @@ wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t 
         return bail(check_hip(e, "hipEventCreate"));
     // capture on two private streams (default priority), joined at the end
     hipStream_t cs = nullptr, fs = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[kPipeEvents] = {};
     auto release = [&]() {
         for (hipEvent_t x : ev)
             if (x)
@@ -1467,7 +1495,7 @@ wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t 
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&fs, hipStreamNonBlocking);
-    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+    for (int k = 0; k < kPipeEvents && e == hipSuccess; ++k)
         e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
     if (e != hipSuccess) {
         release();
@@ -1478,7 +1506,7 @@ wcsim_status wcsim_batch_create(const wcsim_plane *const *planes, const int64_t 
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->ws, b->pinned, b->plan.tables_total, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess)
-        e = launch_pipeline(b->plan, planes, b->ws, cs, fs, ev, ev + 2);
+        e = launch_pipeline(b->plan, planes, b->ws, cs, fs, ev);
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess)
         e = e2;

@@ -1303,22 +1303,27 @@ hipError_t poly_any(const wcsim_plane *pl, const PolyIo &io, const BatchTables &
     return hipGetLastError();
 }
 
-hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
-                                 int nblk_p, int nblk_c, bool poly, hipStream_t s,
-                                 const hipEvent_t *ev)
+hipError_t launch_convolve_batch_ab(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
+                                    int nblk_p, bool poly, hipStream_t s, const hipEvent_t *ev,
+                                    hipEvent_t after_a, hipEvent_t before_b)
 {
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
     hipError_t e;
     if ((e = rows_r2c_any<true>(pl, R2CIo{}, bt, (unsigned)nblk_r, s)) != hipSuccess ||
-        (e = mark(0)) != hipSuccess)
+        (e = mark(0)) != hipSuccess ||
+        (after_a && (e = hipEventRecord(after_a, s)) != hipSuccess) ||
+        (before_b && (e = hipStreamWaitEvent(s, before_b, 0)) != hipSuccess))
         return e;
     if ((e = poly ? poly_any<true>(pl, PolyIo{}, bt, (unsigned)nblk_p, s)
-                  : pitch_any<true>(pl, PitchIo{}, bt, (unsigned)nblk_p, 1.0f, s)) != hipSuccess ||
-        (e = mark(1)) != hipSuccess)
+                  : pitch_any<true>(pl, PitchIo{}, bt, (unsigned)nblk_p, 1.0f, s)) != hipSuccess)
         return e;
-    if ((e = rows_c2r_any<true>(pl, C2RIo{}, bt, (unsigned)nblk_c, s)) != hipSuccess)
-        return e;
-    return mark(2);
+    return mark(1);
+}
+
+hipError_t launch_convolve_batch_c(const wcsim_plane *pl, const BatchTables &bt, int nblk_c,
+                                   hipStream_t s)
+{
+    return rows_c2r_any<true>(pl, C2RIo{}, bt, (unsigned)nblk_c, s);
 }
 
 size_t conv_work_bytes(const wcsim_plane *pl, wcsim_out out_kind)

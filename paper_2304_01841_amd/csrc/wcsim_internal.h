@@ -276,14 +276,18 @@ hipError_t launch_convolve(const wcsim_plane *pl, const float *grid, float *out,
 hipError_t build_response_spectrum(wcsim_plane *pl, const float *resp_dev, void *work,
                                    hipStream_t s);
 size_t response_work_bytes(const wcsim_plane *pl);
-// Batched convolution: the three passes over every event of the tables;
-// nblk_* = total workgroups of each pass (the last entries of the bases).
-// `ev` (nullable): 3 events recorded after passes A, B and C.
+// Batched convolution over every event of the tables, in two parts that may
+// run on different streams: passes A and B, then pass C.  nblk_* = total
+// workgroups of each pass (the last entries of the bases).  `ev` (nullable):
+// 2 events recorded after passes A and B; `after_a` (nullable) is recorded
+// after pass A as well, and pass B waits for `before_b` (nullable).
 // `poly`: wire output through the polyphase pitch pass (pl->poly), whose
 // workgroup counts are in the tables' pblk_base.
-hipError_t launch_convolve_batch(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
-                                 int nblk_p, int nblk_c, bool poly, hipStream_t s,
-                                 const hipEvent_t *ev = nullptr);
+hipError_t launch_convolve_batch_ab(const wcsim_plane *pl, const BatchTables &bt, int nblk_r,
+                                    int nblk_p, bool poly, hipStream_t s, const hipEvent_t *ev,
+                                    hipEvent_t after_a, hipEvent_t before_b);
+hipError_t launch_convolve_batch_c(const wcsim_plane *pl, const BatchTables &bt, int nblk_c,
+                                   hipStream_t s);
 int rows_blocks(int nrows);                       // workgroups of a tick-axis pass
 int pitch_blocks_total(const wcsim_plane *pl);    // workgroups of the pitch pass
 int poly_blocks_total(const wcsim_plane *pl);     // workgroups of the polyphase pitch pass

@@ -478,7 +478,7 @@ def simulate_batch(planes, depos_list, event_ids, outs, kind: int = OUT_WIRE,
     return outs
 
 
-BATCH_STAGE_EVENTS = 8
+BATCH_STAGE_EVENTS = 9
 BATCH_STAGE_NAMES = ("bin_depos", "raster_tiles", "raster_large", None, "fft_ticks", "conv_pitch",
                      "ifft_ticks")
 
