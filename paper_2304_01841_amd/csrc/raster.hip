@@ -1031,23 +1031,25 @@ __device__ __forceinline__ void clear_blocks(gptr<float> grid, int Np, int Nt, i
     }
 }
 
-// One wavefront per block: each lane computes one record into LDS, then the
-// wavefront writes the records out one 256-byte row at a time.  The first
-// `nclr` blocks instead clear the occupied blocks of the grids, one band of
-// kOccRows rows at a time (nbands bands over all events): the clear is bound
-// by HBM writes and the records by FP64 arithmetic, so one launch runs both
-// side by side.
+// Two wavefronts per block of 64 depos: lane l of the first computes depo
+// l's header and pitch weights into LDS, lane l of the second its tick
+// weights (two FP64 chains per depo in flight instead of one, for the same
+// LDS), then the block writes the records out one 256-byte row at a time.
+// The first `nclr` blocks instead clear the occupied blocks of the grids, one
+// band of kOccRows rows per wavefront at a time (nbands bands over all
+// events): the clear is bound by HBM writes and the records by FP64
+// arithmetic, so one launch runs both side by side.
 template <bool B>
-__global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt, int64_t ntotal,
+__global__ __launch_bounds__(128) void k_fill_records(EventCtx e0, BatchTables bt, int64_t ntotal,
                                                      const int32_t *depo_tile,
                                                      const int32_t *depo_slot,
                                                      const int32_t *tile_off, float *records,
                                                      int nbands, int nclr)
 {
     __shared__ float stage[64 * kStageStride];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if ((int)blockIdx.x < nclr) {
-        for (int gb = blockIdx.x; gb < nbands; gb += nclr) {
+        for (int gb = 2 * blockIdx.x + wv; gb < nbands; gb += 2 * nclr) {
             const int e = B ? find_event(bt.band_base, bt.nev, gb) : 0;
             const EventCtx &E = B ? bt.ev[e] : e0;
             const int band = B ? gb - bt.band_base[e] : gb;
@@ -1068,25 +1070,28 @@ __global__ __launch_bounds__(64) void k_fill_records(EventCtx e0, BatchTables bt
         int *h = (int *)rec;
         const int off = w.lo_t & 3;
         const int nq = quad_of(w.lo_t + w.n_t - 1) - quad_of(w.lo_t) + 1;
-        h[kHLoP] = w.lo_p;
-        h[kHLoT] = w.lo_t;
-        h[kHNp] = w.n_p;
-        h[kHNt] = w.n_t;
-        h[kHDepo] = (int)d;
-        const double qs = surviving_charge(w, E.kp, (int)d, E.event);
-        h[kHQlo] = (int)(uint32_t)__double_as_longlong(qs);
-        h[kHQhi] = (int)(uint32_t)((uint64_t)__double_as_longlong(qs) >> 32);
-        h[kHMq] = magic_small(nq);
-        float *Wt = rec + kRecWt;
-        for (int k = 0; k < off; ++k)
-            Wt[k] = 0.0f;
-        for (int k = off + w.n_t; k < 4 * nq; ++k)
-            Wt[k] = 0.0f;
-        thread_axis_weights(w.lo_p, w.n_p, w.mu_p, w.s_p, rec + kRecWp);
-        thread_axis_weights(w.lo_t, w.n_t, w.mu_t, w.s_t, Wt + off);
+        if (wv == 0) {  // header and pitch weights
+            h[kHLoP] = w.lo_p;
+            h[kHLoT] = w.lo_t;
+            h[kHNp] = w.n_p;
+            h[kHNt] = w.n_t;
+            h[kHDepo] = (int)d;
+            const double qs = surviving_charge(w, E.kp, (int)d, E.event);
+            h[kHQlo] = (int)(uint32_t)__double_as_longlong(qs);
+            h[kHQhi] = (int)(uint32_t)((uint64_t)__double_as_longlong(qs) >> 32);
+            h[kHMq] = magic_small(nq);
+            thread_axis_weights(w.lo_p, w.n_p, w.mu_p, w.s_p, rec + kRecWp);
+        } else {  // tick weights
+            float *Wt = rec + kRecWt;
+            for (int k = 0; k < off; ++k)
+                Wt[k] = 0.0f;
+            for (int k = off + w.n_t; k < 4 * nq; ++k)
+                Wt[k] = 0.0f;
+            thread_axis_weights(w.lo_t, w.n_t, w.mu_t, w.s_t, Wt + off);
+        }
     }
-    wave_lds_sync();
-    for (int r = 0; r < 64; ++r) {
+    __syncthreads();
+    for (int r = wv; r < 64; r += 2) {
         const int pr = __builtin_amdgcn_readlane(pos, r);
         if (pr >= 0)
             records[(int64_t)pr * kRecWords + lane] = stage[r * kStageStride + lane];
@@ -2007,7 +2012,7 @@ static hipError_t raster_sequence(const wcsim_plane *pl, const EventCtx &e0,
         launch_tile_list_sort(n, ntiles, w, s);
     // clearing blocks: one per band of grid rows, at most kMaxClearBlocks
     const int nclr = (int)std::min<int64_t>(kMaxClearBlocks, nbands);
-    hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64) + nclr), dim3(64), 0, s, e0, bt,
+    hipLaunchKernelGGL(k_fill_records<B>, dim3(blocks_for(n, 64) + nclr), dim3(128), 0, s, e0, bt,
                        n, w.depo_tile, w.depo_slot, w.tile_count, w.records, (int)nbands, nclr);
     if ((e = hipGetLastError()) != hipSuccess || (e = mark(0)) != hipSuccess)
         return e;
