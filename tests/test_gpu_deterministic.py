@@ -116,8 +116,9 @@ def test_deterministic_against_atomic_and_oracle(ws, fluct):
 
 def test_deterministic_batch_equals_single_bit_for_bit(ws):
     """Events of different planes and sizes (one empty, one ragged) in one
-    batched call: each output equals the event's own single run bit for bit,
-    and the oracle's to the output tolerance."""
+    batched call and in two replays of its captured graph: each output equals
+    the event's own single run bit for bit, and the oracle's to the output
+    tolerance."""
     log("case: deterministic batch vs single")
     pl, phys, dep = _mix(seed=7)
     R = W.response("bipolar")
@@ -134,6 +135,15 @@ def test_deterministic_batch_equals_single_bit_for_bit(ws):
     wsp.fill_(0xFF)
     ws.simulate_batch(planes, deps, [e for _, _, e in evs], outs, workspace=wsp)
     torch.cuda.synchronize()
+    # the captured graph of the same batch, replayed twice
+    gouts = [torch.full_like(o, -2.0) for o in outs]
+    b = ws.Batch(planes, [d.shape[0] for d in deps])
+    for _ in range(2):
+        b.run(deps, [e for _, _, e in evs], gouts)
+        torch.cuda.synchronize()
+        for o, g in zip(outs, gouts):
+            assert torch.equal(o, g)
+    b.destroy()
     for P, (p, d, e), dd, o in zip(planes, evs, deps, outs):
         single = ws.simulate_event(P, dd, e, kind=ws.OUT_WIRE).cpu().numpy()
         got = o.cpu().numpy()
