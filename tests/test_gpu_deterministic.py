@@ -114,6 +114,23 @@ def test_deterministic_against_atomic_and_oracle(ws, fluct):
     assert normwise(od, oa) <= CONV_TOL
 
 
+def test_deterministic_with_lifetime_and_drift_accel(ws):
+    """The extensions that change a record's charge and window (electron
+    lifetime with fluctuation, an accelerating drift): repeats bit for bit and
+    agrees with the oracle."""
+    log("case: deterministic with lifetime and drift acceleration")
+    pl, phys, dep = _mix(seed=9)
+    phys = dict(phys, lifetime=1800.0, drift_accel=2e-4)
+    R = W.response("bipolar")
+    P = ws.Plane(pl, phys, R, schedule={"deterministic": 1})
+    g0, o0 = _run(ws, P, dep, 13, 0xFF)
+    g1, o1 = _run(ws, P, dep, 13, 0x00)
+    assert np.array_equal(g0, g1) and np.array_equal(o0, o1)
+    G = O.grid(dep, phys, pl, 13)
+    assert normwise(g0, G) <= GRID_TOL
+    assert normwise(o0, O.convolve(G, R.astype(np.float64), R.shape[0] // 2)) <= CONV_TOL
+
+
 def test_deterministic_batch_equals_single_bit_for_bit(ws):
     """Events of different planes and sizes (one empty, one ragged) in one
     batched call and in two replays of its captured graph: each output equals
