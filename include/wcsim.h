@@ -353,7 +353,7 @@ wcsim_status wcsim_simulate_batch(const wcsim_plane *const *planes,
 
 /* Number of chunks wcsim_simulate_batch cuts these events into: the events
  * are grouped by schedule class (planes whose kernels can share a launch) and
- * each class is cut into chunks of at most 8 events, in the callers' order.
+ * each class is cut into chunks of at most 16 events, in the callers' order.
  * A chunk's rasterization (binning, records, LDS-tiled raster) runs as one
  * launch sequence on `stream`, its three FFT passes as another on a second
  * stream of the library's, so that one chunk's rasterization overlaps the

@@ -980,7 +980,7 @@ namespace {
 // with the slot.  The descriptor tables of all chunks sit in front of the
 // slots and are uploaded once per call.
 // ---------------------------------------------------------------------------
-constexpr int kChunkEvents = 8;  // events per chunk at most
+constexpr int kChunkEvents = 16;  // events per chunk at most
 
 // Layout of one chunk: its tables (relative to the chunk's table offset) and
 // its data (relative to the base of the slot it runs in).
