@@ -168,8 +168,8 @@ def tuned_plane(wcsim, tuner, plane, phys, resp, dep):
 
 
 def batch_setup(wcsim, W, dev, nevents, phys, tuner):
-    """The batch workload's events and one tuned plane per wire count (tuned
-    on that wire count's median event)."""
+    """The batch workload's events and one tuned plane per wire count, tuned on
+    all of that wire count's events run together through the batched form."""
     import torch
 
     evs = W.batch_events(nevents=nevents)
@@ -178,8 +178,12 @@ def batch_setup(wcsim, W, dev, nevents, phys, tuner):
         mine = sorted((e for e in evs if e["plane"]["nwires"] == nw),
                       key=lambda e: e["depos"].shape[0])
         e = mine[len(mine) // 2]
-        planes[nw], schedules[nw] = tuned_plane(wcsim, tuner, e["plane"], phys, e["response"],
-                                                torch.from_numpy(e["depos"]).to(dev))
+        sched = None
+        if tuner is not None:
+            sched = tuner.tune_batch(e["plane"], phys, e["response"],
+                                     [torch.from_numpy(x["depos"]).to(dev) for x in mine])
+        planes[nw] = wcsim.Plane(e["plane"], phys, e["response"], schedule=sched)
+        schedules[nw] = sched or {}
     pl = [planes[e["plane"]["nwires"]] for e in evs]
     deps = [torch.from_numpy(e["depos"]).to(dev) for e in evs]
     ids = [e["event_id"] for e in evs]

@@ -93,6 +93,53 @@ class Tuner:
         cands = candidates()
         ms = wcsim.tune_schedules(plane, phys, response, depos, cands, r0=r0, kind=kind,
                                   reps=self.reps, stream=stream)
+        return self._keep(key, cands, ms)
+
+    def tune_batch(self, plane: dict, phys: dict, response: np.ndarray, depos_list: list,
+                   r0: int | None = None, kind: int = wcsim.OUT_WIRE) -> dict:
+        """Best schedule for a class of events of one plane shape that run together
+        through the batched form (cached).  A single event can pick a schedule that
+        fills the GPU alone but wastes it beside other events (a small plane's
+        pitch pass, say); here every candidate's plane runs the whole class as one
+        wcsim_simulate_batch and the median of `reps` runs, timed with HIP events
+        on the current stream, decides."""
+        if r0 is None:
+            r0 = np.shape(response)[0] // 2
+        ns = [int(d.shape[0]) for d in depos_list]
+        key = "batch%d|" % len(ns) + cache_key(plane, response, r0, phys["fluctuate"], sum(ns), kind)
+        with self._lock:
+            if key in self.table:
+                return dict(self.table[key]["schedule"])
+        cands = candidates()
+        ids = list(range(len(ns)))
+        dev = depos_list[0].device
+        ms = []
+        for c in cands:
+            try:
+                P = wcsim.Plane(plane, phys, response, r0=r0, schedule=c)
+            except wcsim.WcsimError:
+                ms.append(-1.0)
+                continue
+            planes = [P] * len(ns)
+            outs = [torch.empty((P.out_rows(kind), P.nticks), dtype=torch.float32, device=dev)
+                    for _ in ns]
+            ws = wcsim.batch_workspace(planes, ns, kind)
+            wcsim.simulate_batch(planes, depos_list, ids, outs, kind=kind, workspace=ws)
+            times = []
+            for _ in range(self.reps):
+                t0 = torch.cuda.Event(enable_timing=True)
+                t1 = torch.cuda.Event(enable_timing=True)
+                t0.record()
+                wcsim.simulate_batch(planes, depos_list, ids, outs, kind=kind, workspace=ws)
+                t1.record()
+                t1.synchronize()
+                times.append(t0.elapsed_time(t1))
+            ms.append(float(np.median(times)))
+            del outs, ws
+            P.destroy()
+        return self._keep(key, cands, ms)
+
+    def _keep(self, key: str, cands: list, ms: list) -> dict:
         # the first candidate (in list order) within TIE of the fastest, so that
         # timing noise does not flip between near-equal schedules
         timed = [(t, i) for i, t in enumerate(ms) if t >= 0.0]

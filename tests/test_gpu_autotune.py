@@ -59,3 +59,30 @@ def test_tuned_schedule_matches_oracle_and_is_cached(ws, tmp_path):
     t2 = autotune.Tuner(path)
     assert t2.lookup(pl, R, P.r0, True, dep.shape[0]) == sched
     P.destroy()
+
+
+def test_batch_tuned_schedule_matches_oracle_and_is_cached(ws, tmp_path):
+    """tune_batch times every candidate on a class of events run as one batch:
+    the schedule it picks is a candidate, gives every event the oracle's
+    output through the batched form, and is cached under the class's key."""
+    from paper_2304_01841_amd import autotune
+    print("case: batch tuner, small planes", flush=True)
+    w = W.small()
+    pl, R = w["planes"][0], w["responses"][0]
+    phys = W.physics(True)
+    rng = np.random.default_rng(12)
+    deps_np = [w["depos"], W.uniform_depos(rng, 300, (0.0, 400.0), (0.0, 450.0))]
+    deps = [torch.from_numpy(np.ascontiguousarray(d)).cuda() for d in deps_np]
+    path = str(tmp_path / "tune.json")
+    t = autotune.Tuner(path, reps=2)
+    sched = t.tune_batch(pl, phys, R, deps)
+    assert sched in autotune.candidates()
+    key = next(k for k in t.table if k.startswith("batch2|"))
+    assert sum(c["ms"] > 0 for c in t.entry(key)["candidates"]) >= 2
+    P = ws.Plane(pl, phys, R, schedule=sched)
+    outs = [torch.empty((P.nwires, P.nticks), device="cuda") for _ in deps]
+    ws.simulate_batch([P, P], deps, [5, 6], outs)
+    for d, e, o in zip(deps_np, (5, 6), outs):
+        ref = O.simulate_event(d, phys, pl, R.astype(np.float64), P.r0, e, wire_output=True)
+        assert normwise(o.cpu().numpy(), ref) <= CONV_TOL
+    assert autotune.Tuner(path).tune_batch(pl, phys, R, deps) == sched  # from the file
