@@ -109,3 +109,37 @@ def test_random_configurations_in_one_batch(ws):
                           pl["nimpact"])
         if np.abs(ref).max() > 0:
             assert normwise(got, ref) <= CONV_TOL, e
+
+
+@pytest.mark.parametrize("seed", list(range(4200, 4212)))
+def test_random_patch_sets_scatter_and_convolve(ws, seed):
+    """The other entry points on the same random configurations: patch sets
+    (windows and offsets bit-exact, values per patch within 1e-5), their
+    scatter-add (1e-5) and the convolution of a random grid (1e-4), against the
+    oracle."""
+    pl, R, r0, dep, phys, sched = _config(seed)
+    print("case: seed %d patch sets / scatter / convolve" % seed, flush=True)
+    P = ws.Plane(pl, phys, R, r0=r0, schedule=sched)
+    pt = ws.rasterize(P, torch.from_numpy(dep).cuda(), seed)
+    meta, offs, vals = pt.to_host()
+    ometa, ovals, _ = O.rasterize(dep, phys, pl, seed)
+    for c in range(4):
+        assert np.array_equal(meta[:, c], ometa[:, c]), c
+    assert np.array_equal(offs[:-1], ometa[:, 4]) and offs[-1] == ovals.size
+    for d in range(dep.shape[0]):
+        o, n = ometa[d, 4], ometa[d, 2] * ometa[d, 3]
+        if n and np.abs(ovals[o:o + n]).max() > 0:
+            assert normwise(vals[o:o + n], ovals[o:o + n]) <= GRID_TOL, d
+    grid = torch.full((P.npitch, P.nticks), 5.0, device="cuda")
+    ws.scatter_add(P, pt, grid, zero_first=True)
+    G = O.grid(dep, phys, pl, seed)
+    if np.abs(G).max() > 0:
+        assert normwise(grid.cpu().numpy(), G) <= GRID_TOL
+    pt.destroy()
+    rng = np.random.default_rng(seed)
+    g = rng.normal(0.0, 1.0, (P.npitch, P.nticks)).astype(np.float32)
+    full = O.convolve(g.astype(np.float64), R.astype(np.float64), r0)
+    out = ws.convolve(P, torch.from_numpy(g).cuda(), kind=ws.OUT_PITCH).cpu().numpy()
+    assert normwise(out, full) <= CONV_TOL
+    outw = ws.convolve(P, torch.from_numpy(g).cuda(), kind=ws.OUT_WIRE).cpu().numpy()
+    assert normwise(outw, O.wire_rows(full, pl["nimpact"])) <= CONV_TOL
