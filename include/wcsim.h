@@ -118,7 +118,10 @@ typedef struct {
 /* Execution schedule of a plane; 0 in a field means "choose".  The result of
  * the simulation does not depend on it (up to float32 rounding). */
 typedef struct {
-    int32_t fft_ticks;  /* even padded tick-axis transform length N' >= nticks + resp_nticks - 1 */
+    int32_t fft_ticks;  /* even padded tick-axis transform length N' >= nticks + resp_nticks - 1,
+                         * N'/2 a product of 2, 3 and 5; one row of N'/2 + 1 complex
+                         * values and its twiddle tables must fit a workgroup's LDS,
+                         * so N' <= 20000 (else WCSIM_E_INVALID) */
     int32_t fft_pitch;  /* pitch-axis overlap-save block transform length L > resp_npitch - 1 */
     int32_t freq_chunk; /* spectrum columns per chunk (8 or 16) */
     int32_t tile;       /* raster tile shape id, pitch bins x ticks of a tile: 0 = 32 x 8

@@ -1,0 +1,176 @@
+"""The largest sizes the library takes, and the first it refuses.
+
+Tick axis: a tick-pass workgroup holds one row of N'/2 + 1 complex values and
+its two twiddle tables in LDS (160 KB), which caps the padded tick transform
+at N' = 20000 (N'/2 = 10000 = 2^4 5^4).  The default schedule takes the
+smallest admissible N' >= nticks + resp_nticks - 1, so with 200 response ticks
+the longest plane has 19801 ticks; one tick more needs N' = 20250 and the
+plane is refused with E_INVALID.
+
+Patch windows: at most 1024 bins per axis (Sec. 2 step 1 puts no bound on
+them; the bound sizes the large-patch path's LDS).  A device depo with a
+longer window is counted invalid and adds nothing; host depos whose drift
+could give one are refused.  The oracle has no such bound, so the reference
+is the oracle's grid of the other depos, each keyed by its index in the
+event."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2304_01841_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GRID_TOL = 1e-5
+CONV_TOL = 1e-4
+LONGEST_NTICKS = 19801  # with a 200-tick response
+
+
+@pytest.fixture(scope="module")
+def ws():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_01841_amd import wcsim
+    return wcsim
+
+
+def normwise(got, ref):
+    ref = np.asarray(ref, np.float64)
+    return np.abs(np.asarray(got, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def _long_plane_event():
+    pl = W.plane(8, LONGEST_NTICKS)
+    R = W.response("bipolar", Rp=21, Rt=200, r0=10)
+    rng = np.random.default_rng(41)
+    dep = W.uniform_depos(rng, 3000, (-2.0, 42.0), (-20.0, LONGEST_NTICKS * W.TICK + 20.0),
+                          max_drift_time=2000.0)
+    return pl, R, dep
+
+
+def test_longest_tick_axis_against_oracle(ws):
+    log("case: longest tick axis, 8 wires x 10 impact x %d ticks" % LONGEST_NTICKS)
+    pl, R, dep = _long_plane_event()
+    phys = W.physics(True)
+    P = ws.Plane(pl, phys, R, r0=10)
+    assert P.info["fft_ticks"] == 20000
+    d = torch.from_numpy(dep).cuda()
+    G = O.grid(dep, phys, pl, 17)
+    full = O.convolve(G, R.astype(np.float64), 10)
+    wsp = ws.simulate_workspace(P, dep.shape[0], ws.OUT_PITCH)
+    out = ws.simulate_event(P, d, 17, kind=ws.OUT_PITCH, workspace=wsp).cpu().numpy()
+    grid = ws.workspace_grid(P, wsp, dep.shape[0]).cpu().numpy()
+    assert ws.workspace_invalid_count(wsp) == 0
+    assert normwise(grid, G) <= GRID_TOL
+    assert normwise(out, full) <= CONV_TOL
+    # both ends of the tick axis carry signal
+    assert np.abs(full[:, :200]).max() > 0 and np.abs(full[:, -200:]).max() > 0
+    wire = O.wire_rows(full, pl["nimpact"])
+    single = ws.simulate_event(P, d, 17, kind=ws.OUT_WIRE).cpu().numpy()
+    assert normwise(single, wire) <= CONV_TOL
+    # the same plane in a batch, beside a short one
+    log("  in a batch")
+    small = W.plane(5, 300)
+    Q = ws.Plane(small, phys, R, r0=10)
+    dq = torch.from_numpy(W.uniform_depos(np.random.default_rng(42), 200, (0.0, 25.0),
+                                          (0.0, 150.0))).cuda()
+    outs = [torch.full((8, LONGEST_NTICKS), 3.0, device="cuda"),
+            torch.full((5, 300), 3.0, device="cuda")]
+    ws.simulate_batch([P, Q], [d, dq], [17, 18], outs)
+    assert normwise(outs[0].cpu().numpy(), single) <= 1e-5
+    assert normwise(outs[1].cpu().numpy(),
+                    ws.simulate_event(Q, dq, 18).cpu().numpy()) <= 1e-5
+
+
+def test_one_tick_past_the_longest_is_refused(ws):
+    log("case: tick axis one past the longest")
+    R = W.response("bipolar", Rp=21, Rt=200, r0=10)
+    with pytest.raises(ws.WcsimError) as ei:
+        ws.Plane(W.plane(8, LONGEST_NTICKS + 1), W.physics(False), R, r0=10)
+    assert ei.value.status == ws.E_INVALID
+    # an explicit transform length past the bound is refused the same way
+    with pytest.raises(ws.WcsimError) as ei:
+        ws.Plane(W.plane(8, 1000), W.physics(False), R, r0=10,
+                 schedule={"fft_ticks": 20250})
+    assert ei.value.status == ws.E_INVALID
+
+
+T0 = 1000.0  # us: drift time at which the wide axis spans 980 bins
+
+
+def _wide_physics(axis):
+    """Diffusion constants giving, at drift time T0, a 980-bin window on the
+    wide axis and a 300-bin window on the other (window ~ 2 nsigma sigma)."""
+    phys = W.physics(True)
+    ns, v = phys["nsigma"], phys["drift_speed"]
+    dp = W.PITCH / W.NIMPACT
+    wide, narrow = 980.0 / (2 * ns), 300.0 / (2 * ns)
+    s_p, s_t = (narrow, wide) if axis == "ticks" else (wide, narrow)
+    phys["DT"] = (s_p * dp) ** 2 / (2.0 * T0)
+    phys["DL"] = (s_t * v * W.TICK) ** 2 / (2.0 * T0)
+    return phys
+
+
+def _wide_event(phys):
+    """Small depos (drift up to 2 us: windows up to 44 bins), then depos of
+    drift T0 (980 bins), 1.0833 T0 (1020 bins) and, last, 1.12 T0 (1037 bins,
+    past the bound)."""
+    v = phys["drift_speed"]
+    rng = np.random.default_rng(43)
+    small = W.uniform_depos(rng, 200, (0.0, 300.0), (0.0, 800.0), max_drift_time=2.0)
+    big = []
+    for T, z, arrival in ((T0, 150.0, 400.0), (1.0833 * T0, 100.0, 350.0),
+                          (1.12 * T0, 200.0, 450.0)):
+        big.append([v * T, 0.0, z, arrival - T, 2.0e5])
+    return np.ascontiguousarray(np.concatenate([small, np.array(big)]))
+
+
+@pytest.mark.parametrize("axis,det", [("ticks", 0), ("pitch", 0), ("ticks", 1), ("pitch", 1)])
+def test_window_bound(ws, axis, det):
+    log("case: window bound on the %s axis, reproducible sums %d" % (axis, det))
+    pl = W.plane(60, 1600)  # 600 pitch bins x 1600 ticks
+    phys = _wide_physics(axis)
+    dep = _wide_event(phys)
+    n = dep.shape[0]
+    lens = []
+    for d in dep[-3:]:
+        st, _, (_, _, n_p, n_t) = O.depo_window(d, phys, pl)
+        assert st == 0
+        lens.append(n_t if axis == "ticks" else n_p)
+    assert 975 <= lens[0] <= 985 and 1018 <= lens[1] <= 1024 and lens[2] > 1024, lens
+    R = W.response("bipolar")
+    P = ws.Plane(pl, phys, R, schedule={"deterministic": det})
+    keep = np.arange(n - 1)
+    G = O.grid(dep[keep], phys, pl, 19, ids=keep)
+    full = O.convolve(G, R.astype(np.float64), R.shape[0] // 2)
+    # device depos: the last one is counted invalid and adds nothing
+    wsp = ws.simulate_workspace(P, n, ws.OUT_PITCH)
+    wsp.fill_(0xFF)
+    out = ws.simulate_event(P, torch.from_numpy(dep).cuda(), 19, kind=ws.OUT_PITCH,
+                            workspace=wsp).cpu().numpy()
+    grid = ws.workspace_grid(P, wsp, n).cpu().numpy()
+    assert ws.workspace_invalid_count(wsp) == 1
+    assert normwise(grid, G) <= GRID_TOL
+    assert normwise(out, full) <= CONV_TOL
+    # host depos: refused with the long one, taken without it
+    with pytest.raises(ws.WcsimError) as ei:
+        ws.simulate_event(P, dep, 19, kind=ws.OUT_PITCH)
+    assert ei.value.status == ws.E_INVALID
+    host = ws.simulate_event(P, np.ascontiguousarray(dep[:-1]), 19, kind=ws.OUT_PITCH)
+    assert normwise(host.cpu().numpy(), full) <= CONV_TOL
+    # the patch set of the device depos: the long one gets an empty patch
+    pt = ws.rasterize(P, torch.from_numpy(dep).cuda(), 19)
+    meta, offs, vals = pt.to_host()
+    pt.destroy()
+    assert meta[-1, 2] * meta[-1, 3] == 0
+    ometa, ovals, _ = O.rasterize(dep[:-1], phys, pl, 19)
+    for c in range(4):
+        assert np.array_equal(meta[:-1, c], ometa[:, c]), c
+    for i in (n - 3, n - 2):
+        o, m = ometa[i, 4], ometa[i, 2] * ometa[i, 3]
+        assert normwise(vals[offs[i]:offs[i] + m], ovals[o:o + m]) <= GRID_TOL, i
