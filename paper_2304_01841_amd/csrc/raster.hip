@@ -259,6 +259,17 @@ __device__ __forceinline__ float fluct_value(float q, float p, float z)
     return fmaxf(0.0f, fmaf(z, __builtin_amdgcn_sqrtf(var), qp));
 }
 
+// The same value from the squared Box-Muller radius r2 = -2 ln u and the
+// branch's cosine or sine c: z sqrt(var) = c sqrt(r2 var), as rho and the
+// standard deviation are both non-negative (one square root instead of two
+// per value pair).
+__device__ __forceinline__ float fluct_value_r2(float q, float p, float r2, float c)
+{
+    const float qp = q * p;
+    const float var = fmaf(-qp, p, qp);  // q p (1 - p)
+    return fmaxf(0.0f, fmaf(c, __builtin_amdgcn_sqrtf(r2 * var), qp));
+}
+
 __device__ __forceinline__ int quad_of(int J) { return J >> 2; }  // floor(J / 4)
 
 // ---------------------------------------------------------------------------
@@ -1242,12 +1253,16 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
                     const uint4 rr = philox4x32_10(
                         make_uint4((uint32_t)qd, (uint32_t)(lo_p + i), (uint32_t)d, E.event),
                         P.key0, P.key1);
-                    float z[4];
-                    box_muller(rr.x, rr.y, z[0], z[1]);
-                    box_muller(rr.z, rr.w, z[2], z[3]);
+                    constexpr float kMinus2Ln2 = -1.38629436111989061883f;
+                    const float r2a = kMinus2Ln2 * __builtin_amdgcn_logf(word_to_uniform(rr.x));
+                    const float r2b = kMinus2Ln2 * __builtin_amdgcn_logf(word_to_uniform(rr.z));
+                    const float ua = word_to_uniform(rr.y), ub = word_to_uniform(rr.w);
+                    const float r2[4] = {r2a, r2a, r2b, r2b};
+                    const float c[4] = {__builtin_amdgcn_cosf(ua), __builtin_amdgcn_sinf(ua),
+                                        __builtin_amdgcn_cosf(ub), __builtin_amdgcn_sinf(ub)};
 #pragma unroll
                     for (int mm = 0; mm < 4; ++mm)
-                        F[b][mm] = fluct_value(q, wp * w4[mm], z[mm]);
+                        F[b][mm] = fluct_value_r2(q, wp * w4[mm], r2[mm], c[mm]);
                     // the item's total in FP64, and its prefix over the batch
                     const double t = valid ? ((double)F[b][0] + (double)F[b][1]) +
                                                  ((double)F[b][2] + (double)F[b][3])
