@@ -932,33 +932,41 @@ __global__ __launch_bounds__(256) void k_sort_slots(const uint32_t *keys, const 
 // holding the centre is 2 - c_a - c_b.  The window total is the same
 // difference taken between the window's outer edges.
 // erfc(x) for x >= 0 in FP64 without branches: exp(-x^2) erfcx(x), with
-// erfcx(x) = exp(x^2) erfc(x) from its Chebyshev expansion of degree 18 in
-// u = 9 / (3 + x) - 2 (the interval [0, 6] of x mapped onto [-1, 1]), fitted by
-// weighted least squares at 300 Chebyshev nodes in 40-digit arithmetic: at
-// most 1.6e-15 relative to the library erfc on [0, 6].  Beyond x = 6 erfcx is
-// held at its value at 6 (erfc(6) = 2.2e-17: the absolute error stays below
-// 1e-17).  The library erfc branches over three ranges of x here, and the
-// lanes of a wavefront take all three.
-__constant__ const double kErfcxCheb[19] = {
-    0.43106340548200280783,     0.4317768845374619746,      0.11240012030838863907,
-    0.021602701119412269399,    0.0029235483262740457863,   0.00023395398679905218146,
-    1.3120228285000756815e-06,  -1.8388769572666935182e-06, -1.036155682341427026e-07,
-    1.5512144298939361581e-08,  1.3916389949762914822e-09,  -1.8185219119865354685e-10,
-    -1.5415890937672703625e-11, 2.7673211570784812338e-12,  1.1975973105657121435e-13,
-    -4.5294816534347390793e-14, 6.1173784776326125931e-16,  6.7176043883895186765e-16,
-    -4.7338253409245980876e-17};
+// erfcx(x) = exp(x^2) erfc(x) a polynomial of degree 18 in
+// u = 9 / (3 + x) - 2 (the interval [0, 6] of x mapped onto [-1, 1]).  The
+// polynomial is a Chebyshev expansion fitted by weighted least squares at 300
+// Chebyshev nodes in 40-digit arithmetic, turned into powers of u in 50-digit
+// arithmetic; the magnitudes of its coefficients sum to 1.0003, so Horner's
+// rule loses nothing to cancellation: at most 2e-15 relative to the library
+// erfc on [0, 6].  Beyond x = 6 erfcx is held at its value at 6 (erfc(6) =
+// 2.2e-17: the absolute error stays below 1e-17).  The library erfc branches
+// over three ranges of x here, and the lanes of a wavefront take all three.
+__constant__ const double kErfcxPoly[19] = {
+    0.32158541645431749, 0.36815156489826012, 0.2014388568192258,
+    0.081626845134045015, 0.023308261232626117, 0.003956151636291854,
+    7.0125313652629907e-05, -0.00012716419781459492, -1.5153801949992285e-05,
+    4.532602482660329e-06, 8.1181436388616683e-07, -2.2753363747095745e-07,
+    -3.482226636786867e-08, 1.44452931474044e-08, 8.4853769242305189e-10,
+    -9.2921436560768322e-10, 4.7966663774361644e-11, 4.402449211974955e-11,
+    -6.2047195508566893e-12};
+
+// 1 / d for d in [3, 9] (no scaling or special cases needed): the hardware
+// reciprocal refined by two Newton steps, each squaring the relative error.
+__device__ __forceinline__ double recip_3_9(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
+}
 
 __device__ __forceinline__ double erfc_tail(double x)
 {
-    const double u = 9.0 / (3.0 + fmin(x, 6.0)) - 2.0;
-    double b1 = 0.0, b2 = 0.0;  // Clenshaw recurrence
+    const double u = fma(9.0, recip_3_9(3.0 + fmin(x, 6.0)), -2.0);
+    double p = kErfcxPoly[18];
 #pragma unroll
-    for (int k = 18; k >= 1; --k) {
-        const double t = fma(2.0 * u, b1, kErfcxCheb[k] - b2);
-        b2 = b1;
-        b1 = t;
-    }
-    return exp(-x * x) * fma(u, b1, kErfcxCheb[0] - b2);
+    for (int k = 17; k >= 0; --k)
+        p = fma(p, u, kErfcxPoly[k]);
+    return exp(-x * x) * p;
 }
 
 __device__ __forceinline__ double edge_tail(int lo, int k, double mu, double inv, bool &neg)

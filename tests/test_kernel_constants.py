@@ -19,26 +19,45 @@ def _array(path, name):
 
 
 def test_record_erfc_tail_matches_erfc():
-    """The record kernel's erfc(x) = exp(-x^2) * sum_k a_k T_k(u),
-    u = 9 / (3 + min(x, 6)) - 2, evaluated by the same Clenshaw recurrence in
-    float64, is within 4e-15 of erfc on [0, 6] (relative) and within 1e-17 of
-    it beyond (absolute)."""
-    a = _array(RASTER, "kErfcxCheb")
-    assert a.size == 19
+    """The record kernel's erfc(x) = exp(-x^2) * sum_j m_j u^j,
+    u = 9 / (3 + min(x, 6)) - 2, evaluated by the same Horner rule in float64
+    (the reciprocal rounded once, as the kernel's Newton-refined reciprocal
+    gives it to within an ulp), is within 4e-15 of erfc on [0, 6] (relative)
+    and within 1e-17 of it beyond (absolute); and the coefficients are
+    well conditioned for Horner's rule (their magnitudes sum to about 1)."""
+    m = _array(RASTER, "kErfcxPoly")
+    assert m.size == 19
+    assert np.abs(m).sum() < 1.001
 
     def tail(x):
-        u = 9.0 / (3.0 + np.minimum(x, 6.0)) - 2.0
-        b1 = np.zeros_like(x)
-        b2 = np.zeros_like(x)
-        for k in range(18, 0, -1):
-            b1, b2 = 2.0 * u * b1 + (a[k] - b2), b1
-        return np.exp(-x * x) * (u * b1 + (a[0] - b2))
+        u = 9.0 * (1.0 / (3.0 + np.minimum(x, 6.0))) - 2.0
+        p = np.full_like(x, m[18])
+        for k in range(17, -1, -1):
+            p = p * u + m[k]
+        return np.exp(-x * x) * p
 
     x = np.linspace(0.0, 6.0, 60001)
     ref = special.erfc(x)
     assert np.max(np.abs(tail(x) / ref - 1.0)) < 4e-15
     xb = np.linspace(6.0, 40.0, 3401)
     assert np.max(np.abs(tail(xb) - special.erfc(xb))) < 1e-17
+
+
+def test_record_reciprocal_refinement_reaches_double_precision():
+    """Two Newton steps r <- r + r (1 - d r) from a reciprocal good to 2^-22
+    (worse than the hardware's) give 1 / d to within 2 ulp for d in [3, 9]:
+    each step squares the relative error.  Checked in float64 with the FMA
+    residual formed exactly in 40-digit arithmetic."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    rng = np.random.default_rng(3)
+    for d in np.concatenate([[3.0, 9.0, 4.5], rng.uniform(3.0, 9.0, 400)]):
+        r = (1.0 / d) * (1.0 + float(rng.choice([-1, 1])) * 2.0 ** -22)
+        for _ in range(2):
+            e = float(1 - mp.mpf(d) * mp.mpf(r))  # fma(-d, r, 1)
+            r = float(mp.mpf(r) * mp.mpf(e) + mp.mpf(r))  # fma(r, e, r)
+        exact = mp.mpf(1) / mp.mpf(d)
+        assert abs(mp.mpf(r) - exact) <= 2 * np.spacing(1.0 / d), d
 
 
 def test_butterfly_constants_match_their_trig_values():
