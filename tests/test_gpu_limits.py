@@ -1,4 +1,5 @@
-"""The largest sizes the library takes, and the first it refuses.
+"""The largest sizes the library takes, the first it refuses, and the
+method's degenerate depos.
 
 Tick axis: a tick-pass workgroup holds one row of N'/2 + 1 complex values and
 its two twiddle tables in LDS (160 KB), which caps the padded tick transform
@@ -12,7 +13,10 @@ them; the bound sizes the large-patch path's LDS).  A device depo with a
 longer window is counted invalid and adds nothing; host depos whose drift
 could give one are refused.  The oracle has no such bound, so the reference
 is the oracle's grid of the other depos, each keyed by its index in the
-event."""
+event.
+
+Degenerate depos (zero charge, a few electrons, zero drift, means on bin and
+tick edges) against the oracle through the tile path and the patch sets."""
 import numpy as np
 import pytest
 import torch
@@ -174,3 +178,62 @@ def test_window_bound(ws, axis, det):
     for i in (n - 3, n - 2):
         o, m = ometa[i, 4], ometa[i, 2] * ometa[i, 3]
         assert normwise(vals[offs[i]:offs[i] + m], ovals[o:o + m]) <= GRID_TOL, i
+
+
+def _degenerate_sets():
+    """Three depo sets of the method's degenerate cases, each alone so that the
+    normwise comparison is about them: zero charge; a few electrons each (the
+    fluctuation clamps many bins at zero, and all of some short-drift
+    patches, which then keep their mean); zero
+    drift (a zero-width Gaussian: one bin per axis) with means on bin and tick
+    edges, and means on pitch-bin edges after a drift."""
+    rng = np.random.default_rng(44)
+    zero_q = W.uniform_depos(rng, 300, (0.0, 100.0), (0.0, 200.0), max_drift_time=300.0)
+    zero_q[:, 4] = 0.0
+    few = np.concatenate([
+        W.uniform_depos(rng, 150, (0.0, 100.0), (0.0, 200.0), max_drift_time=300.0),
+        W.uniform_depos(rng, 150, (0.0, 100.0), (0.0, 200.0), max_drift_time=2.0)])
+    few[:, 4] = rng.uniform(0.2, 4.0, 300)
+    edges = W.uniform_depos(rng, 300, (0.0, 100.0), (0.0, 200.0), max_drift_time=300.0)
+    dp = W.PITCH / W.NIMPACT
+    edges[:, 2] = np.round(edges[:, 2] / dp) * dp          # pitch means on bin edges
+    arrival = edges[:150, 3] + edges[:150, 0] / W.DRIFT_SPEED
+    edges[:150, 3] = np.round(arrival / W.TICK) * W.TICK     # zero drift, arriving on a tick edge
+    edges[:150, 0] = 0.0
+    return {"zero charge": zero_q, "few electrons": few, "zero drift and edges": edges}
+
+
+@pytest.mark.parametrize("det", [0, 1])
+def test_degenerate_depos_against_oracle(ws, det):
+    pl = W.plane(20, 400)
+    R = W.response("bipolar", Rp=21, Rt=40, r0=10)
+    for name, dep in _degenerate_sets().items():
+        for fl in (False, True):
+            log("case: degenerate depos (%s), fluctuation %s, reproducible sums %d" % (name, fl, det))
+            phys = W.physics(fl)
+            P = ws.Plane(pl, phys, R, r0=10, schedule={"deterministic": det})
+            n = dep.shape[0]
+            wsp = ws.simulate_workspace(P, n, ws.OUT_PITCH)
+            wsp.fill_(0xFF)
+            out = ws.simulate_event(P, torch.from_numpy(dep).cuda(), 23, kind=ws.OUT_PITCH,
+                                    workspace=wsp).cpu().numpy()
+            grid = ws.workspace_grid(P, wsp, n).cpu().numpy()
+            assert ws.workspace_invalid_count(wsp) == 0
+            G = O.grid(dep, phys, pl, 23)
+            if name == "zero charge":
+                assert np.abs(G).max() == 0.0
+                assert np.abs(grid).max() == 0.0 and np.abs(out).max() == 0.0
+                continue
+            assert normwise(grid, G) <= GRID_TOL, (name, fl)
+            assert normwise(out, O.convolve(G, R.astype(np.float64), 10)) <= CONV_TOL, (name, fl)
+            # the patch set: windows bit-exact, each patch within the grid tolerance
+            pt = ws.rasterize(P, torch.from_numpy(dep).cuda(), 23)
+            meta, offs, vals = pt.to_host()
+            pt.destroy()
+            ometa, ovals, _ = O.rasterize(dep, phys, pl, 23)
+            for c in range(4):
+                assert np.array_equal(meta[:, c], ometa[:, c]), (name, c)
+            for d in range(n):
+                o, m = ometa[d, 4], ometa[d, 2] * ometa[d, 3]
+                if m and np.abs(ovals[o:o + m]).max() > 0:
+                    assert normwise(vals[offs[d]:offs[d] + m], ovals[o:o + m]) <= GRID_TOL, (name, d)
