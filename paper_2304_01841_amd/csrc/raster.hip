@@ -1227,18 +1227,24 @@ __device__ __forceinline__ void raster_item(float4 *acc4, double *xsum, const in
         float F[kFluctItems][4];
         int cell[kFluctItems], kk[kFluctItems];
         double carry = 0.0;  // total of the batch's earlier passes (uniform)
+        // each item's patch: kb plus the patch ends at or below its flat index
+        // (one pass over the batch's patch ends serves the lane's items)
+#pragma unroll
+        for (int b = 0; b < kFluctItems; ++b)
+            kk[b] = kb;
+        for (int j = kb; j < ke; ++j) {
+            const int e = __builtin_amdgcn_readlane(incl, j) - base;
+#pragma unroll
+            for (int b = 0; b < kFluctItems; ++b)
+                kk[b] += (64 * b + lane >= e) ? 1 : 0;
+        }
 #pragma unroll
         for (int b = 0; b < kFluctItems; ++b) {
             cell[b] = -1;
-            kk[b] = 0;
             if (b < npass) {
                 const int g = 64 * b + lane;  // flat item index within the batch
                 const bool valid = g < nitems;
-                // the item's patch: kb plus the patch ends at or below g
-                int k = kb;
-                for (int j = kb; j < ke; ++j)
-                    k += (g >= __builtin_amdgcn_readlane(incl, j) - base) ? 1 : 0;
-                kk[b] = k;
+                const int k = kk[b];
                 // the patch's header, from the lane holding it
                 const int lo_p = __shfl(win.x, k, 64), lo_t = __shfl(win.y, k, 64);
                 const int d = __shfl(hdr.x, k, 64), m = __shfl(hdr.w, k, 64);
